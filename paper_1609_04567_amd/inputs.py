@@ -1,0 +1,239 @@
+"""Seeded synthetic inputs for the loop-of-stencil-reduce workloads.
+
+This module is shared by the tests, the benchmark and the CPU oracle's callers.
+It holds no arithmetic of the method itself (no sweep, no reduce, no stopping
+test): it only draws random numbers and lays out grids. Both the HIP path and the
+oracle read the exact bytes produced here.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based generator:
+draw i of the stream with seed s is ``mix(s + (i + 1) * GAMMA)``, so any slice of
+a stream can be produced independently. A 64-bit draw becomes a double in [0, 1)
+as ``(x >> 11) * 2**-53``.
+
+The paper's own inputs (the Helmholtz matrices of Sect. 4.1, the images and
+videos of Sect. 4.2 and 4.3) are not available; these recipes are stand-ins of
+the same shape and structure:
+
+* ``laplace_input``: square FP64 grid, fixed boundary ring drawn U[0,1), interior 0.
+* ``helmholtz_input``: manufactured solution u* = sin(pi x) sin(pi y) on the unit
+  square, right-hand side f = (2 pi^2 + alpha) u*, boundary u* = 0, interior 0;
+  the env passed to the sweep is g = h^2 f.
+* ``life_input``: random soup, a cell is alive iff its draw is below the density.
+* ``restore_input``: smooth 8-bit image (sum of Gaussian blobs) plus salt-and-pepper
+  impulses at a given rate.
+* ``job_stream``: a mixed stream of Laplace / Helmholtz / Life jobs with
+  log-uniform sides, for the served form.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_CHUNK = 1 << 22
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Draws start .. start+count-1 of the SplitMix64 stream with this seed (uint64)."""
+    out = np.empty(count, dtype=np.uint64)
+    s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        for lo in range(0, count, _CHUNK):
+            hi = min(count, lo + _CHUNK)
+            idx = np.arange(start + lo + 1, start + hi + 1, dtype=np.uint64)
+            out[lo:hi] = _mix(s + idx * GAMMA)
+    return out
+
+
+def uniform01(seed: int, start: int, count: int) -> np.ndarray:
+    """Doubles in [0, 1): (draw >> 11) * 2**-53."""
+    out = np.empty(count, dtype=np.float64)
+    for lo in range(0, count, _CHUNK):
+        hi = min(count, lo + _CHUNK)
+        x = splitmix64(seed, start + lo, hi - lo)
+        out[lo:hi] = (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Jacobi / Laplace: fixed boundary ring U[0,1), interior 0.
+# ---------------------------------------------------------------------------
+def laplace_input(rows: int, cols: int | None = None, seed: int = 1) -> np.ndarray:
+    """FP64 grid; ring cells take draw (i*cols + j) of the stream, interior cells are 0.
+
+    The side includes the ring, so only (rows-2) x (cols-2) cells are updated.
+    """
+    cols = rows if cols is None else cols
+    u = uniform01(seed, 0, rows * cols).reshape(rows, cols)
+    u[1:-1, 1:-1] = 0.0
+    return np.ascontiguousarray(u)
+
+
+def harmonic_input(rows: int, cols: int, kind: str) -> np.ndarray:
+    """Integer-valued discrete harmonic polynomials on the index lattice (FP64)."""
+    i = np.arange(rows, dtype=np.float64)[:, None]
+    j = np.arange(cols, dtype=np.float64)[None, :]
+    if kind == "x2-y2":
+        return np.ascontiguousarray(i * i - j * j)
+    if kind == "xy":
+        return np.ascontiguousarray(i * j + 0.0 * j)
+    if kind == "x3-3xy2":
+        return np.ascontiguousarray(i * i * i - 3.0 * i * j * j)
+    raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz: manufactured solution on the unit square.
+# ---------------------------------------------------------------------------
+@dataclass
+class HelmholtzInput:
+    u0: np.ndarray      # initial iterate: ring = u* (= 0), interior 0
+    g: np.ndarray       # env: h^2 * f
+    ustar: np.ndarray   # sin(pi x) sin(pi y) on the lattice (ring exactly 0)
+    s: np.ndarray       # the 1-D factor sin(pi x_i)
+    alpha: float
+    h: float
+
+
+def helmholtz_input(n: int, alpha: float = 1.0) -> HelmholtzInput:
+    """N x N lattice including the ring, x_i = i/(N-1), h = 1/(N-1)."""
+    h = 1.0 / (n - 1)
+    x = np.arange(n, dtype=np.float64) * h
+    s = np.sin(np.pi * x)
+    s[0] = 0.0
+    s[-1] = 0.0
+    ustar = np.ascontiguousarray(np.outer(s, s))
+    f = (2.0 * np.pi * np.pi + alpha) * ustar
+    g = np.ascontiguousarray((h * h) * f)
+    u0 = np.zeros((n, n), dtype=np.float64)
+    return HelmholtzInput(u0=u0, g=g, ustar=ustar, s=s, alpha=float(alpha), h=float(h))
+
+
+# ---------------------------------------------------------------------------
+# Game of Life soup.
+# ---------------------------------------------------------------------------
+def life_input(rows: int, cols: int | None = None, seed: int = 3, density: float = 0.3) -> np.ndarray:
+    """uint8 grid, cell (i, j) alive (1) iff draw i*cols + j is below the density."""
+    cols = rows if cols is None else cols
+    out = np.empty(rows * cols, dtype=np.uint8)
+    for lo in range(0, rows * cols, _CHUNK):
+        hi = min(rows * cols, lo + _CHUNK)
+        out[lo:hi] = (uniform01(seed, lo, hi - lo) < density).astype(np.uint8)
+    return out.reshape(rows, cols)
+
+
+def life_pattern(rows: int, cols: int, cells) -> np.ndarray:
+    g = np.zeros((rows, cols), dtype=np.uint8)
+    for (i, j) in cells:
+        g[i % rows, j % cols] = 1
+    return g
+
+
+# ---------------------------------------------------------------------------
+# Impulse-noise restoration input.
+# ---------------------------------------------------------------------------
+@dataclass
+class RestoreInput:
+    y: np.ndarray        # noisy uint8 image
+    clean: np.ndarray    # uint8 image before noise, values in [16, 239]
+    impulse: np.ndarray  # bool, where noise was injected
+
+
+def restore_input(rows: int, cols: int | None = None, seed: int = 4, noise: float = 0.4,
+                  blobs: int = 8) -> RestoreInput:
+    """Sum of Gaussian blobs mapped to [16, 239], then salt (255) / pepper (0) impulses.
+
+    Draw layout: blob b uses draws 4b..4b+3 (amplitude in [-1,1), centre row,
+    centre column, width in [W/16, W/4) with W = max(rows, cols)); pixel p (raster
+    order) uses draws 4*blobs + 2p (impulse iff < noise) and 4*blobs + 2p + 1
+    (salt iff < 0.5, else pepper).
+    """
+    cols = rows if cols is None else cols
+    w = float(max(rows, cols))
+    d = uniform01(seed, 0, 4 * blobs)
+    r = np.arange(rows, dtype=np.float64)[:, None]
+    c = np.arange(cols, dtype=np.float64)[None, :]
+    field = np.zeros((rows, cols), dtype=np.float64)
+    for b in range(blobs):
+        amp = 2.0 * d[4 * b] - 1.0
+        cr = d[4 * b + 1] * rows
+        cc = d[4 * b + 2] * cols
+        sig = w / 16.0 + d[4 * b + 3] * (w / 4.0 - w / 16.0)
+        field += amp * np.exp(-((r - cr) ** 2 + (c - cc) ** 2) / (2.0 * sig * sig))
+    lo, hi = field.min(), field.max()
+    scale = 223.0 / (hi - lo) if hi > lo else 0.0
+    clean = np.rint(16.0 + (field - lo) * scale).astype(np.uint8)
+    npx = rows * cols
+    y = clean.reshape(-1).copy()
+    imp = np.zeros(npx, dtype=bool)
+    base = 4 * blobs
+    for lo_p in range(0, npx, _CHUNK):
+        hi_p = min(npx, lo_p + _CHUNK)
+        u = uniform01(seed, base + 2 * lo_p, 2 * (hi_p - lo_p)).reshape(-1, 2)
+        hit = u[:, 0] < noise
+        salt = u[:, 1] < 0.5
+        seg = y[lo_p:hi_p]
+        seg[hit & salt] = 255
+        seg[hit & ~salt] = 0
+        imp[lo_p:hi_p] = hit
+    return RestoreInput(y=y.reshape(rows, cols), clean=clean, impulse=imp.reshape(rows, cols))
+
+
+# ---------------------------------------------------------------------------
+# Mixed job stream for the served form.
+# ---------------------------------------------------------------------------
+KIND_LAPLACE, KIND_HELMHOLTZ, KIND_LIFE = "laplace", "helmholtz", "life"
+
+
+@dataclass
+class JobSpec:
+    index: int
+    kind: str
+    side: int
+    seed: int          # seed of the job's own grid-content stream
+    arrival_u: float   # U[0,1) draw turned into an inter-arrival gap by the caller
+
+
+def job_stream(count: int, base_seed: int = 5, side_lo: int = 128, side_hi: int = 4096,
+               p_laplace: float = 0.6, p_helm: float = 0.25) -> list[JobSpec]:
+    """Job j draws from its own stream seeded with draw j of the base stream.
+
+    Draw 0 picks the kind (Laplace if < p_laplace, Helmholtz if < p_laplace+p_helm,
+    else Life), draw 1 the side round(exp(U(ln lo, ln hi))), draw 2 (raw) the
+    grid-content seed, draw 3 the arrival-gap uniform.
+    """
+    seeds = splitmix64(base_seed, 0, count)
+    jobs = []
+    llo, lhi = math.log(side_lo), math.log(side_hi)
+    for j in range(count):
+        sj = int(seeds[j])
+        u = uniform01(sj, 0, 2)
+        raw = splitmix64(sj, 2, 2)
+        if u[0] < p_laplace:
+            kind = KIND_LAPLACE
+        elif u[0] < p_laplace + p_helm:
+            kind = KIND_HELMHOLTZ
+        else:
+            kind = KIND_LIFE
+        side = int(round(math.exp(llo + u[1] * (lhi - llo))))
+        side = min(max(side, side_lo), side_hi)
+        arr = float((raw[1] >> np.uint64(11)).astype(np.float64) * (2.0 ** -53))
+        jobs.append(JobSpec(index=j, kind=kind, side=side, seed=int(raw[0]), arrival_u=arr))
+    return jobs
+
+
+def poisson_arrivals(jobs: list[JobSpec], rate: float) -> np.ndarray:
+    """Arrival times (s) from the jobs' own uniforms: gap = -ln(1 - U) / rate."""
+    gaps = np.array([-math.log1p(-j.arrival_u) / rate for j in jobs], dtype=np.float64)
+    return np.cumsum(gaps)

@@ -1,0 +1,70 @@
+"""Generator pins: SplitMix64 known answers, counter-based slicing, recipe shapes."""
+import os
+
+import numpy as np
+
+from paper_1609_04567_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    for seed, idx, hexv in rows:
+        assert int(I.splitmix64(int(seed), int(idx), 1)[0]) == int(hexv, 16)
+
+
+def test_stream_slices_are_consistent():
+    full = I.splitmix64(12345, 0, 5000)
+    assert np.array_equal(full[1234:2345], I.splitmix64(12345, 1234, 2345 - 1234))
+    u = I.uniform01(7, 0, 100000)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 0.01
+
+
+def test_laplace_recipe():
+    a = I.laplace_input(64, 40)
+    assert a.shape == (64, 40) and a.dtype == np.float64
+    assert np.all(a[1:-1, 1:-1] == 0.0)
+    ring = np.concatenate([a[0], a[-1], a[:, 0], a[:, -1]])
+    assert ring.min() >= 0.0 and ring.max() < 1.0 and ring.std() > 0.1
+    # ring cell (i, j) is draw i*cols + j
+    u = I.uniform01(1, 0, 64 * 40).reshape(64, 40)
+    assert a[0, 5] == u[0, 5] and a[63, 39] == u[63, 39] and a[17, 0] == u[17, 0]
+
+
+def test_helmholtz_recipe():
+    h = I.helmholtz_input(65, alpha=1.0)
+    assert h.s[0] == 0.0 and h.s[-1] == 0.0
+    assert np.all(h.ustar[0] == 0.0) and np.all(h.ustar[:, -1] == 0.0)
+    assert np.all(h.u0 == 0.0)
+    assert abs(h.h - 1.0 / 64) < 1e-18
+    assert np.allclose(h.g, h.h ** 2 * (2 * np.pi ** 2 + 1.0) * h.ustar, rtol=1e-15, atol=0)
+
+
+def test_life_recipe_density():
+    g = I.life_input(256, seed=3)
+    assert set(np.unique(g)) <= {0, 1}
+    assert abs(g.mean() - 0.3) < 0.01
+
+
+def test_restore_recipe():
+    r = I.restore_input(128, 96, seed=4, noise=0.4)
+    assert r.clean.min() >= 16 and r.clean.max() <= 239
+    assert r.clean.min() == 16 and r.clean.max() == 239
+    assert abs(r.impulse.mean() - 0.4) < 0.02
+    assert np.all((r.y[r.impulse] == 0) | (r.y[r.impulse] == 255))
+    assert np.array_equal(r.y[~r.impulse], r.clean[~r.impulse])
+
+
+def test_job_stream_mix():
+    jobs = I.job_stream(2000)
+    kinds = [j.kind for j in jobs]
+    assert abs(kinds.count("laplace") / 2000 - 0.6) < 0.04
+    assert abs(kinds.count("helmholtz") / 2000 - 0.25) < 0.04
+    sides = np.array([j.side for j in jobs])
+    assert sides.min() >= 128 and sides.max() <= 4096
+    # log-uniform: the median side is near sqrt(128*4096) = 724
+    assert 600 < np.median(sides) < 870
+    assert I.job_stream(5)[3].seed == jobs[3].seed

@@ -1,0 +1,141 @@
+"""Pins for the oracle's two-phase impulse restoration (Sect. 4.3).
+
+Detection: every injected impulse is flagged (0 is never above a window's
+minimum, 255 never below its maximum), and brute force with sorted windows on
+small images. Restoration: affine and constant images are fixed points, the
+quadratic functional gives the neighbour mean, and the bisection agrees with a
+bounded scalar minimiser of the functional itself.
+
+Parity unpinned by the paper: phi(t) = sqrt(beta + t^2), beta = 100, w_max = 19
+and the detection edge rules are this project's readings; the paper only names
+the method.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+
+import oracle as O
+from paper_1609_04567_amd import inputs as I
+
+
+def _amf_brute(y, w_max):
+    rows, cols = y.shape
+    mask = np.zeros_like(y)
+    u0 = y.copy()
+    for i in range(rows):
+        for j in range(cols):
+            yv = int(y[i, j])
+            decided = False
+            for w in range(3, w_max + 1, 2):
+                k = w // 2
+                win = np.sort(y[max(0, i - k):i + k + 1, max(0, j - k):j + k + 1].ravel())
+                lo, hi, med = int(win[0]), int(win[-1]), int(win[(len(win) - 1) // 2])
+                if lo < med < hi:
+                    flag = not (lo < yv < hi)
+                    decided = True
+                    break
+            if not decided:
+                flag = yv == lo or yv == hi
+            mask[i, j] = flag
+            if flag:
+                u0[i, j] = med
+    return mask, u0
+
+
+@pytest.mark.parametrize("shape,noise,wmax", [((8, 8), 0.4, 19), ((13, 11), 0.7, 7),
+                                              ((24, 20), 0.4, 5), ((6, 9), 0.9, 3)])
+def test_amf_against_sorted_windows(shape, noise, wmax):
+    r = I.restore_input(*shape, seed=21, noise=noise)
+    m, u0 = O.amf_detect(r.y, wmax)
+    mb, ub = _amf_brute(r.y, wmax)
+    assert np.array_equal(m, mb) and np.array_equal(u0, ub)
+
+
+@pytest.mark.parametrize("side,noise", [(64, 0.4), (200, 0.7), (256, 0.3)])
+def test_amf_flags_every_impulse(side, noise):
+    r = I.restore_input(side, seed=4, noise=noise)
+    m, u0 = O.amf_detect(r.y, 19)
+    assert np.all(m[r.impulse] == 1)
+    assert np.array_equal(u0[m == 0], r.y[m == 0])
+    # false positives are a small fraction of the clean pixels at moderate noise
+    if noise <= 0.4:
+        assert m[~r.impulse].mean() < 0.1
+
+
+def test_argmin_matches_scalar_minimiser():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        k = int(rng.integers(1, 9))
+        v = rng.integers(0, 256, size=k).astype(np.float64)
+        t = O.restore_argmin(v, 100.0)
+        F = lambda x: np.sum(np.sqrt(100.0 + (x - v) ** 2))
+        if v.min() == v.max():
+            assert t == v[0]
+            continue
+        ref = minimize_scalar(F, bounds=(v.min(), v.max()), method="bounded",
+                              options={"xatol": 1e-10}).x
+        assert abs(t - ref) < 1e-4 and F(t) <= F(ref) + 1e-9
+        # the functional's slope changes sign across t (within a few ulps)
+        dF = lambda x: np.sum((x - v) / np.sqrt(100.0 + (x - v) ** 2))
+        eps = 1e-12 * max(1.0, abs(t))
+        assert dF(t - eps) <= 1e-12 and dF(t + eps) >= -1e-12
+
+
+def test_argmin_quadratic_is_the_mean():
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        v = rng.random(int(rng.integers(2, 9))) * 255
+        t = O.restore_argmin(v, 100.0, quadratic=True)
+        assert abs(t - v.mean()) <= 4e-14 * 255
+
+
+def test_quadratic_sweep_is_neighbour_mean():
+    r = I.restore_input(16, 12, seed=5)
+    m, u0 = O.amf_detect(r.y, 19)
+    u = u0.astype(np.float64)
+    b, res = O.restore_run(u, m, quadratic=True, cond=O.COND_NEVER, max_iter=1)
+    p = np.pad(u, 1, constant_values=np.nan)
+    for i, j in zip(*np.nonzero(m)):
+        w = p[i:i + 3, j:j + 3].ravel()
+        nb = np.delete(w, 4)
+        nb = nb[~np.isnan(nb)]
+        assert abs(b[i, j] - nb.mean()) <= 1e-12 * 255
+    assert np.array_equal(b[m == 0], u[m == 0])
+
+
+def test_affine_image_is_a_fixed_point():
+    i = np.arange(20, dtype=np.float64)[:, None]
+    j = np.arange(24, dtype=np.float64)[None, :]
+    u = 30.0 + 3.0 * i + 2.0 * j
+    m = np.zeros(u.shape, dtype=np.uint8)
+    m[1:-1, 1:-1] = 1
+    b, r = O.restore_run(u, m, thr=0.1, max_iter=50)
+    assert r.n == 1 and r.converged and r.r < 1e-12
+    assert np.max(np.abs(b - u)) < 1e-12
+
+
+def test_constant_image_is_exact_fixed_point():
+    u = np.full((9, 7), 77.0)
+    m = np.ones(u.shape, dtype=np.uint8)
+    b, r = O.restore_run(u, m, thr=0.1, max_iter=50)
+    assert r.n == 1 and r.r == 0.0 and np.array_equal(b, u)
+
+
+def test_restoration_pipeline_plausibility():
+    r = I.restore_input(256, seed=4, noise=0.4)
+    m, u0 = O.amf_detect(r.y, 19)
+    u, res = O.restore_run(u0.astype(np.float64), m, thr=0.1, max_iter=200, trace_cap=200)
+    assert res.converged and 3 <= res.n <= 60
+    err_noisy = np.abs(r.y.astype(float) - r.clean).mean()
+    err_rest = np.abs(u - r.clean).mean()
+    assert err_rest < 0.1 * err_noisy
+    # the field stays inside the value range of the data
+    assert u.min() >= 0 and u.max() <= 255
+
+
+def test_mean_abs_reduce_matches_definition():
+    r = I.restore_input(32, seed=6)
+    m, u0 = O.amf_detect(r.y, 19)
+    u = u0.astype(np.float64)
+    b, res = O.restore_run(u, m, reduce_op=O.RED_MEAN_ABS_DELTA, cond=O.COND_NEVER, max_iter=1)
+    assert abs(res.r - np.abs(b - u).sum() / u.size) < 1e-14 * 255
