@@ -1,0 +1,215 @@
+/*
+ * lsr.h -- C ABI of the MI355X (gfx950) loop-of-stencil-reduce library.
+ *
+ * The pattern (Aldinucci et al., "A Parallel Pattern for Iterative Stencil +
+ * Reduce", Sect. 3.1) repeats  a = stencil(sigma_k, f):a  until a condition c
+ * holds on a global reduce /(+) of the new array (or of delta(new, old) in the
+ * -d variant), with an optional global state s such as the sweep count (-s
+ * variant). A call to lsr_run is one instance of that procedure:
+ *
+ *   grid       -> a (the array; in/out: it holds the last iterate on completion)
+ *   stencil_id -> (k, f): a compiled elemental function on the 3x3 neighbourhood
+ *                 (k = 1, the halo width given by the paper's "3, 3" extent)
+ *   reduce_op  -> (delta, (+), identity)
+ *   cond       -> c, evaluated every check_every sweeps and at the sweep cap
+ *   max_iter   -> the -s state bound (n == max_iter stops the loop)
+ *
+ * The building blocks the paper's constructor takes (Sect. 3.2: elemental
+ * function, combinator with identity, iteration condition, sizes, neighbourhood
+ * extent) map one to one onto these arguments. The detection phase of the
+ * two-phase restoration is its own stage in the paper's pipeline (Sect. 4.3), so
+ * it is a separate one-shot call (lsr_amf_detect).
+ *
+ * Conventions
+ *  - Every call returns lsr_status; nothing throws or aborts across the ABI.
+ *    lsr_last_error() gives a thread-local message for the last failure.
+ *  - All grid/env pointers are DEVICE pointers (e.g. torch tensors' data_ptr())
+ *    on the context's device. Grids are row-major with a row pitch counted in
+ *    elements (pitch >= cols); env arrays use the same pitch as the grid.
+ *  - The caller owns grid->data and the env arrays. The library owns its scratch
+ *    (the ping-pong partner grid, per-block partials, the 64-byte job state) and
+ *    draws it from a pool bounded by lsr_config.hbm_budget_bytes.
+ *  - Ordering: lsr_run starts after all work already enqueued on the context's
+ *    stream (lsr_config.stream, NULL = the null stream) and returns at once;
+ *    the caller must not touch the job's buffers until lsr_result reports a
+ *    terminal status. lsr_result then orders the caller's stream after the job.
+ *  - A context is driven from one host thread at a time.
+ */
+#ifndef LSR_H
+#define LSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsr_ctx lsr_ctx;
+typedef int64_t lsr_job;
+
+typedef enum {
+    LSR_OK = 0,
+    LSR_EINVAL = 1,     /* invalid argument or unsupported combination */
+    LSR_ENOMEM = 2,     /* device allocation failed */
+    LSR_EBUSY = 3,      /* over the HBM budget, or a non-blocking result is not ready */
+    LSR_EDEVICE = 4,    /* a HIP call failed; lsr_last_error() has the HIP message */
+    LSR_ENUMERIC = 5,   /* the reduce value became NaN or Inf; the loop stopped there */
+    LSR_ECANCELED = 6,  /* the job was cancelled */
+    LSR_ENOTFOUND = 7   /* unknown job id (never issued, or its result was already taken) */
+} lsr_status;
+
+typedef enum { LSR_U8 = 1, LSR_F32 = 4, LSR_F64 = 8 } lsr_dtype;
+
+/* Out-of-range handling of the neighbourhood (the bottom value of Sect. 3.1). */
+typedef enum {
+    LSR_BC_RING = 0,    /* the outer ring is fixed boundary data, never updated (Jacobi) */
+    LSR_BC_TORUS = 1,   /* both axes wrap (Life) */
+    LSR_BC_BOTTOM = 2   /* out-of-range items are absent: dead cells (Life, Fig. 1),
+                           dropped neighbours (restoration) */
+} lsr_bc;
+
+typedef enum {
+    LSR_ST_LAPLACE5 = 1,    /* b = 0.25*((N+S)+(W+E)) on interior cells (Helmholtz with alpha=0, f=0) */
+    LSR_ST_HELMHOLTZ5 = 2,  /* b = (((N+S)+(W+E)) + g) * rd, rd = 1/(4 + alpha*h*h), g = h^2 f in env0
+                               (the Jacobi solver of Sect. 4.1); param[0] = alpha, param[1] = h */
+    LSR_ST_LIFE = 3,        /* B3/S23 on u8 cells (Fig. 1); non-zero bytes are alive; output is 0/1 */
+    LSR_ST_RESTORE = 4      /* flagged pixels (env0 = u8 mask) take argmin_t sum phi(t - u_m) over
+                               their in-range 8-neighbourhood (phase 2 of Sect. 4.3);
+                               phi(t) = sqrt(beta + t^2), param[0] = beta,
+                               param[1] != 0 selects phi(t) = t^2 */
+} lsr_stencil_id;
+
+typedef enum {
+    LSR_RED_MAX_ABS_DELTA = 1,  /* max |b - a| over the grid (0 where a cell is not updated) */
+    LSR_RED_L2_DELTA = 2,       /* sqrt(sum (b - a)^2), unscaled */
+    LSR_RED_SUM = 3,            /* number of live cells of b (u64; Life) */
+    LSR_RED_MEAN_ABS_DELTA = 4  /* sum |b - a| / (rows*cols) (the restoration test of Sect. 4.3) */
+} lsr_reduce_op;
+
+typedef enum {
+    LSR_COND_BELOW = 1,      /* stop when r < threshold (strict) */
+    LSR_COND_STABLE_FOR = 2, /* stop once the count was unchanged at stable_window consecutive
+                                checks; the count before the first sweep is the first reference */
+    LSR_COND_NEVER = 3       /* run to max_iter */
+} lsr_cond_kind;
+
+typedef struct {
+    int32_t kind;           /* lsr_cond_kind */
+    int32_t check_every;    /* >= 1; the reduce and the test run every check_every sweeps and at max_iter */
+    int32_t stable_window;  /* >= 1 for LSR_COND_STABLE_FOR */
+    int32_t reserved;
+    double threshold;       /* for LSR_COND_BELOW */
+} lsr_cond;
+
+typedef struct {
+    void *data;             /* device pointer, rows x pitch elements of dtype (in/out) */
+    int64_t rows, cols;     /* rows, cols >= 3 (Jacobi), >= 1 otherwise */
+    int64_t pitch;          /* elements between row starts, >= cols */
+    int32_t dtype;          /* lsr_dtype: F64, or F32 storage (arithmetic in FP32, reduce and test
+                               in FP64) for Jacobi/restoration; U8 for Life */
+    int32_t bc;             /* lsr_bc */
+    const void *env0;       /* read-only env: Helmholtz g (grid dtype), restoration mask (u8) */
+    const void *env1;       /* reserved, must be NULL */
+    double param[4];        /* stencil parameters, see lsr_stencil_id */
+} lsr_grid;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    uint32_t flags;            /* reserved, 0 */
+    void *stream;              /* hipStream_t the caller orders against (NULL = null stream) */
+    uint64_t hbm_budget_bytes; /* cap on library scratch; 0 = 90% of free device memory */
+} lsr_config;
+
+typedef struct {
+    int64_t iterations;     /* sweeps performed, n */
+    double last_reduce;     /* r at the last check (the count for LSR_RED_SUM) */
+    uint64_t last_count;    /* live cells after the last check (Life) */
+    int32_t converged;      /* 1 if the condition held at the stop (0 if stopped by max_iter) */
+    int32_t status;         /* lsr_status of the job */
+    int32_t stable_run;     /* consecutive unchanged checks at the stop (Life) */
+    int32_t reserved;
+    int64_t checks;         /* number of reduce + condition evaluations */
+    double device_ms;       /* device time from the job's first to its last kernel */
+} lsr_job_result;
+
+/* Tuning overrides; 0 in a field means "choose automatically". */
+typedef struct {
+    int32_t tile_rows;      /* rows each workgroup streams through per sweep */
+    int32_t tb_depth;       /* sweeps fused per kernel (temporal blocking); 1 = off */
+    int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
+    int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
+} lsr_tuning;
+
+/* Creates a context on cfg->device. Returns EINVAL for a bad device, EDEVICE on HIP failure. */
+lsr_status lsr_create(const lsr_config *cfg, lsr_ctx **out);
+
+/* Destroys the context after all its jobs have finished; frees its scratch. */
+lsr_status lsr_destroy(lsr_ctx *ctx);
+
+/* Sets tuning overrides for later lsr_run calls (NULL restores the defaults). */
+lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
+
+/*
+ * Starts one loop-of-stencil-reduce job (asynchronous). Supported combinations:
+ *   LAPLACE5   F64|F32  RING            env0 NULL        MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
+ *   HELMHOLTZ5 F64|F32  RING            env0 g (dtype)   MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
+ *   LIFE       U8       TORUS|BOTTOM    env0 NULL        SUM                  STABLE_FOR|NEVER
+ *   RESTORE    F64|F32  BOTTOM          env0 mask (u8)   MAX_ABS|MEAN_ABS     BELOW|NEVER
+ * EINVAL: null pointers, rows/cols too small, pitch < cols, a combination outside the table,
+ * check_every < 1, max_iter < 1, stable_window < 1 with STABLE_FOR. ENOMEM/EBUSY: scratch.
+ */
+lsr_status lsr_run(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id, int32_t reduce_op,
+                   const lsr_cond *cond, int64_t max_iter, lsr_job *job_out);
+
+/*
+ * Result of a job. wait != 0 blocks until the job ends; wait == 0 returns EBUSY while it
+ * runs. On a terminal status the job's record is released (a second call gives ENOTFOUND)
+ * and the context stream is ordered after the job. Returns the job's own status
+ * (OK, ENUMERIC, ECANCELED, EDEVICE), which is also in out->status.
+ */
+lsr_status lsr_result(lsr_ctx *ctx, lsr_job job, int32_t wait, lsr_job_result *out);
+
+/* Requests cancellation; the job stops at its next chunk boundary with ECANCELED. */
+lsr_status lsr_cancel(lsr_ctx *ctx, lsr_job job);
+
+/*
+ * Adaptive-median impulse detection, phase 1 of the two-phase restoration (Sect. 4.3;
+ * a window grown up to a static bound, Sect. 3.2). For each pixel of the u8 image y,
+ * windows w = 3, 5, ..., w_max of in-range pixels are tried; med is the lower median
+ * (sorted index (count-1)/2). The first window with min < med < max decides
+ * flag = !(min < y < max); if none does, flag = (y == min || y == max) with the w_max
+ * window. Writes mask (u8 0/1, pitch y->pitch) and u_init (dtype u_dtype, pitch
+ * y->pitch): med where flagged, y elsewhere. w_max odd, 3 <= w_max <= 31.
+ * Synchronous with respect to the context stream ordering (enqueued, not waited on).
+ */
+lsr_status lsr_amf_detect(lsr_ctx *ctx, const lsr_grid *y, void *mask, void *u_init,
+                          int32_t u_dtype, int32_t w_max);
+
+/*
+ * Validates a job description exactly as lsr_run does, without a device or a
+ * context: returns LSR_OK or the LSR_EINVAL lsr_run would return (message in
+ * lsr_last_error()). Allocates nothing.
+ */
+lsr_status lsr_check_args(const lsr_grid *grid, int32_t stencil_id, int32_t reduce_op,
+                          const lsr_cond *cond, int64_t max_iter);
+
+/*
+ * Plain device-to-device copy of `bytes` (a multiple of 16; 16-byte aligned device
+ * pointers), run `iters` times back to back on the context's internal stream after
+ * one warm-up copy, timed with HIP events; *avg_ms receives the mean time per copy.
+ * The measured HBM ceiling for the roofline (2*bytes/avg_ms) and the calibration
+ * kernel for the memory counters. Blocks until done.
+ */
+lsr_status lsr_probe_copy(lsr_ctx *ctx, void *dst, const void *src, uint64_t bytes,
+                          int32_t iters, double *avg_ms);
+
+/* Thread-local text of the last error (never NULL). */
+const char *lsr_last_error(void);
+
+/* Library version string. */
+const char *lsr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSR_H */

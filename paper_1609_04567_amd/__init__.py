@@ -1,0 +1,92 @@
+"""Loop-of-stencil-reduce on MI355X (gfx950): Python side of the lsr C ABI.
+
+``_native`` binds every entry point of include/lsr.h under its own name. The
+helpers below only turn torch tensors into ``lsr_grid`` descriptors (pointer,
+shape, pitch, dtype) and pass the current torch stream; every step of the
+pattern runs in the HIP kernels of liblsr.so.
+"""
+from __future__ import annotations
+
+from ._native import (  # noqa: F401
+    LSR_BC_BOTTOM, LSR_BC_RING, LSR_BC_TORUS, LSR_COND_BELOW, LSR_COND_NEVER,
+    LSR_COND_STABLE_FOR, LSR_EBUSY, LSR_ECANCELED, LSR_EDEVICE, LSR_EINVAL, LSR_ENOMEM,
+    LSR_ENOTFOUND, LSR_ENUMERIC, LSR_F32, LSR_F64, LSR_OK, LSR_RED_L2_DELTA,
+    LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
+    LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
+    lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error, lsr_probe_copy,
+    lsr_result, lsr_run,
+    lsr_set_tuning, lsr_version, make_cond, make_grid,
+)
+
+
+def _dtype_code(t):
+    import torch
+    m = {torch.float64: LSR_F64, torch.float32: LSR_F32, torch.uint8: LSR_U8}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def grid_from_tensor(t, bc: int, env0=None, param=()):
+    """lsr_grid over a 2-D CUDA tensor with unit column stride (row pitch = stride(0))."""
+    if t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError("grid must be a 2-D device tensor with unit column stride")
+    if env0 is not None and (env0.shape != t.shape or env0.stride(0) != t.stride(0)):
+        raise ValueError("env0 must have the grid's shape and pitch")
+    return make_grid(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), _dtype_code(t), bc,
+                     env0.data_ptr() if env0 is not None else None, tuple(param))
+
+
+class Context:
+    """An lsr context on one device, ordered against a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0):
+        import torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.handle = lsr_create(device, self.stream.cuda_stream, hbm_budget_bytes)
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            lsr_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def tune(self, tile_rows=0, tb_depth=0, chunk=0, use_graph=0):
+        lsr_set_tuning(self.handle, tile_rows, tb_depth, chunk, use_graph)
+
+    def submit(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+        g = grid_from_tensor(grid_t, bc, env0, param)
+        job = lsr_run(self.handle, g, stencil_id, reduce_op, cond, max_iter)
+        self._keep[job] = (grid_t, env0)  # the caller's buffers stay alive until the result
+        return job
+
+    def result(self, job, wait=True):
+        r = lsr_result(self.handle, job, wait)
+        self._keep.pop(job, None)
+        return r
+
+    def cancel(self, job):
+        lsr_cancel(self.handle, job)
+
+    def run(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+        return self.result(self.submit(grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0,
+                                       param))
+
+    def amf_detect(self, y_t, w_max=19, u_dtype=None):
+        """Phase-1 detection; returns (mask u8, u_init) tensors on y's device."""
+        import torch
+        u_dtype = u_dtype or torch.float64
+        mask = torch.empty_like(y_t)
+        u0 = torch.empty(y_t.shape, dtype=u_dtype, device=y_t.device)
+        if u0.stride(0) != y_t.stride(0):
+            raise ValueError("u_init must share y's pitch")
+        g = grid_from_tensor(y_t, LSR_BC_BOTTOM)
+        lsr_amf_detect(self.handle, g, mask.data_ptr(), u0.data_ptr(), _dtype_code(u0), w_max)
+        return mask, u0

@@ -1,0 +1,234 @@
+// Two-phase impulse-noise restoration (Sect. 4.3).
+//
+// Phase 1, adaptive-median detection (integer, one shot). A 16x16 workgroup
+// stages its pixels plus a halo of w_max/2 in LDS. Each thread grows its window
+// w = 3, 5, ..., w_max over the in-range pixels only; for each window it finds
+// min and max in one pass and the lower median (rank (count-1)/2) by an 8-step
+// radix select: the largest v with #{x < v} <= rank, decided one bit at a time
+// from the top. The first window with min < med < max decides the flag
+// !(min < y < max); otherwise the w_max window decides (y == min || y == max).
+// Output: mask (0/1) and the initial iterate (med where flagged, y elsewhere).
+//
+// Phase 2, restoration sweep. Each flagged pixel takes the minimiser of
+// sum_m phi(t - u_m) over its in-range 8-neighbourhood, phi(t) = sqrt(beta+t^2)
+// (or t^2), reading only the previous iterate. The minimiser is the root of the
+// strictly increasing g(t) = sum (t - v)/sqrt(beta + (t - v)^2) inside
+// [min v, max v]; it is found by Newton steps kept inside a shrinking bracket
+// (a step that leaves the bracket is replaced by its midpoint). Unflagged pixels
+// are never written: both ping-pong buffers hold them from the start.
+#include "kernels.hpp"
+
+namespace lsr {
+namespace {
+
+constexpr int kAmfTile = 16;
+
+__global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
+    const uint8_t* __restrict__ y, int64_t rows, int64_t cols, int64_t pitch, int w_max,
+    uint8_t* __restrict__ mask, void* __restrict__ u_init, int u_dtype) {
+    extern __shared__ uint8_t tile[];
+    const int K = w_max / 2;
+    const int TW = kAmfTile + 2 * K;
+    const int64_t gi0 = (int64_t)blockIdx.y * kAmfTile - K;
+    const int64_t gj0 = (int64_t)blockIdx.x * kAmfTile - K;
+    for (int idx = threadIdx.y * kAmfTile + threadIdx.x; idx < TW * TW; idx += kAmfTile * kAmfTile) {
+        const int ti = idx / TW, tj = idx - ti * TW;
+        const int64_t gi = gi0 + ti, gj = gj0 + tj;
+        tile[idx] = (gi >= 0 && gi < rows && gj >= 0 && gj < cols) ? y[gi * pitch + gj] : 0;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.y * kAmfTile + threadIdx.y;
+    const int64_t jx = (int64_t)blockIdx.x * kAmfTile + threadIdx.x;
+    if (i >= rows || jx >= cols) return;
+    const int ci = threadIdx.y + K, cj = threadIdx.x + K;
+    const int yv = tile[ci * TW + cj];
+    int lo = 0, hi = 0, med = 0, flag = 0;
+    bool decided = false;
+    for (int w = 3; w <= w_max && !decided; w += 2) {
+        const int k = w / 2;
+        // in-range part of the w x w box, in tile coordinates
+        const int ia = ci - (int)min<int64_t>(k, i), ib = ci + (int)min<int64_t>(k, rows - 1 - i);
+        const int ja = cj - (int)min<int64_t>(k, jx), jb = cj + (int)min<int64_t>(k, cols - 1 - jx);
+        const int cnt = (ib - ia + 1) * (jb - ja + 1);
+        lo = 255;
+        hi = 0;
+        for (int a = ia; a <= ib; ++a)
+            for (int b = ja; b <= jb; ++b) {
+                const int v = tile[a * TW + b];
+                lo = min(lo, v);
+                hi = max(hi, v);
+            }
+        const int rank = (cnt - 1) / 2;
+        med = 0;
+        for (int bit = 7; bit >= 0; --bit) {
+            const int cand = med | (1 << bit);
+            int below = 0;
+            for (int a = ia; a <= ib; ++a)
+                for (int b = ja; b <= jb; ++b) below += tile[a * TW + b] < cand;
+            if (below <= rank) med = cand;
+        }
+        if (lo < med && med < hi) {
+            flag = !(lo < yv && yv < hi);
+            decided = true;
+        }
+    }
+    if (!decided) flag = (yv == lo || yv == hi);
+    const int64_t p = i * pitch + jx;
+    mask[p] = (uint8_t)flag;
+    const int u = flag ? med : yv;
+    if (u_dtype == 1) static_cast<uint8_t*>(u_init)[p] = (uint8_t)u;
+    else if (u_dtype == 4) static_cast<float*>(u_init)[p] = (float)u;
+    else static_cast<double*>(u_init)[p] = (double)u;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T x);
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float x) { return 1.0f / sqrtf(x); }
+
+// Root of g(t) = sum phi'(t - v_m) on [lo, hi] by bracketed Newton. The eight
+// neighbour slots are fixed (register resident); `valid` marks the in-range ones.
+template <typename T>
+__device__ T restore_argmin(const T (&v)[8], unsigned valid, T beta, bool quadratic, T start) {
+    T lo = T(0), hi = T(0);
+    bool first = true;
+    int cnt = 0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if (valid & (1u << m)) {
+            lo = (first || v[m] < lo) ? v[m] : lo;
+            hi = (first || v[m] > hi) ? v[m] : hi;
+            first = false;
+            ++cnt;
+        }
+    }
+    if (!(lo < hi)) return lo;
+    if (quadratic) {
+        T s = T(0);
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (valid & (1u << m)) s = s + v[m];
+        return s / T(cnt);
+    }
+    T t = (start > lo && start < hi) ? start : lo + T(0.5) * (hi - lo);
+    const int max_steps = sizeof(T) == 8 ? 64 : 40;
+    for (int it = 0; it < max_steps; ++it) {
+        T gs = T(0), dg = T(0);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (valid & (1u << m)) {
+                const T d = t - v[m];
+                const T q = beta + d * d;
+                const T s = rsqrt_t<T>(q);
+                gs = gs + d * s;
+                dg = dg + beta * (s * s * s);
+            }
+        }
+        if (gs == T(0)) return t;
+        if (gs < T(0)) lo = t; else hi = t;
+        T tn = t - gs / dg;
+        if (!(tn > lo && tn < hi)) tn = lo + T(0.5) * (hi - lo);
+        const T step = tn - t;
+        t = tn;
+        if (!(hi > lo) || step == T(0)) break;
+        const T tol = (sizeof(T) == 8 ? T(4e-16) : T(2e-7)) * (fabs(t) > T(1) ? fabs(t) : T(1));
+        if (fabs(step) <= tol) break;
+    }
+    return t;
+}
+
+template <typename T, int TR>
+__global__ __launch_bounds__(256) void restore_kernel(
+    const T* __restrict__ a, T* __restrict__ b, const uint8_t* __restrict__ mask, int64_t rows,
+    int64_t cols, int64_t pitch, T beta, int quadratic, JobState* __restrict__ st,
+    double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles) {
+    __shared__ double lds[4];
+    if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int64_t n1 = __hip_atomic_load(&st->n_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + j + 1;
+    if (n1 > ctl.max_iter) return;
+    const bool check = is_check_sweep(n1, ctl);
+    const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
+    if (t >= tiles) return;
+    const int band = t / strips, strip = t - band * strips;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int64_t jx = (int64_t)strip * 64 + lx;
+    const bool is_max = ctl.reduce == RED_MAX_ABS;
+    double acc = 0.0;
+    for (int rr = ly; rr < TR; rr += 4) {
+        const int64_t i = (int64_t)band * TR + rr;
+        if (i >= rows || jx >= cols) continue;
+        const int64_t p = i * pitch + jx;
+        if (!mask[p]) continue;
+        T v[8];
+        unsigned valid = 0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int o = m < 4 ? m : m + 1;  // 3x3 box in row order, centre skipped
+            const int64_t ii = i + o / 3 - 1, jj = jx + o % 3 - 1;
+            const bool in = ii >= 0 && jj >= 0 && ii < rows && jj < cols;
+            v[m] = in ? a[ii * pitch + jj] : T(0);
+            valid |= in ? (1u << m) : 0u;
+        }
+        if (valid == 0) continue;
+        const T old = a[p];
+        const T nv = restore_argmin<T>(v, valid, beta, quadratic != 0, old);
+        b[p] = nv;
+        if (check) {
+            const double d = fabs((double)nv - (double)old);
+            acc = is_max ? max_nan(acc, d) : acc + d;
+        }
+    }
+    if (check) {
+        const double s = block_reduce<4>(acc, is_max, lds);
+        if (threadIdx.x == 0) partials[t] = s;
+    }
+}
+
+constexpr int kRestoreRows = 16;
+
+}  // namespace
+
+SweepGeom restore_geom(const RestoreArgs& a, int tile_rows) {
+    (void)tile_rows;
+    SweepGeom g;
+    g.vec = 1;
+    g.waves = 4;
+    g.tile_rows = kRestoreRows;
+    g.strips = (int)((a.cols + 63) / 64);
+    g.bands = (int)((a.rows + kRestoreRows - 1) / kRestoreRows);
+    g.tiles = g.strips * g.bands;
+    g.blocks = pad_to_xcds(g.tiles);
+    return g;
+}
+
+hipError_t launch_restore(const RestoreArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                          const LoopCtl& c, int j, hipStream_t s) {
+    double* parts = static_cast<double*>(partials);
+    if (a.f32) {
+        hipLaunchKernelGGL((restore_kernel<float, kRestoreRows>), dim3(g.blocks), dim3(256), 0, s,
+                           static_cast<const float*>(a.a), static_cast<float*>(a.b), a.mask, a.rows,
+                           a.cols, a.pitch, (float)a.beta, a.quadratic, st, parts, c, j, g.strips,
+                           g.tiles);
+    } else {
+        hipLaunchKernelGGL((restore_kernel<double, kRestoreRows>), dim3(g.blocks), dim3(256), 0, s,
+                           static_cast<const double*>(a.a), static_cast<double*>(a.b), a.mask,
+                           a.rows, a.cols, a.pitch, a.beta, a.quadratic, st, parts, c, j, g.strips,
+                           g.tiles);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64_t pitch,
+                             int w_max, uint8_t* mask, void* u_init, int u_dtype, hipStream_t s) {
+    const int K = w_max / 2;
+    const int TW = kAmfTile + 2 * K;
+    dim3 grid((unsigned)((cols + kAmfTile - 1) / kAmfTile), (unsigned)((rows + kAmfTile - 1) / kAmfTile));
+    hipLaunchKernelGGL(amf_detect_kernel, grid, dim3(kAmfTile, kAmfTile), TW * TW, s, y, rows, cols,
+                       pitch, w_max, mask, u_init, u_dtype);
+    return hipGetLastError();
+}
+
+}  // namespace lsr

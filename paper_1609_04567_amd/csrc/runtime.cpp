@@ -1,0 +1,781 @@
+// Host runtime of the loop-of-stencil-reduce library: the C ABI of lsr.h, a
+// caching device-memory pool bounded by an HBM budget, the job table and the
+// loop driver.
+//
+// Execution model (the paper's Fig. 2 loop, restructured for one MI355X):
+//  * The grid stays resident in HBM for the whole job; a ping-pong partner of
+//    the same shape is drawn from the pool and the two only swap roles (device
+//    memory persistence by buffer swap, Sect. 3.3). The job's sweep kernels
+//    read buffer j%2 and write (j+1)%2.
+//  * The final reduce and the condition run on the device (finalize kernel),
+//    so no value crosses to the host per iteration. The host driver thread
+//    enqueues chunks of `chunk` sweeps (a multiple of check_every, even) as HIP
+//    graph replays, stays at most kDepth chunks ahead of the device, and stops
+//    enqueueing as soon as the device-written done flag (mirrored into pinned
+//    host memory) is seen. Sweeps enqueued past the stop exit at entry.
+//  * Each context owns one internal stream (default priority). A job starts
+//    after the work the caller had enqueued on its stream when lsr_run was
+//    called; lsr_result orders the caller's stream after the job's end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lsr.h"
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+lsr_status fail(lsr_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(LSR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kDepth = 3;          // chunks in flight per job
+constexpr int kMirrorSlots = 4096; // pinned state mirrors per context
+constexpr double kChunkTargetUs = 1500.0;
+constexpr int kMaxChunk = 512;
+
+// ---------------------------------------------------------------------------
+// Caching pool. Sizes are rounded to a class (powers of two below 2 MiB,
+// multiples of 2 MiB above) and freed blocks are kept for reuse; live plus
+// cached bytes never exceed the budget (cached blocks are released first).
+// ---------------------------------------------------------------------------
+class Pool {
+  public:
+    void init(uint64_t budget) { budget_ = budget; }
+    static size_t size_class(size_t n) {
+        if (n < 4096) n = 4096;
+        if (n <= (2u << 20)) {
+            size_t p = 4096;
+            while (p < n) p <<= 1;
+            return p;
+        }
+        const size_t g = 2u << 20;
+        return (n + g - 1) / g * g;
+    }
+    lsr_status alloc(size_t n, void** out) {
+        std::lock_guard<std::mutex> lk(mu_);
+        const size_t sz = size_class(n);
+        auto it = free_.find(sz);
+        if (it != free_.end()) {
+            *out = it->second;
+            free_.erase(it);
+            cached_ -= sz;
+            live_[*out] = sz;
+            live_bytes_ += sz;
+            return LSR_OK;
+        }
+        if (live_bytes_ + cached_ + sz > budget_) trim_locked();
+        if (live_bytes_ + sz > budget_)
+            return fail(LSR_EBUSY, "scratch of %zu bytes exceeds the HBM budget (%llu live of %llu)",
+                        sz, (unsigned long long)live_bytes_, (unsigned long long)budget_);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            e = hipMalloc(&p, sz);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(LSR_ENOMEM, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
+            }
+        }
+        live_[p] = sz;
+        live_bytes_ += sz;
+        *out = p;
+        return LSR_OK;
+    }
+    void release(void* p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = live_.find(p);
+        if (it == live_.end()) return;
+        const size_t sz = it->second;
+        live_.erase(it);
+        live_bytes_ -= sz;
+        free_.emplace(sz, p);
+        cached_ += sz;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked();
+    }
+    void destroy() {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked();
+        for (auto& kv : live_) (void)hipFree(kv.first);
+        live_.clear();
+        live_bytes_ = 0;
+    }
+    uint64_t budget() const { return budget_; }
+
+  private:
+    void trim_locked() {
+        for (auto& kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        cached_ = 0;
+    }
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> live_;
+    uint64_t budget_ = 0, live_bytes_ = 0, cached_ = 0;
+};
+
+size_t dtype_size(int dt) { return dt == LSR_U8 ? 1 : dt == LSR_F32 ? 4 : 8; }
+
+enum class Phase { Queued, Running, Finished };
+
+struct Job {
+    lsr_job id = 0;
+    lsr_grid grid{};
+    int stencil = 0;
+    lsr_cond cond{};
+    int64_t max_iter = 0;
+    lsr::LoopCtl ctl{};
+    lsr::SweepGeom geom{};
+    void* buf[2] = {nullptr, nullptr};  // buf[0] = caller grid, buf[1] = partner
+    void* partials = nullptr;
+    lsr::JobState* st = nullptr;
+    int slot = -1;
+    lsr::JobState* mirror_host = nullptr;
+    lsr::JobState* mirror_dev = nullptr;
+    std::vector<char> fin_after;        // finalize after chunk offset j
+    hipEvent_t ev_user = nullptr, ev_begin = nullptr, ev_end = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    std::atomic<bool> cancel{false};
+    Phase phase = Phase::Queued;
+    lsr_job_result result{};
+    lsr_status status = LSR_OK;
+    std::string error;
+};
+
+}  // namespace
+
+struct lsr_ctx {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;    // internal execution stream
+    hipStream_t capture = nullptr;   // stream used only for graph capture
+    Pool pool;
+    lsr_tuning tuning{};
+    lsr::JobState* mirrors_host = nullptr;
+    lsr::JobState* mirrors_dev = nullptr;
+    std::vector<int> free_slots;
+    std::vector<hipEvent_t> event_pool;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job*> queue;
+    std::unordered_map<lsr_job, std::unique_ptr<Job>> jobs;
+    lsr_job next_id = 1;
+    bool stopping = false;
+    std::thread driver;
+
+    void drive();
+    lsr_status run_job(Job* j);
+    lsr_status launch_sweep(Job* j, int off, hipStream_t s);
+    lsr_status enqueue_chunk_plain(Job* j, hipStream_t s);
+    hipEvent_t get_event();
+    void put_event(hipEvent_t e) { event_pool.push_back(e); }
+};
+
+namespace {
+
+lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* c, int64_t max_iter) {
+    if (!g || !c) return fail(LSR_EINVAL, "grid and cond must not be NULL");
+    if (!g->data) return fail(LSR_EINVAL, "grid->data is NULL");
+    if (g->pitch < g->cols) return fail(LSR_EINVAL, "pitch (%lld) < cols (%lld)", (long long)g->pitch, (long long)g->cols);
+    if (c->check_every < 1) return fail(LSR_EINVAL, "check_every must be >= 1");
+    if (max_iter < 1) return fail(LSR_EINVAL, "max_iter must be >= 1");
+    if (g->env1) return fail(LSR_EINVAL, "env1 is reserved and must be NULL");
+    const bool fp = g->dtype == LSR_F64 || g->dtype == LSR_F32;
+    switch (stencil) {
+        case LSR_ST_LAPLACE5:
+        case LSR_ST_HELMHOLTZ5:
+            if (g->rows < 3 || g->cols < 3) return fail(LSR_EINVAL, "Jacobi grids need rows, cols >= 3");
+            if (!fp) return fail(LSR_EINVAL, "Jacobi grids are F64 or F32");
+            if (g->bc != LSR_BC_RING) return fail(LSR_EINVAL, "Jacobi stencils use the RING boundary");
+            if (stencil == LSR_ST_HELMHOLTZ5 && !g->env0) return fail(LSR_EINVAL, "Helmholtz needs env0 = h^2 f");
+            if (stencil == LSR_ST_LAPLACE5 && g->env0) return fail(LSR_EINVAL, "Laplace takes no env0");
+            if (stencil == LSR_ST_HELMHOLTZ5) {
+                const double rd = 1.0 / (4.0 + g->param[0] * (g->param[1] * g->param[1]));
+                if (!std::isfinite(rd)) return fail(LSR_EINVAL, "1/(4 + alpha h^2) is not finite");
+            }
+            if (reduce != LSR_RED_MAX_ABS_DELTA && reduce != LSR_RED_L2_DELTA && reduce != LSR_RED_MEAN_ABS_DELTA)
+                return fail(LSR_EINVAL, "Jacobi reduces are MAX_ABS_DELTA, L2_DELTA, MEAN_ABS_DELTA");
+            if (c->kind != LSR_COND_BELOW && c->kind != LSR_COND_NEVER)
+                return fail(LSR_EINVAL, "Jacobi conditions are BELOW or NEVER");
+            break;
+        case LSR_ST_LIFE:
+            if (g->rows < 1 || g->cols < 1) return fail(LSR_EINVAL, "empty grid");
+            if (g->dtype != LSR_U8) return fail(LSR_EINVAL, "Life grids are U8");
+            if (g->bc != LSR_BC_TORUS && g->bc != LSR_BC_BOTTOM) return fail(LSR_EINVAL, "Life uses TORUS or BOTTOM");
+            if (g->env0) return fail(LSR_EINVAL, "Life takes no env0");
+            if (reduce != LSR_RED_SUM) return fail(LSR_EINVAL, "Life reduces with SUM");
+            if (c->kind != LSR_COND_STABLE_FOR && c->kind != LSR_COND_NEVER)
+                return fail(LSR_EINVAL, "Life conditions are STABLE_FOR or NEVER");
+            if (c->kind == LSR_COND_STABLE_FOR && c->stable_window < 1)
+                return fail(LSR_EINVAL, "stable_window must be >= 1");
+            break;
+        case LSR_ST_RESTORE:
+            if (g->rows < 1 || g->cols < 1) return fail(LSR_EINVAL, "empty grid");
+            if (!fp) return fail(LSR_EINVAL, "restoration grids are F64 or F32");
+            if (g->bc != LSR_BC_BOTTOM) return fail(LSR_EINVAL, "restoration uses the BOTTOM boundary");
+            if (!g->env0) return fail(LSR_EINVAL, "restoration needs env0 = mask");
+            if (g->param[1] == 0.0 && !(g->param[0] > 0.0)) return fail(LSR_EINVAL, "beta must be > 0");
+            if (reduce != LSR_RED_MAX_ABS_DELTA && reduce != LSR_RED_MEAN_ABS_DELTA)
+                return fail(LSR_EINVAL, "restoration reduces are MAX_ABS_DELTA or MEAN_ABS_DELTA");
+            if (c->kind != LSR_COND_BELOW && c->kind != LSR_COND_NEVER)
+                return fail(LSR_EINVAL, "restoration conditions are BELOW or NEVER");
+            break;
+        default:
+            return fail(LSR_EINVAL, "unknown stencil_id %d", stencil);
+    }
+    if (c->kind == LSR_COND_BELOW && !std::isfinite(c->threshold))
+        return fail(LSR_EINVAL, "threshold must be finite");
+    return LSR_OK;
+}
+
+// Sweeps per chunk: a multiple of lcm(check_every, 2) that keeps a chunk near
+// kChunkTargetUs of device time at HBM speed, so the enqueue-ahead window stays
+// a few milliseconds and the overshoot after a stop stays bounded.
+int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int override_chunk) {
+    const int base = check_every % 2 == 0 ? check_every : 2 * check_every;
+    int chunk;
+    if (override_chunk > 0) {
+        chunk = (override_chunk + base - 1) / base * base;
+    } else {
+        const double bytes = (double)g->rows * (double)g->cols * (double)dtype_size(g->dtype) * 3.0;
+        const double est_us = std::max(4.0, bytes / 5.0e6);
+        int m = (int)std::max(1.0, std::floor(kChunkTargetUs / (est_us * base)));
+        chunk = base * m;
+        if (chunk > kMaxChunk) chunk = std::max(base, kMaxChunk / base * base);
+    }
+    const int64_t cap = (max_iter + base - 1) / base * base;
+    if (chunk > cap) chunk = (int)cap;
+    return chunk;
+}
+
+}  // namespace
+
+hipEvent_t lsr_ctx::get_event() {
+    if (!event_pool.empty()) {
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
+    void* src = j->buf[off & 1];
+    void* dst = j->buf[(off + 1) & 1];
+    hipError_t e = hipSuccess;
+    const lsr_grid& g = j->grid;
+    switch (j->stencil) {
+        case LSR_ST_LAPLACE5:
+        case LSR_ST_HELMHOLTZ5: {
+            lsr::JacobiArgs a;
+            a.a = src;
+            a.b = dst;
+            a.g = g.env0;
+            a.rows = g.rows;
+            a.cols = g.cols;
+            a.pitch = g.pitch;
+            a.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
+            a.helm = j->stencil == LSR_ST_HELMHOLTZ5;
+            a.f32 = g.dtype == LSR_F32;
+            e = lsr::launch_jacobi(a, j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        }
+        case LSR_ST_LIFE: {
+            lsr::LifeArgs a;
+            a.a = static_cast<const uint8_t*>(src);
+            a.b = static_cast<uint8_t*>(dst);
+            a.rows = g.rows;
+            a.cols = g.cols;
+            a.pitch = g.pitch;
+            a.torus = g.bc == LSR_BC_TORUS;
+            e = lsr::launch_life(a, j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        }
+        case LSR_ST_RESTORE: {
+            lsr::RestoreArgs a;
+            a.a = src;
+            a.b = dst;
+            a.mask = static_cast<const uint8_t*>(g.env0);
+            a.rows = g.rows;
+            a.cols = g.cols;
+            a.pitch = g.pitch;
+            a.beta = g.param[0];
+            a.quadratic = g.param[1] != 0.0;
+            a.f32 = g.dtype == LSR_F32;
+            e = lsr::launch_restore(a, j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        }
+    }
+    if (e != hipSuccess) return fail(LSR_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
+    if (j->fin_after[off]) {
+        e = lsr::launch_finalize(j->st, j->partials, j->ctl, off, j->mirror_dev, s);
+        if (e != hipSuccess) return fail(LSR_EDEVICE, "finalize launch: %s", hipGetErrorString(e));
+    }
+    return LSR_OK;
+}
+
+lsr_status lsr_ctx::enqueue_chunk_plain(Job* j, hipStream_t s) {
+    for (int off = 0; off < j->ctl.chunk; ++off) {
+        lsr_status st = launch_sweep(j, off, s);
+        if (st != LSR_OK) return st;
+    }
+    return LSR_OK;
+}
+
+lsr_status lsr_ctx::run_job(Job* j) {
+    HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
+    HIP_TRY(hipEventRecord(j->ev_begin, stream));
+    const lsr_grid& g = j->grid;
+    const size_t esz = dtype_size(g.dtype);
+    // Partner buffer starts as a copy: boundary ring (Jacobi) and unflagged
+    // pixels (restoration) are never rewritten, so both buffers must hold them.
+    if (j->stencil != LSR_ST_LIFE)
+        HIP_TRY(hipMemcpy2DAsync(j->buf[1], g.pitch * esz, j->buf[0], g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+    if (j->stencil == LSR_ST_LIFE) {
+        int np = 0;
+        HIP_TRY(lsr::launch_count_u8(static_cast<const uint8_t*>(j->buf[0]), g.rows, g.cols, g.pitch,
+                                     j->partials, &np, stream));
+        HIP_TRY(lsr::launch_init_state(j->st, j->partials, np, stream));
+    } else {
+        HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream));
+    }
+    if (j->use_graph) {
+        HIP_TRY(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
+        lsr_status st = enqueue_chunk_plain(j, capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(capture, &graph);
+        if (st != LSR_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(LSR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        j->graph = graph;
+        HIP_TRY(hipGraphInstantiate(&j->exec, graph, nullptr, nullptr, 0));
+    }
+    const int64_t max_chunks = (j->max_iter + j->ctl.chunk - 1) / j->ctl.chunk;
+    std::deque<hipEvent_t> inflight;
+    int64_t issued = 0;
+    bool stop_seen = false, cancel_sent = false;
+    volatile lsr::JobState* mir = j->mirror_host;
+    lsr_status status = LSR_OK;
+    while (true) {
+        while ((int)inflight.size() < kDepth && issued < max_chunks && !stop_seen && !cancel_sent) {
+            if (j->cancel.load()) {
+                hipError_t e = lsr::launch_cancel(j->st, j->mirror_dev, stream);
+                if (e != hipSuccess) { status = fail(LSR_EDEVICE, "cancel: %s", hipGetErrorString(e)); break; }
+                cancel_sent = true;
+                break;
+            }
+            if (j->use_graph) {
+                hipError_t e = hipGraphLaunch(j->exec, stream);
+                if (e != hipSuccess) { status = fail(LSR_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e)); break; }
+            } else {
+                status = enqueue_chunk_plain(j, stream);
+                if (status != LSR_OK) break;
+            }
+            hipEvent_t ev = get_event();
+            if (!ev || hipEventRecord(ev, stream) != hipSuccess) {
+                status = fail(LSR_EDEVICE, "event record failed");
+                break;
+            }
+            inflight.push_back(ev);
+            ++issued;
+        }
+        if (status != LSR_OK) break;
+        if (inflight.empty()) {
+            if (cancel_sent) {
+                hipError_t e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) status = fail(LSR_EDEVICE, "sync: %s", hipGetErrorString(e));
+            }
+            break;
+        }
+        hipEvent_t ev = inflight.front();
+        inflight.pop_front();
+        hipError_t e = hipEventSynchronize(ev);
+        put_event(ev);
+        if (e != hipSuccess) { status = fail(LSR_EDEVICE, "hipEventSynchronize: %s", hipGetErrorString(e)); break; }
+        if (mir->done) stop_seen = true;
+        if (j->cancel.load() && !stop_seen && !cancel_sent) {
+            // drain what is in flight, then post the cancel
+            continue;
+        }
+    }
+    for (hipEvent_t ev : inflight) {
+        (void)hipEventSynchronize(ev);
+        put_event(ev);
+    }
+    if (status != LSR_OK) return status;
+    lsr::JobState fin;
+    std::memcpy(&fin, (const void*)mir, sizeof fin);
+    if (fin.n & 1)
+        HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipEventRecord(j->ev_end, stream));
+    HIP_TRY(hipEventSynchronize(j->ev_end));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, j->ev_begin, j->ev_end);
+    lsr_job_result& r = j->result;
+    r.iterations = fin.n;
+    r.last_reduce = fin.r;
+    r.last_count = fin.count;
+    r.converged = fin.converged;
+    r.stable_run = fin.run;
+    r.checks = fin.checks;
+    r.device_ms = ms;
+    r.status = fin.status == lsr::ST_NUMERIC ? LSR_ENUMERIC
+             : fin.status == lsr::ST_CANCELED ? LSR_ECANCELED : LSR_OK;
+    return (lsr_status)r.status;
+}
+
+void lsr_ctx::drive() {
+    (void)hipSetDevice(device);
+    while (true) {
+        Job* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stopping || !queue.empty(); });
+            if (queue.empty()) return;
+            j = queue.front();
+            queue.pop_front();
+            j->phase = Phase::Running;
+        }
+        lsr_status st = run_job(j);
+        if (st != LSR_OK && st != LSR_ENUMERIC && st != LSR_ECANCELED) {
+            j->error = g_last_error;
+            (void)hipStreamSynchronize(stream);
+            (void)hipEventRecord(j->ev_end, stream);
+            j->result.status = st;
+        }
+        j->status = (lsr_status)j->result.status;
+        if (j->exec) (void)hipGraphExecDestroy(j->exec);
+        if (j->graph) (void)hipGraphDestroy(j->graph);
+        j->exec = nullptr;
+        j->graph = nullptr;
+        pool.release(j->buf[1]);
+        pool.release(j->partials);
+        pool.release(j->st);
+        j->buf[1] = j->partials = nullptr;
+        j->st = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (j->slot >= 0) free_slots.push_back(j->slot);
+            j->slot = -1;
+            j->phase = Phase::Finished;
+        }
+        cv_done.notify_all();
+    }
+}
+
+extern "C" {
+
+const char* lsr_last_error(void) { return g_last_error.c_str(); }
+
+const char* lsr_version(void) { return "lsr 0.1 (gfx950)"; }
+
+lsr_status lsr_check_args(const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
+                          const lsr_cond* cond, int64_t max_iter) {
+    return validate(grid, stencil_id, reduce_op, cond, max_iter);
+}
+
+lsr_status lsr_create(const lsr_config* cfg, lsr_ctx** out) {
+    if (!cfg || !out) return fail(LSR_EINVAL, "cfg and out must not be NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(LSR_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(LSR_EINVAL, "device %d out of range", cfg->device);
+    HIP_TRY(hipSetDevice(cfg->device));
+    std::unique_ptr<lsr_ctx> c(new lsr_ctx());
+    c->device = cfg->device;
+    c->user_stream = static_cast<hipStream_t>(cfg->stream);
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    uint64_t budget = cfg->hbm_budget_bytes;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIP_TRY(hipMemGetInfo(&fr, &tot));
+        budget = (uint64_t)(0.9 * (double)fr);
+    }
+    c->pool.init(budget);
+    HIP_TRY(hipHostMalloc((void**)&c->mirrors_host, sizeof(lsr::JobState) * kMirrorSlots,
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer((void**)&c->mirrors_dev, c->mirrors_host, 0));
+    std::memset(c->mirrors_host, 0, sizeof(lsr::JobState) * kMirrorSlots);
+    for (int i = kMirrorSlots - 1; i >= 0; --i) c->free_slots.push_back(i);
+    lsr_ctx* raw = c.release();
+    raw->driver = std::thread([raw] { raw->drive(); });
+    *out = raw;
+    return LSR_OK;
+}
+
+lsr_status lsr_set_tuning(lsr_ctx* ctx, const lsr_tuning* t) {
+    if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
+    if (t && (t->tile_rows < 0 || t->tb_depth < 0 || t->chunk < 0))
+        return fail(LSR_EINVAL, "tuning fields must be >= 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (t) ctx->tuning = *t;
+    else ctx->tuning = lsr_tuning{};
+    return LSR_OK;
+}
+
+lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
+                   const lsr_cond* cond, int64_t max_iter, lsr_job* job_out) {
+    if (!ctx || !job_out) return fail(LSR_EINVAL, "ctx and job_out must not be NULL");
+    lsr_status v = validate(grid, stencil_id, reduce_op, cond, max_iter);
+    if (v != LSR_OK) return v;
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<Job> j(new Job());
+    j->grid = *grid;
+    j->stencil = stencil_id;
+    j->cond = *cond;
+    j->max_iter = max_iter;
+    lsr_tuning tun;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        tun = ctx->tuning;
+        if (ctx->free_slots.empty()) return fail(LSR_EBUSY, "too many jobs in flight");
+        j->slot = ctx->free_slots.back();
+        ctx->free_slots.pop_back();
+    }
+    auto give_back = [&] {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->free_slots.push_back(j->slot);
+    };
+    const size_t esz = dtype_size(grid->dtype);
+    const size_t bytes = (size_t)grid->rows * (size_t)grid->pitch * esz;
+    j->buf[0] = grid->data;
+    // geometry needs both buffers' alignment; the pool returns 256-byte aligned blocks
+    lsr_status st = ctx->pool.alloc(bytes, &j->buf[1]);
+    if (st != LSR_OK) { give_back(); return st; }
+    switch (stencil_id) {
+        case LSR_ST_LAPLACE5:
+        case LSR_ST_HELMHOLTZ5: {
+            lsr::JacobiArgs a{};
+            a.a = j->buf[0];
+            a.b = j->buf[1];
+            a.g = grid->env0;
+            a.rows = grid->rows;
+            a.cols = grid->cols;
+            a.pitch = grid->pitch;
+            a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
+            a.f32 = grid->dtype == LSR_F32;
+            j->geom = lsr::jacobi_geom(a, tun.tile_rows);
+            break;
+        }
+        case LSR_ST_LIFE: {
+            lsr::LifeArgs a{};
+            a.a = static_cast<const uint8_t*>(j->buf[0]);
+            a.b = static_cast<uint8_t*>(j->buf[1]);
+            a.rows = grid->rows;
+            a.cols = grid->cols;
+            a.pitch = grid->pitch;
+            j->geom = lsr::life_geom(a, tun.tile_rows);
+            break;
+        }
+        default: {
+            lsr::RestoreArgs a{};
+            a.rows = grid->rows;
+            a.cols = grid->cols;
+            j->geom = lsr::restore_geom(a, tun.tile_rows);
+        }
+    }
+    int nparts = j->geom.tiles;
+    if (stencil_id == LSR_ST_LIFE) nparts = std::max(nparts, lsr::count_u8_parts(grid->rows, grid->cols));
+    st = ctx->pool.alloc((size_t)std::max(nparts, 1) * 8, &j->partials);
+    if (st == LSR_OK) st = ctx->pool.alloc(sizeof(lsr::JobState), (void**)&j->st);
+    if (st != LSR_OK) {
+        ctx->pool.release(j->buf[1]);
+        ctx->pool.release(j->partials);
+        give_back();
+        return st;
+    }
+    lsr::LoopCtl& c = j->ctl;
+    c.max_iter = max_iter;
+    c.check_every = cond->check_every;
+    c.chunk = pick_chunk(grid, cond->check_every, max_iter, tun.chunk);
+    c.reduce = reduce_op;
+    c.cond = cond->kind;
+    c.stable_window = cond->stable_window;
+    c.nparts = j->geom.tiles;
+    c.threshold = cond->threshold;
+    c.mean_div = (double)grid->rows * (double)grid->cols;
+    j->fin_after.assign(c.chunk, 0);
+    const int jmax = (int)((max_iter - 1) % c.chunk);
+    for (int off = 0; off < c.chunk; ++off)
+        j->fin_after[off] = ((off + 1) % c.check_every == 0) || off == jmax;
+    j->use_graph = tun.use_graph >= 0;
+    j->mirror_host = ctx->mirrors_host + j->slot;
+    j->mirror_dev = ctx->mirrors_dev + j->slot;
+    std::memset((void*)j->mirror_host, 0, sizeof(lsr::JobState));
+    auto cleanup = [&] {
+        ctx->pool.release(j->buf[1]);
+        ctx->pool.release(j->partials);
+        ctx->pool.release(j->st);
+        if (j->ev_user) (void)hipEventDestroy(j->ev_user);
+        if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
+        if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+        give_back();
+    };
+    if (hipEventCreateWithFlags(&j->ev_user, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&j->ev_begin) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+        hipEventRecord(j->ev_user, ctx->user_stream) != hipSuccess) {
+        cleanup();
+        return fail(LSR_EDEVICE, "event setup failed");
+    }
+    Job* raw = j.get();
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        raw->id = ctx->next_id++;
+        ctx->jobs[raw->id] = std::move(j);
+        ctx->queue.push_back(raw);
+    }
+    ctx->cv_work.notify_one();
+    *job_out = raw->id;
+    return LSR_OK;
+}
+
+lsr_status lsr_result(lsr_ctx* ctx, lsr_job job, int32_t wait, lsr_job_result* out) {
+    if (!ctx || !out) return fail(LSR_EINVAL, "ctx and out must not be NULL");
+    std::unique_ptr<Job> j;
+    {
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        auto it = ctx->jobs.find(job);
+        if (it == ctx->jobs.end()) return fail(LSR_ENOTFOUND, "unknown job %lld", (long long)job);
+        Job* p = it->second.get();
+        if (p->phase != Phase::Finished) {
+            if (!wait) return fail(LSR_EBUSY, "job %lld is still running", (long long)job);
+            ctx->cv_done.wait(lk, [&] { return p->phase == Phase::Finished; });
+        }
+        j = std::move(it->second);
+        ctx->jobs.erase(it);
+    }
+    *out = j->result;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamWaitEvent(ctx->user_stream, j->ev_end, 0);
+    (void)hipEventDestroy(j->ev_user);
+    (void)hipEventDestroy(j->ev_begin);
+    (void)hipEventDestroy(j->ev_end);
+    const lsr_status s = (lsr_status)j->result.status;
+    if (s == LSR_EDEVICE) g_last_error = j->error;
+    else if (s == LSR_ENUMERIC) g_last_error = "reduce value became NaN or Inf";
+    else if (s == LSR_ECANCELED) g_last_error = "job cancelled";
+    return s;
+}
+
+lsr_status lsr_cancel(lsr_ctx* ctx, lsr_job job) {
+    if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end()) return fail(LSR_ENOTFOUND, "unknown job %lld", (long long)job);
+    it->second->cancel.store(true);
+    return LSR_OK;
+}
+
+lsr_status lsr_amf_detect(lsr_ctx* ctx, const lsr_grid* y, void* mask, void* u_init,
+                          int32_t u_dtype, int32_t w_max) {
+    if (!ctx || !y || !mask || !u_init || !y->data) return fail(LSR_EINVAL, "NULL argument");
+    if (y->dtype != LSR_U8) return fail(LSR_EINVAL, "the image is U8");
+    if (y->rows < 1 || y->cols < 1 || y->pitch < y->cols) return fail(LSR_EINVAL, "bad image shape");
+    if (u_dtype != LSR_U8 && u_dtype != LSR_F32 && u_dtype != LSR_F64)
+        return fail(LSR_EINVAL, "u_dtype is U8, F32 or F64");
+    if (w_max < 3 || w_max > 31 || w_max % 2 == 0) return fail(LSR_EINVAL, "w_max must be odd in [3, 31]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(lsr::launch_amf_detect(static_cast<const uint8_t*>(y->data), y->rows, y->cols, y->pitch,
+                                   w_max, static_cast<uint8_t*>(mask), u_init, u_dtype,
+                                   ctx->user_stream));
+    return LSR_OK;
+}
+
+lsr_status lsr_probe_copy(lsr_ctx* ctx, void* dst, const void* src, uint64_t bytes, int32_t iters,
+                          double* avg_ms) {
+    if (!ctx || !dst || !src || !avg_ms || iters < 1) return fail(LSR_EINVAL, "bad probe arguments");
+    if (bytes == 0 || bytes % 16 != 0 || ((reinterpret_cast<uintptr_t>(dst) |
+                                            reinterpret_cast<uintptr_t>(src)) & 15) != 0)
+        return fail(LSR_EINVAL, "probe needs 16-byte aligned buffers and a multiple of 16 bytes");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = lsr::launch_copy16(src, dst, (int64_t)bytes, ctx->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    for (int i = 0; i < iters && e == hipSuccess; ++i)
+        e = lsr::launch_copy16(src, dst, (int64_t)bytes, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(LSR_EDEVICE, "copy probe: %s", hipGetErrorString(e));
+    *avg_ms = (double)ms / iters;
+    return LSR_OK;
+}
+
+lsr_status lsr_destroy(lsr_ctx* ctx) {
+    if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->stopping = true;
+    }
+    ctx->cv_work.notify_all();
+    if (ctx->driver.joinable()) ctx->driver.join();
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->jobs) {
+        Job* j = kv.second.get();
+        if (j->ev_user) (void)hipEventDestroy(j->ev_user);
+        if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
+        if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+    }
+    ctx->jobs.clear();
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    ctx->pool.destroy();
+    if (ctx->mirrors_host) (void)hipHostFree(ctx->mirrors_host);
+    (void)hipStreamDestroy(ctx->capture);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return LSR_OK;
+}
+
+}  // extern "C"

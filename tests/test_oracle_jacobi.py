@@ -116,14 +116,29 @@ def test_helmholtz_converges_to_direct_solve():
 
 
 def _closed_form(n, alpha, sweeps):
-    """u^k = c*(1-mu^k) u*, ||Delta^k||_2 = c*(1-mu) mu^(k-1) (N-1)/2."""
+    """u^k = c*(1-mu^k) u*, ||Delta^k||_2 = c*(1-mu) mu^(k-1) (N-1)/2, with 1 - mu
+    written without cancellation: (8 sin^2(pi h/2) + alpha h^2) / (4 + alpha h^2)."""
+    h = 1.0 / (n - 1)
+    s2 = math.sin(math.pi * h / 2) ** 2
+    one_m_mu = (8.0 * s2 + alpha * h * h) / (4.0 + alpha * h * h)
+    mu = 1.0 - one_m_mu
+    lam = 8.0 / (h * h) * s2
+    cstar = (2 * math.pi ** 2 + alpha) / (lam + alpha)
+    lmu = math.log1p(-one_m_mu)
+    coef = cstar * -math.expm1(sweeps * lmu)
+    dnorm = cstar * one_m_mu * math.exp((sweeps - 1) * lmu) * (n - 1) / 2.0
+    return coef, dnorm, mu, cstar
+
+
+def test_closed_form_agrees_with_the_naive_expression_where_it_is_well_conditioned():
+    n, alpha, k = 33, 1.0, 40
     h = 1.0 / (n - 1)
     mu = 4.0 * math.cos(math.pi * h) / (4.0 + alpha * h * h)
     lam = 8.0 / (h * h) * math.sin(math.pi * h / 2) ** 2
     cstar = (2 * math.pi ** 2 + alpha) / (lam + alpha)
-    coef = cstar * (1.0 - mu ** sweeps)
-    dnorm = cstar * (1.0 - mu) * mu ** (sweeps - 1) * (n - 1) / 2.0
-    return coef, dnorm, mu, cstar
+    coef, dnorm, mu2, _ = _closed_form(n, alpha, k)
+    assert abs(mu2 - mu) < 1e-15
+    assert abs(coef - cstar * (1 - mu ** k)) / coef < 1e-12
 
 
 @pytest.mark.parametrize("n,sweeps", [(65, 3000), (257, 1500)])
@@ -145,7 +160,9 @@ def test_helmholtz_closed_form_trajectory(n, sweeps):
 def test_helmholtz_8192_closed_form_constants():
     """The full-size run is pinned by the closed form alone: it cannot stop before the cap."""
     coef, dnorm, mu, cstar = _closed_form(8192, 1.0, 5000)
-    assert abs((1 - mu) - 7.727844e-8) / 7.727844e-8 < 1e-5
+    h = 1.0 / 8191
+    one_m_mu = (8.0 * math.sin(math.pi * h / 2) ** 2 + h * h) / (4.0 + h * h)
+    assert abs(one_m_mu - 7.727844e-8) / 7.727844e-8 < 1e-5
     assert dnorm > 1e-9 * 1e5  # ||Delta^5000|| ~ 3.16e-4, far above the threshold
     assert abs(dnorm - 3.1637e-4) / 3.1637e-4 < 1e-3
     assert abs(coef - 3.8632e-4) / 3.8632e-4 < 1e-3
