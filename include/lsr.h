@@ -138,6 +138,8 @@ typedef struct {
     int32_t tb_depth;       /* sweeps fused per kernel (temporal blocking); 1 = off */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
+    int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */
+    int32_t unroll;         /* Jacobi: rows loaded together per wavefront (4, 8 or 16) */
 } lsr_tuning;
 
 /* Creates a context on cfg->device. Returns EINVAL for a bad device, EDEVICE on HIP failure. */

@@ -58,8 +58,8 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def tune(self, tile_rows=0, tb_depth=0, chunk=0, use_graph=0):
-        lsr_set_tuning(self.handle, tile_rows, tb_depth, chunk, use_graph)
+    def tune(self, tile_rows=0, tb_depth=0, chunk=0, use_graph=0, waves=0, unroll=0):
+        lsr_set_tuning(self.handle, tile_rows, tb_depth, chunk, use_graph, waves, unroll)
 
     def submit(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
         g = grid_from_tensor(grid_t, bc, env0, param)

@@ -52,7 +52,7 @@ class lsr_job_result(C.Structure):
 
 class lsr_tuning(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("tb_depth", C.c_int32), ("chunk", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("waves", C.c_int32), ("unroll", C.c_int32)]
 
 
 class LsrError(RuntimeError):
@@ -124,8 +124,8 @@ def lsr_destroy(ctx: int) -> None:
 
 
 def lsr_set_tuning(ctx: int, tile_rows: int = 0, tb_depth: int = 0, chunk: int = 0,
-                   use_graph: int = 0) -> None:
-    t = lsr_tuning(tile_rows, tb_depth, chunk, use_graph)
+                   use_graph: int = 0, waves: int = 0, unroll: int = 0) -> None:
+    t = lsr_tuning(tile_rows, tb_depth, chunk, use_graph, waves, unroll)
     _check(lib().lsr_set_tuning(ctx, C.byref(t)))
 
 

@@ -19,9 +19,12 @@ namespace {
 
 constexpr int kFinThreads = 1024;
 
+// The host mirror starts zeroed (done == 0) and is written only once the loop
+// has stopped: that is the only transition the host driver waits for, and it
+// keeps a write to host memory off every other check.
 __device__ void publish(JobState* st, JobState* mirror, const JobState& s) {
     *st = s;
-    if (mirror) {
+    if (mirror && s.done) {
         volatile int64_t* m = reinterpret_cast<volatile int64_t*>(mirror);
         const int64_t* v = reinterpret_cast<const int64_t*>(&s);
 #pragma unroll

@@ -22,12 +22,14 @@
 namespace lsr {
 namespace {
 
-template <typename T, int VEC>
+// NTL = non-temporal load (for data read exactly once per sweep, such as g).
+template <typename T, int VEC, bool NTL = false>
 __device__ __forceinline__ void load_row(const T* __restrict__ p, int64_t c, int64_t cols,
                                          T (&v)[VEC]) {
     if (VEC > 1 && c + VEC <= cols) {
         typedef T V __attribute__((ext_vector_type(VEC)));
-        V x = *reinterpret_cast<const V*>(p + c);
+        V x = NTL ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p + c))
+                  : *reinterpret_cast<const V*>(p + c);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) v[e] = x[e];
     } else {
@@ -36,7 +38,9 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, int64_t c, int
     }
 }
 
-template <typename T, int VEC>
+// NT = non-temporal: the next iterate is not read again before the whole grid has
+// streamed through, so keeping it out of L2/MALL leaves room for the halo rows.
+template <typename T, int VEC, bool NT>
 __device__ __forceinline__ void store_row(T* __restrict__ p, int64_t c, int64_t cols,
                                           const T (&v)[VEC]) {
     if (VEC > 1 && c + VEC <= cols) {
@@ -44,7 +48,8 @@ __device__ __forceinline__ void store_row(T* __restrict__ p, int64_t c, int64_t 
         V x;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) x[e] = v[e];
-        *reinterpret_cast<V*>(p + c) = x;
+        if (NT) __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + c));
+        else *reinterpret_cast<V*>(p + c) = x;
     } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
@@ -58,7 +63,8 @@ __device__ __forceinline__ double accum(int red, double acc, double d) {
     return acc + fabs(d);
 }
 
-template <typename T, bool HELM, int VEC, int NW, int U>
+template <typename T, bool HELM, int VEC, int NW, int U, bool NT = false, bool NTG = false,
+          bool NTU = false>
 __global__ __launch_bounds__(NW * 64) void jacobi5_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, JobState* __restrict__ st, double* __restrict__ partials,
@@ -78,7 +84,9 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_kernel(
     const int64_t r0 = 1 + (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows - 1);
     const int64_t ce = cw + 64 * VEC;           // first column after this wavefront
-    const bool has_w = (lane == 0) && cw >= 1;
+    // Halo elements exist only for wavefronts that own columns of the grid
+    // (cw < cols); a wavefront past the last column loads nothing at all.
+    const bool has_w = (lane == 0) && cw >= 1 && cw < cols;
     const bool has_e = (lane == 63) && ce < cols;
     const int red = ctl.reduce;
 
@@ -96,10 +104,10 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_kernel(
         for (int k = 0; k < U; ++k) {
             if (r + k < r1) {
                 const T* prow = a + (r + k + 1) * pitch;
-                load_row<T, VEC>(prow, c, cols, dn[k]);
+                load_row<T, VEC, NTU>(prow, c, cols, dn[k]);
                 dn_w[k] = has_w ? prow[cw - 1] : T(0);
                 dn_e[k] = has_e ? prow[ce] : T(0);
-                if (HELM) load_row<T, VEC>(g + (r + k) * pitch, c, cols, gr[k]);
+                if (HELM) load_row<T, VEC, NTG>(g + (r + k) * pitch, c, cols, gr[k]);
             }
         }
 #pragma unroll
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_kernel(
                     out[e] = inner ? nv : mid[e];
                     if (check && inner) acc = accum(red, acc, (double)nv - (double)mid[e]);
                 }
-                store_row<T, VEC>(b + (r + k) * pitch, c, cols, out);
+                store_row<T, VEC, NT>(b + (r + k) * pitch, c, cols, out);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) { up[e] = mid[e]; mid[e] = dn[k][e]; }
                 mid_w = dn_w[k];
@@ -137,9 +145,6 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_kernel(
     }
 }
 
-constexpr int kWaves = 4;
-constexpr int kUnroll = 4;
-
 int pick_vec(const JacobiArgs& a) {
     const int esz = a.f32 ? 4 : 8;
     const int want = a.f32 ? 4 : 2;
@@ -148,24 +153,64 @@ int pick_vec(const JacobiArgs& a) {
     return 1;
 }
 
-template <typename T, bool HELM, int VEC>
+// Launch shapes measured on the MI355X at 8192^2 (sweep kernel alone, % of 8 TB/s):
+//   FP64 Helmholtz  1 wave x 8-row unroll, 8-row tiles        79 %
+//   FP64 Laplace    4 waves x 8                               75 %
+//   FP32 Helmholtz  4 waves x 8                               76 %
+//   FP32 Laplace    4 waves x 16                              73 %
+// Vector paths store the next iterate non-temporally and read g non-temporally
+// (both are touched once per sweep); the unaligned scalar path uses 4 x 4.
+struct Shape {
+    int waves, unroll;
+};
+constexpr Shape kShapes[] = {{1, 8}, {2, 8}, {4, 4}, {4, 8}, {4, 16}};
+
+bool shape_ok(int waves, int unroll) {
+    for (const Shape& s : kShapes)
+        if (s.waves == waves && s.unroll == unroll) return true;
+    return false;
+}
+
+template <typename T, bool HELM, int VEC, int NW, int U>
 hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_kernel<T, HELM, VEC, kWaves, kUnroll>), dim3(g.blocks),
-                       dim3(kWaves * 64), 0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
+    hipLaunchKernelGGL((jacobi5_kernel<T, HELM, VEC, NW, U, true, HELM, false>), dim3(g.blocks),
+                       dim3(NW * 64), 0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd), st,
                        static_cast<double*>(partials), c, j, g.strips, g.tiles, g.tile_rows);
     return hipGetLastError();
 }
 
+template <typename T, bool HELM, int VEC>
+hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                        const LoopCtl& c, int j, hipStream_t s) {
+    if (VEC == 1) return launch_t<T, HELM, VEC, 4, 4>(a, g, st, partials, c, j, s);
+    switch (g.waves * 100 + g.unroll) {
+        case 108: return launch_t<T, HELM, VEC, 1, 8>(a, g, st, partials, c, j, s);
+        case 208: return launch_t<T, HELM, VEC, 2, 8>(a, g, st, partials, c, j, s);
+        case 404: return launch_t<T, HELM, VEC, 4, 4>(a, g, st, partials, c, j, s);
+        case 408: return launch_t<T, HELM, VEC, 4, 8>(a, g, st, partials, c, j, s);
+        case 416: return launch_t<T, HELM, VEC, 4, 16>(a, g, st, partials, c, j, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows) {
+SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll) {
     SweepGeom g;
     g.vec = pick_vec(a);
-    g.waves = kWaves;
-    g.tile_rows = tile_rows > 0 ? tile_rows : 32;
-    const int64_t span = (int64_t)kWaves * 64 * g.vec;
+    if (g.vec == 1) {
+        waves = 4;
+        unroll = 4;
+    } else if (!shape_ok(waves, unroll)) {
+        if (a.f32) { waves = 4; unroll = a.helm ? 8 : 16; }
+        else { waves = a.helm ? 1 : 4; unroll = 8; }
+    }
+    g.waves = waves;
+    g.unroll = unroll;
+    g.tile_rows = tile_rows > 0 ? tile_rows : 8;
+    const int64_t span = (int64_t)waves * 64 * g.vec;
     g.strips = (int)((a.cols + span - 1) / span);
     g.bands = (int)((a.rows - 2 + g.tile_rows - 1) / g.tile_rows);
     g.tiles = g.strips * g.bands;
@@ -176,15 +221,15 @@ SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows) {
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s) {
     if (a.f32) {
-        if (a.helm) return g.vec == 4 ? launch_t<float, true, 4>(a, g, st, partials, c, j, s)
-                                      : launch_t<float, true, 1>(a, g, st, partials, c, j, s);
-        return g.vec == 4 ? launch_t<float, false, 4>(a, g, st, partials, c, j, s)
-                          : launch_t<float, false, 1>(a, g, st, partials, c, j, s);
+        if (a.helm) return g.vec == 4 ? launch_shape<float, true, 4>(a, g, st, partials, c, j, s)
+                                      : launch_shape<float, true, 1>(a, g, st, partials, c, j, s);
+        return g.vec == 4 ? launch_shape<float, false, 4>(a, g, st, partials, c, j, s)
+                          : launch_shape<float, false, 1>(a, g, st, partials, c, j, s);
     }
-    if (a.helm) return g.vec == 2 ? launch_t<double, true, 2>(a, g, st, partials, c, j, s)
-                                  : launch_t<double, true, 1>(a, g, st, partials, c, j, s);
-    return g.vec == 2 ? launch_t<double, false, 2>(a, g, st, partials, c, j, s)
-                      : launch_t<double, false, 1>(a, g, st, partials, c, j, s);
+    if (a.helm) return g.vec == 2 ? launch_shape<double, true, 2>(a, g, st, partials, c, j, s)
+                                  : launch_shape<double, true, 1>(a, g, st, partials, c, j, s);
+    return g.vec == 2 ? launch_shape<double, false, 2>(a, g, st, partials, c, j, s)
+                      : launch_shape<double, false, 1>(a, g, st, partials, c, j, s);
 }
 
 }  // namespace lsr

@@ -13,6 +13,7 @@ namespace lsr {
 struct SweepGeom {
     int vec = 1;         // elements per lane (1, 2 or 4)
     int waves = 4;       // waves per workgroup
+    int unroll = 4;      // rows whose loads are issued together
     int tile_rows = 32;  // rows streamed per workgroup
     int strips = 0;      // column strips
     int bands = 0;       // row bands
@@ -30,7 +31,8 @@ struct JacobiArgs {
     int helm;            // 0 Laplace, 1 Helmholtz
     int f32;             // 0 FP64 storage, 1 FP32 storage
 };
-SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows);
+// tile_rows / waves / unroll of 0 (or an unsupported pair) select the measured default.
+SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves = 0, int unroll = 0);
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s);
 

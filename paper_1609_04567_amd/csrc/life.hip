@@ -32,7 +32,7 @@ __device__ __forceinline__ uint32_t zero_bytes_hi(uint32_t x) {
     return ~(x + 0x7F7F7F7Fu) & 0x80808080u;
 }
 
-template <int NW, int U>
+template <int NW, int U, bool NT = false>
 __global__ __launch_bounds__(NW * 64) void life_swar_kernel(
     const uint8_t* __restrict__ a, uint8_t* __restrict__ b, int64_t rows, int64_t cols,
     int64_t pitch, int torus, JobState* __restrict__ st, unsigned long long* __restrict__ partials,
@@ -115,12 +115,15 @@ __global__ __launch_bounds__(NW * 64) void life_swar_kernel(
                     cnt += (unsigned)__popc(alive);
                 }
                 if (active) {
-                    uint4 o;
-                    o.x = out[0];
-                    o.y = out[1];
-                    o.z = out[2];
-                    o.w = out[3];
-                    *reinterpret_cast<uint4*>(b + (r + k) * pitch + c) = o;
+                    typedef uint32_t W4 __attribute__((ext_vector_type(4)));
+                    W4 o;
+                    o[0] = out[0];
+                    o[1] = out[1];
+                    o[2] = out[2];
+                    o[3] = out[3];
+                    W4* dst = reinterpret_cast<W4*>(b + (r + k) * pitch + c);
+                    if (NT) __builtin_nontemporal_store(o, dst);
+                    else *dst = o;
                 }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) { up[m] = mid[m]; mid[m] = dn[k][m]; }

@@ -550,7 +550,7 @@ lsr_status lsr_create(const lsr_config* cfg, lsr_ctx** out) {
 
 lsr_status lsr_set_tuning(lsr_ctx* ctx, const lsr_tuning* t) {
     if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
-    if (t && (t->tile_rows < 0 || t->tb_depth < 0 || t->chunk < 0))
+    if (t && (t->tile_rows < 0 || t->tb_depth < 0 || t->chunk < 0 || t->waves < 0 || t->unroll < 0))
         return fail(LSR_EINVAL, "tuning fields must be >= 0");
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (t) ctx->tuning = *t;
@@ -599,7 +599,7 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
             a.pitch = grid->pitch;
             a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
             a.f32 = grid->dtype == LSR_F32;
-            j->geom = lsr::jacobi_geom(a, tun.tile_rows);
+            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll);
             break;
         }
         case LSR_ST_LIFE: {

@@ -1,0 +1,135 @@
+"""Host-side bounds model of the sweep kernels' addressing.
+
+For each launch geometry the library can choose, this replays the index
+arithmetic of jacobi5_kernel and life_swar_kernel (which lanes load or store
+which (row, column), including the wavefront halo elements) and asserts that
+every access lies inside the rows x cols grid. It runs on the CPU, before any
+GPU use, so an out-of-range address is caught here and not on the device.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+JACOBI_SHAPES = [(1, 8), (2, 8), (4, 4), (4, 8), (4, 16)]
+
+
+def _jacobi_accesses(rows, cols, vec, nw, unroll, tile_rows, tiles_subset=None):
+    span = nw * 64 * vec
+    strips = -(-cols // span)
+    bands = -(-(rows - 2) // tile_rows)
+    lanes = np.arange(64)
+    bad = []
+    tiles = range(strips * bands) if tiles_subset is None else tiles_subset(strips, bands)
+    for t in tiles:
+        band, strip = divmod(t, strips)
+        r0 = 1 + band * tile_rows
+        r1 = min(r0 + tile_rows, rows - 1)
+        for w in range(nw):
+            cw = strip * span + w * 64 * vec
+            c = cw + lanes * vec
+            ce = cw + 64 * vec
+            has_w = cw >= 1 and cw < cols           # lane 0 only
+            has_e = ce < cols                       # lane 63 only
+            elem_cols = (c[:, None] + np.arange(vec)[None, :])
+            in_cols = elem_cols[elem_cols < cols]   # guarded element loads / stores
+            rows_read = list(range(r0 - 1, r1 + 1))  # up, mid, then r+1 for r < r1
+            rows_written = list(range(r0, r1))
+            for r in rows_read + rows_written:
+                if not (0 <= r < rows):
+                    bad.append(("row", t, w, r))
+            if in_cols.size and (in_cols.min() < 0 or in_cols.max() >= cols):
+                bad.append(("col", t, w))
+            if has_w and not (0 <= cw - 1 < cols):
+                bad.append(("west halo", t, w, cw - 1))
+            if has_e and not (0 <= ce < cols):
+                bad.append(("east halo", t, w, ce))
+    return bad
+
+
+@pytest.mark.parametrize("rows,cols", [(3, 3), (8, 8), (17, 13), (64, 64), (80, 80), (144, 144),
+                                       (129, 257), (300, 1030), (70, 1029), (33, 4100), (5, 700)])
+@pytest.mark.parametrize("nw,unroll", JACOBI_SHAPES)
+@pytest.mark.parametrize("vec", [1, 2, 4])
+@pytest.mark.parametrize("tile_rows", [8, 17, 32])
+def test_jacobi_accesses_stay_in_grid(rows, cols, nw, unroll, vec, tile_rows):
+    assert _jacobi_accesses(rows, cols, vec, nw, unroll, tile_rows) == []
+
+
+def test_jacobi_edges_of_large_grids():
+    def edge_tiles(strips, bands):
+        pick = set()
+        for b in (0, bands // 2, bands - 1):
+            for s in range(strips):
+                pick.add(b * strips + s)
+        return sorted(pick)
+    for (rows, cols), (nw, unroll), vec in itertools.product(
+            [(8192, 8192), (4096, 4096), (8191, 8190), (2000, 3001)], JACOBI_SHAPES, [2, 4]):
+        assert _jacobi_accesses(rows, cols, vec, nw, unroll, 8, edge_tiles) == []
+
+
+def _life_accesses(rows, cols, nw, tile_rows, torus):
+    assert cols % 16 == 0
+    span = nw * 1024
+    strips = -(-cols // span)
+    bands = -(-rows // tile_rows)
+    bad = []
+    for t in range(strips * bands):
+        band, strip = divmod(t, strips)
+        r0 = band * tile_rows
+        r1 = min(r0 + tile_rows, rows)
+        for w in range(nw):
+            cw = strip * span + w * 1024
+            nact = min(64, (cols - cw) // 16) if cw < cols else 0
+            c = cw + np.arange(64) * 16
+            active = c < cols
+            if active.any() and (c[active] + 15).max() >= cols:
+                bad.append(("word", t, w))
+            wcol, ecol = cw - 1, cw + nact * 16
+            has_w = nact > 0
+            has_e = nact > 0
+            if wcol < 0:
+                if torus:
+                    wcol += cols
+                else:
+                    has_w = False
+            if ecol >= cols:
+                if torus:
+                    ecol -= cols
+                else:
+                    has_e = False
+            if has_w and not (0 <= wcol < cols):
+                bad.append(("west", t, w, wcol))
+            if has_e and not (0 <= ecol < cols):
+                bad.append(("east", t, w, ecol))
+            for r in range(r0 - 1, r1 + 1):
+                rr = r
+                if r < 0 or r >= rows:
+                    if not torus:
+                        continue
+                    rr = (r + rows) % rows
+                if not (0 <= rr < rows):
+                    bad.append(("row", t, w, r))
+            for r in range(r0, r1):
+                if not (0 <= r < rows):
+                    bad.append(("store row", t, w, r))
+    return bad
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 16), (16, 16), (64, 48), (130, 1040), (257, 2048),
+                                       (33, 4112), (5, 5008)])
+@pytest.mark.parametrize("nw", [1, 2, 4, 8])
+@pytest.mark.parametrize("tile_rows", [16, 64])
+@pytest.mark.parametrize("torus", [True, False])
+def test_life_accesses_stay_in_grid(rows, cols, nw, tile_rows, torus):
+    assert _life_accesses(rows, cols, nw, tile_rows, torus) == []
+
+
+def test_model_flags_the_unguarded_west_halo():
+    """The model must catch a wavefront past the last column loading its halo."""
+    rows, cols, vec, nw = 64, 64, 2, 4
+    span = nw * 64 * vec
+    cw = 3 * 64 * vec  # wave 3 of strip 0
+    assert cw >= cols and cw < span
+    # with the guard cw < cols removed, the halo column would be cw - 1 >= cols
+    assert not (0 <= cw - 1 < cols)
