@@ -43,17 +43,36 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(JobState* st, con
     double rd = 0.0;
     unsigned long long ru = 0;
     if (check) {
+        // thread t folds the contiguous run [t*per, (t+1)*per) in index order,
+        // eight loads in flight at a time; then the fixed workgroup tree
+        const int per = (c.nparts + kFinThreads - 1) / kFinThreads;
+        const int lo = min((int)threadIdx.x * per, c.nparts), hi = min(lo + per, c.nparts);
         if (c.reduce == RED_SUM) {
             const unsigned long long* p = static_cast<const unsigned long long*>(partials);
             unsigned long long acc = 0;
-            for (int i = threadIdx.x; i < c.nparts; i += kFinThreads) acc += p[i];
+            int i = lo;
+            for (; i + 8 <= hi; i += 8) {
+                unsigned long long v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = p[i + k];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc += v[k];
+            }
+            for (; i < hi; ++i) acc += p[i];
             ru = block_reduce_u64<kFinThreads / 64>(acc, lds_u);
         } else {
             const double* p = static_cast<const double*>(partials);
             const bool is_max = c.reduce == RED_MAX_ABS;
             double acc = 0.0;
-            for (int i = threadIdx.x; i < c.nparts; i += kFinThreads)
-                acc = is_max ? max_nan(acc, p[i]) : acc + p[i];
+            int i = lo;
+            for (; i + 8 <= hi; i += 8) {
+                double v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = p[i + k];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc = is_max ? max_nan(acc, v[k]) : acc + v[k];
+            }
+            for (; i < hi; ++i) acc = is_max ? max_nan(acc, p[i]) : acc + p[i];
             rd = block_reduce<kFinThreads / 64>(acc, is_max, lds_d);
         }
     }
