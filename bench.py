@@ -15,6 +15,11 @@ launch time measured with HIP events on the library's own stream (the job's
 device time over its sweep launches, so it also carries the small finalize
 kernels and launch gaps), against 8 TB/s.
 
+Other workloads (--workload): laplace (256^2 FP64, 2000 sweeps), life (16384^2
+u8 torus, 2000 generations), restore (4096^2 two-phase restoration, FP64 and
+FP32), served (a prefix of the mixed job stream through the batched engine in
+FP32 storage, against the plain per-grid FP64 path on the same jobs).
+
 --gpus N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -25,6 +30,7 @@ import json
 import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -34,15 +40,15 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("jacobi.hip", "tile_jacobi.hpp", "common.hpp", "kernels.hpp")) -> str:
     h = hashlib.sha256()
-    for f in ("jacobi.hip", "common.hpp", "kernels.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1609_04567_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str, launches_per_step: int):
+def measured_traffic(name: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None when the
     kernel source changed since they were taken."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -55,19 +61,338 @@ def measured_traffic(name: str, launches_per_step: int):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(n: int, sweeps: int):
-    """The oracle (plain C, OpenMP over rows) on a bounded prefix of the same job."""
-    import oracle as O
-    from paper_1609_04567_amd import inputs as I
+def base_line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def copy_probe(L, ctx, torch, dev):
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+    ms = L.lsr_probe_copy(ctx.handle, dst.data_ptr(), src.data_ptr(), nb, 20)
+    return round(2 * nb / (ms * 1e-3) / 1e9, 1)
+
+
+def roofline(alg_bytes_per_launch, per_launch_s, traffic):
+    achieved = alg_bytes_per_launch / per_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
+
+
+# ---------------------------------------------------------------------------
+def run_helmholtz(args, L, I, torch):
+    n, sweeps = args.n or 8192, args.sweeps or 5000
+    dev = "cuda:0"
     h = I.helmholtz_input(n)
+    g = torch.from_numpy(h.g).to(dev)
+    grids = [torch.zeros((n, n), dtype=torch.float64, device=dev)
+             for _ in range(args.steps + args.warmup)]
+    ustar = torch.from_numpy(h.ustar).to(dev)
+    cond = L.make_cond(L.LSR_COND_BELOW, 1e-9, 10)
+    ctx = L.Context(0)
+    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph, waves=args.waves,
+             unroll=args.unroll)
+    copy_gbs = copy_probe(L, ctx, torch, dev)
+
+    def step(t):
+        return ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, sweeps, L.LSR_BC_RING,
+                       env0=g, param=(h.alpha, h.h))
+
+    for k in range(args.warmup):
+        r = step(grids[k])
+        print(f"warmup {k}: n={r.iterations} device_ms={r.device_ms:.1f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, r = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
-                        reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10, max_iter=sweeps)
-    dt = time.perf_counter() - t0
-    lups = (n - 2) ** 2 * r.n
-    return {"value": round(lups / dt / 1e9, 4), "unit": "GLUP/s", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"first {sweeps} sweeps of the {n}x{n} job ({dt:.1f} s of CPU time)"}
+    results = [step(grids[args.warmup + k]) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for k, r in enumerate(results):
+        print(f"step {k}: n={r.iterations} device_ms={r.device_ms:.1f}", file=sys.stderr, flush=True)
+        assert r.status == L.LSR_OK and r.iterations == sweeps
+    value = (n - 2) ** 2 * sweeps * args.steps / wall / 1e9
+    # closed form of the last step, u^n = c*(1 - mu^n) u*, with 1 - mu written
+    # without cancellation (it is 7.7e-8 at N = 8192)
+    hh = 1.0 / (n - 1)
+    s2 = math.sin(math.pi * hh / 2) ** 2
+    one_m_mu = (8.0 * s2 + hh * hh) / (4.0 + hh * hh)
+    lam = 8.0 / (hh * hh) * s2
+    coef = (2 * math.pi ** 2 + 1.0) / (lam + 1.0) * -math.expm1(sweeps * math.log1p(-one_m_mu))
+    err = float((grids[-1] - coef * ustar).abs().max() / (coef * ustar).abs().max())
+    dev_ms = sum(r.device_ms for r in results)
+    per_launch_s = dev_ms * 1e-3 / (sweeps * args.steps)
+    out = base_line("GLUP/s", round(value, 3), "GLUP/s", args.steps, args.warmup,
+                    round(wall / args.steps * 1e3, 3), "f64",
+                    {"workload": f"helmholtz-jacobi5 {n}x{n} fp64, L2 of update every 10 sweeps, "
+                                 f"stop <1e-9 or {sweeps} sweeps", "rows": n, "cols": n,
+                     "sweeps": sweeps, "check_every": 10, "parallelism": "single-gpu"})
+    out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s,
+                               measured_traffic(f"jacobi5_helmholtz_f64_{n}"))
+    out["copy_probe_gbs"] = copy_gbs
+    out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
+                       "last_l2_update": results[-1].last_reduce}
+    if not args.no_cpu:
+        import oracle as O
+        t0 = time.perf_counter()
+        _, r = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                            reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10,
+                            max_iter=args.cpu_sweeps)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round((n - 2) ** 2 * r.n / dt / 1e9, 4), "unit": "GLUP/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"first {r.n} sweeps of the {n}x{n} job ({dt:.1f} s)"}
+    ctx.close()
+    return out
+
+
+def run_laplace(args, L, I, torch):
+    import numpy as np
+    n, sweeps = args.n or 256, args.sweeps or 2000
+    a = I.laplace_input(n, seed=1)
+    grids = [torch.from_numpy(a).to("cuda:0") for _ in range(args.steps + args.warmup)]
+    ctx = L.Context(0)
+    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph, waves=args.waves,
+             unroll=args.unroll)
+    cond = L.make_cond(L.LSR_COND_BELOW, 1e-6, 1)
+    step = lambda t: ctx.run(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA, cond, sweeps,
+                             L.LSR_BC_RING)
+    for k in range(args.warmup):
+        step(grids[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step(grids[args.warmup + k]) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert all(r.iterations == sweeps for r in results)
+    value = (n - 2) ** 2 * sweeps * args.steps / wall / 1e9
+    per_launch_s = sum(r.device_ms for r in results) * 1e-3 / (sweeps * args.steps)
+    out = base_line("GLUP/s", round(value, 4), "GLUP/s", args.steps, args.warmup,
+                    round(wall / args.steps * 1e3, 3), "f64",
+                    {"workload": f"laplace-jacobi5 {n}x{n} fp64, max|update| every sweep, "
+                                 f"stop <1e-6 or {sweeps}", "rows": n, "cols": n, "sweeps": sweeps})
+    out["sweeps_per_s"] = round(sweeps * args.steps / wall, 1)
+    out["roofline"] = roofline(16.0 * (n - 2) ** 2, per_launch_s, None)
+    out["roofline"]["note"] = "1 MiB working set: cache-resident and launch-bound; HBM % is context"
+    if not args.no_cpu:
+        import oracle as O
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        o, ro = O.jacobi_run(a, thr=1e-6, max_iter=sweeps)
+        dt = time.perf_counter() - t0
+        O.set_threads(0)
+        out["cpu_baseline"] = {"value": round((n - 2) ** 2 * ro.n / dt / 1e9, 4), "unit": "GLUP/s",
+                               "cores": 1, "kind": "oracle", "sample": f"the whole job ({dt:.2f} s)"}
+        out["accuracy"] = {"bit_identical_to_oracle": bool(np.array_equal(grids[-1].cpu().numpy(), o))}
+    ctx.close()
+    return out
+
+
+def run_life(args, L, I, torch):
+    import numpy as np
+    n, gens = args.n or 16384, args.sweeps or 2000
+    s = I.life_input(n, seed=3)
+    grids = [torch.from_numpy(s).to("cuda:0") for _ in range(args.steps + args.warmup)]
+    ctx = L.Context(0)
+    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph)
+    cond = L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10)
+    step = lambda t: ctx.run(t, L.LSR_ST_LIFE, L.LSR_RED_SUM, cond, gens, L.LSR_BC_TORUS)
+    for k in range(args.warmup):
+        step(grids[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [step(grids[args.warmup + k]) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lups = sum(n * n * r.iterations for r in results)
+    per_launch_s = sum(r.device_ms for r in results) * 1e-3 / sum(r.iterations for r in results)
+    out = base_line("GLUP/s", round(lups / wall / 1e9, 2), "GLUP/s", args.steps, args.warmup,
+                    round(wall / args.steps * 1e3, 3), "u8",
+                    {"workload": f"life-b3s23 {n}x{n} u8 torus, live count every generation, "
+                                 f"stop when unchanged for 10 or {gens}", "rows": n, "cols": n,
+                     "generations": gens})
+    out["roofline"] = roofline(2.0 * n * n, per_launch_s, None)
+    out["result"] = {"iterations": int(results[-1].iterations), "count": int(results[-1].last_count)}
+    if not args.no_cpu:
+        import oracle as O
+        k = 10
+        t0 = time.perf_counter()
+        O.life_run(s, cond=O.COND_NEVER, max_iter=k)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n * n * k / dt / 1e9, 4), "unit": "GLUP/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"first {k} generations ({dt:.1f} s)"}
+    ctx.close()
+    return out
+
+
+def run_restore(args, L, I, torch):
+    import numpy as np
+    n = args.n or 4096
+    rin = I.restore_input(n, seed=4, noise=0.4)
+    y = torch.from_numpy(rin.y).to("cuda:0")
+    ctx = L.Context(0)
+    out_runs = {}
+    for dtname, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        for k in range(args.warmup):
+            m, u = ctx.amf_detect(y, 19, dt)
+            ctx.run(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA, L.make_cond(L.LSR_COND_BELOW, 0.1, 1),
+                    200, L.LSR_BC_BOTTOM, env0=m, param=(100.0, 0.0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m, u = ctx.amf_detect(y, 19, dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = ctx.run(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA,
+                    L.make_cond(L.LSR_COND_BELOW, 0.1, 1), 200, L.LSR_BC_BOTTOM, env0=m,
+                    param=(100.0, 0.0))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        flagged = int(m.sum())
+        out_runs[dtname] = {"detect_ms": round((t1 - t0) * 1e3, 3),
+                            "restore_ms": round((t2 - t1) * 1e3, 3), "iterations": int(r.iterations),
+                            "flagged": flagged,
+                            "flagged_px_per_s": round(flagged * r.iterations / (t2 - t1), 1),
+                            "px_per_s": round(n * n * r.iterations / (t2 - t1), 1),
+                            "field": u.cpu().numpy().astype(np.float64)}
+    err = float(np.max(np.abs(out_runs["f32"]["field"] - out_runs["f64"]["field"])) /
+                np.max(np.abs(out_runs["f64"]["field"])))
+    for v in out_runs.values():
+        v.pop("field")
+    wall = (out_runs["f64"]["detect_ms"] + out_runs["f64"]["restore_ms"]) / 1e3
+    out = base_line("GLUP/s", round(n * n * out_runs["f64"]["iterations"] / wall / 1e9, 3), "GLUP/s",
+                    1, args.warmup, round(wall * 1e3, 3), "f64",
+                    {"workload": f"two-phase restoration {n}x{n} u8, 40% impulses, w_max 19, "
+                                 f"beta 100, stop max|change| < 0.1 or 200", "rows": n, "cols": n})
+    out["runs"] = out_runs
+    out["f32_vs_f64_max_rel"] = err
+    ctx.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+def _served_jobs(L, I, torch, count, f32):
+    """Tensors and arguments for the first `count` jobs of the mixed stream."""
+    import numpy as np
+    jobs = I.job_stream(count)
+    built = []
+    dt = np.float32 if f32 else np.float64
+    for j in jobs:
+        if j.kind == I.KIND_LAPLACE:
+            a = I.laplace_input(j.side, seed=j.seed)
+            t = torch.from_numpy(a.astype(dt)).to("cuda:0")
+            built.append((j, t, None, (L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                                       L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), 2000, L.LSR_BC_RING, ())))
+        elif j.kind == I.KIND_HELMHOLTZ:
+            h = I.helmholtz_input(j.side)
+            t = torch.from_numpy(h.u0.astype(dt)).to("cuda:0")
+            g = torch.from_numpy(h.g.astype(dt)).to("cuda:0")
+            built.append((j, t, g, (L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                                    L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 5000, L.LSR_BC_RING,
+                                    (h.alpha, h.h))))
+        else:
+            s = I.life_input(j.side, seed=j.seed)
+            t = torch.from_numpy(s).to("cuda:0")
+            built.append((j, t, None, (L.LSR_ST_LIFE, L.LSR_RED_SUM,
+                                       L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10), 2000,
+                                       L.LSR_BC_TORUS, ())))
+    return built
+
+
+def run_served(args, L, I, torch):
+    import numpy as np
+    count = args.jobs
+    t0 = time.perf_counter()
+    f32_jobs = _served_jobs(L, I, torch, count, True)
+    print(f"built {count} FP32 jobs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    originals = [t.clone() for (_, t, _, _) in f32_jobs]
+
+    def reset():
+        for (_, t, _, _), o in zip(f32_jobs, originals):
+            t.copy_(o)
+        torch.cuda.synchronize()
+
+    bctx = L.Context(0, batched=True)
+
+    def submit(entry):
+        j, t, g, (st, red, cond, mi, bc, param) = entry
+        return bctx.submit(t, st, red, cond, mi, bc, env0=g, param=param)
+
+    # closed loop: every job present at t = 0
+    reset()
+    t0 = time.perf_counter()
+    ids = [submit(e) for e in f32_jobs]
+    res = [bctx.result(i) for i in ids]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sat = count / wall
+    lat = np.array([r.latency_ms for r in res])
+    lups = sum((e[0].side - (0 if e[0].kind == I.KIND_LIFE else 2)) ** 2 * r.iterations
+               for e, r in zip(f32_jobs, res))
+    print(f"batched closed loop: {sat:.2f} jobs/s", file=sys.stderr, flush=True)
+    f32_fields = [t.clone() for (_, t, _, _) in f32_jobs]
+
+    # open loop: Poisson arrivals at 0.8 x the closed-loop rate
+    reset()
+    rate = 0.8 * sat
+    arrivals = I.poisson_arrivals([e[0] for e in f32_jobs], rate)
+    ids2 = [None] * count
+
+    def feeder():
+        start = time.perf_counter()
+        for k, e in enumerate(f32_jobs):
+            d = start + arrivals[k] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ids2[k] = submit(e)
+
+    th = threading.Thread(target=feeder)
+    t0 = time.perf_counter()
+    th.start()
+    th.join()
+    res2 = [bctx.result(i) for i in ids2]
+    wall2 = time.perf_counter() - t0
+    lat2 = np.array([r.latency_ms for r in res2])
+    bctx.close()
+
+    # plain FP64 path: one grid per launch sequence, jobs one after another
+    del originals
+    f64_jobs = _served_jobs(L, I, torch, count, False)
+    pctx = L.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res3 = []
+    for j, t, g, (st, red, cond, mi, bc, param) in f64_jobs:
+        res3.append(pctx.run(t, st, red, cond, mi, bc, env0=g, param=param))
+    torch.cuda.synchronize()
+    wall3 = time.perf_counter() - t0
+    pctx.close()
+    # accuracy of every FP32 result against the FP64 path (bit-identical to the
+    # oracle in the parity tests); Life must be bit-exact
+    worst, count_match = 0.0, 0
+    for (e, _, _, _), x32, (_, x64, _, _), r32, r64 in zip(f32_jobs, f32_fields, f64_jobs, res, res3):
+        count_match += int(r32.iterations == r64.iterations)
+        if e.kind == I.KIND_LIFE:
+            assert bool((x32 == x64).all()), "life result differs"
+        else:
+            d = float((x32.double() - x64).abs().max() / x64.abs().max().clamp_min(1e-300))
+            worst = max(worst, d)
+    out = base_line("jobs/s", round(sat, 3), "jobs/s", 1, 0, round(wall * 1e3, 1), "f32",
+                    {"workload": f"served mixed stream, first {count} jobs (60% Laplace, 25% "
+                                 "Helmholtz, 15% Life; side log-uniform 128..4096), FP32 storage "
+                                 "with FP64 reduce, batched engine", "jobs": count})
+    out["batched_glup_s"] = round(lups / wall / 1e9, 2)
+    out["latency_closed_loop_ms"] = {"p50": round(float(np.percentile(lat, 50)), 2),
+                                     "p99": round(float(np.percentile(lat, 99)), 2)}
+    out["poisson"] = {"rate_jobs_s": round(rate, 3), "wall_s": round(wall2, 3),
+                      "p50_ms": round(float(np.percentile(lat2, 50)), 2),
+                      "p99_ms": round(float(np.percentile(lat2, 99)), 2)}
+    out["plain_fp64_jobs_s"] = round(count / wall3, 3)
+    out["speedup_vs_plain_fp64"] = round(sat / (count / wall3), 3)
+    out["accuracy"] = {"f32_vs_f64_max_rel": worst, "iteration_counts_equal": count_match,
+                       "jobs": count}
+    return out
 
 
 def main():
@@ -75,13 +400,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sweeps", type=int, default=5000)
+    ap.add_argument("--workload", default="helmholtz",
+                    choices=["helmholtz", "laplace", "life", "restore", "served"])
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--sweeps", type=int, default=0)
+    ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--cpu-sweeps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--unroll", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
@@ -93,79 +423,9 @@ def main():
     import paper_1609_04567_amd as L
     from paper_1609_04567_amd import inputs as I
 
-    n, sweeps = args.n, args.sweeps
-    dev = "cuda:0"
-    h = I.helmholtz_input(n)
-    g = torch.from_numpy(h.g).to(dev)
-    grids = [torch.zeros((n, n), dtype=torch.float64, device=dev)
-             for _ in range(args.steps + args.warmup)]
-    ustar = torch.from_numpy(h.ustar).to(dev)
-    cond = L.make_cond(L.LSR_COND_BELOW, 1e-9, 10)
-    ctx = L.Context(0)
-    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph)
-
-    # measured HBM ceiling (plain copy), for context
-    nb = 1 << 30
-    src = torch.empty(nb, dtype=torch.uint8, device=dev)
-    dst = torch.empty(nb, dtype=torch.uint8, device=dev)
-    copy_ms = L.lsr_probe_copy(ctx.handle, dst.data_ptr(), src.data_ptr(), nb, 20)
-    copy_gbs = 2 * nb / (copy_ms * 1e-3) / 1e9
-    del src, dst
-
-    def step(t):
-        return ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, sweeps, L.LSR_BC_RING,
-                       env0=g, param=(h.alpha, h.h))
-
-    for k in range(args.warmup):
-        r = step(grids[k])
-        print(f"warmup {k}: n={r.iterations} device_ms={r.device_ms:.1f}", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [step(grids[args.warmup + k]) for k in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for k, r in enumerate(results):
-        print(f"step {k}: n={r.iterations} device_ms={r.device_ms:.1f}", file=sys.stderr, flush=True)
-        assert r.status == L.LSR_OK and r.iterations == sweeps
-
-    lup_step = (n - 2) ** 2 * sweeps
-    value = lup_step * args.steps / wall / 1e9
-    # closed form check of the last step (u^n = c*(1 - mu^n) u*)
-    # (1 - mu written without cancellation; at N = 8192 it is 7.7e-8)
-    hh = 1.0 / (n - 1)
-    s2 = math.sin(math.pi * hh / 2) ** 2
-    one_m_mu = (8.0 * s2 + hh * hh) / (4.0 + hh * hh)
-    lam = 8.0 / (hh * hh) * s2
-    coef = (2 * math.pi ** 2 + 1.0) / (lam + 1.0) * -math.expm1(sweeps * math.log1p(-one_m_mu))
-    last = grids[-1]
-    err = float((last - coef * ustar).abs().max() / (coef * ustar).abs().max())
-
-    dev_ms = sum(r.device_ms for r in results)
-    launches = sweeps * args.steps
-    per_launch_s = dev_ms * 1e-3 / launches
-    alg_bytes = 24.0 * (n - 2) ** 2
-    achieved = alg_bytes / per_launch_s / 1e9
-    traffic = measured_traffic("jacobi5_helmholtz_f64_8192", launches)
-    out = {
-        "metric": "GLUP/s", "value": round(value, 3), "unit": "GLUP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "helmholtz-jacobi5 8192x8192 fp64, L2 of update every 10 sweeps, "
-                               "stop <1e-9 or 5000 sweeps", "rows": n, "cols": n,
-                   "sweeps": sweeps, "check_every": 10, "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic},
-        "copy_probe_gbs": round(copy_gbs, 1),
-        "accuracy": {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
-                     "last_l2_update": results[-1].last_reduce},
-    }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sweeps)
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    fn = {"helmholtz": run_helmholtz, "laplace": run_laplace, "life": run_life,
+          "restore": run_restore, "served": run_served}[args.workload]
+    print(json.dumps(fn(args, L, I, torch)), flush=True)
 
 
 if __name__ == "__main__":

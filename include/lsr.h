@@ -113,9 +113,23 @@ typedef struct {
     double param[4];        /* stencil parameters, see lsr_stencil_id */
 } lsr_grid;
 
+/*
+ * LSR_FLAG_BATCHED: the context runs the batched engine (continuous batching of
+ * many jobs, the stream-of-tasks form of Sect. 3.2/4): lsr_run queues the job and
+ * returns; an engine thread admits queued jobs in arrival order as soon as the
+ * pool can hold their scratch within the HBM budget, advances every admitted job
+ * by one sweep per round (one launch per kernel family for the sweeps of all
+ * jobs, one launch for all their final reduces and conditions), and retires jobs
+ * as they stop, freeing their memory for the next arrivals. A job's tile shape and
+ * reduce order depend only on its own shape, so its result is the same alone and
+ * in any mix. Supported: LAPLACE5, HELMHOLTZ5 (F64 or F32) and LIFE; RESTORE is
+ * EINVAL on a batched context.
+ */
+#define LSR_FLAG_BATCHED 1u
+
 typedef struct {
     int32_t device;            /* HIP device ordinal */
-    uint32_t flags;            /* reserved, 0 */
+    uint32_t flags;            /* LSR_FLAG_* */
     void *stream;              /* hipStream_t the caller orders against (NULL = null stream) */
     uint64_t hbm_budget_bytes; /* cap on library scratch; 0 = 90% of free device memory */
 } lsr_config;
@@ -129,7 +143,10 @@ typedef struct {
     int32_t stable_run;     /* consecutive unchanged checks at the stop (Life) */
     int32_t reserved;
     int64_t checks;         /* number of reduce + condition evaluations */
-    double device_ms;       /* device time from the job's first to its last kernel */
+    double device_ms;       /* device time from the job's first to its last kernel (batched: from
+                               admission to retirement, shared with the other jobs of the batch) */
+    double queue_ms;        /* host time from lsr_run to the start of the job's device work */
+    double latency_ms;      /* host time from lsr_run until the host saw the job end */
 } lsr_job_result;
 
 /* Tuning overrides; 0 in a field means "choose automatically". */

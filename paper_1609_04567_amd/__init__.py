@@ -9,7 +9,7 @@ from __future__ import annotations
 
 from ._native import (  # noqa: F401
     LSR_BC_BOTTOM, LSR_BC_RING, LSR_BC_TORUS, LSR_COND_BELOW, LSR_COND_NEVER,
-    LSR_COND_STABLE_FOR, LSR_EBUSY, LSR_ECANCELED, LSR_EDEVICE, LSR_EINVAL, LSR_ENOMEM,
+    LSR_COND_STABLE_FOR, LSR_FLAG_BATCHED, LSR_EBUSY, LSR_ECANCELED, LSR_EDEVICE, LSR_EINVAL, LSR_ENOMEM,
     LSR_ENOTFOUND, LSR_ENUMERIC, LSR_F32, LSR_F64, LSR_OK, LSR_RED_L2_DELTA,
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
@@ -40,11 +40,13 @@ def grid_from_tensor(t, bc: int, env0=None, param=()):
 class Context:
     """An lsr context on one device, ordered against a torch stream."""
 
-    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 0,
+                 batched: bool = False):
         import torch
         self.device = device
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        self.handle = lsr_create(device, self.stream.cuda_stream, hbm_budget_bytes)
+        self.handle = lsr_create(device, self.stream.cuda_stream, hbm_budget_bytes,
+                                 LSR_FLAG_BATCHED if batched else 0)
         self._keep = {}
 
     def close(self):

@@ -23,6 +23,7 @@ LSR_BC_RING, LSR_BC_TORUS, LSR_BC_BOTTOM = 0, 1, 2
 LSR_ST_LAPLACE5, LSR_ST_HELMHOLTZ5, LSR_ST_LIFE, LSR_ST_RESTORE = 1, 2, 3, 4
 LSR_RED_MAX_ABS_DELTA, LSR_RED_L2_DELTA, LSR_RED_SUM, LSR_RED_MEAN_ABS_DELTA = 1, 2, 3, 4
 LSR_COND_BELOW, LSR_COND_STABLE_FOR, LSR_COND_NEVER = 1, 2, 3
+LSR_FLAG_BATCHED = 1
 
 
 class lsr_grid(C.Structure):
@@ -44,7 +45,8 @@ class lsr_config(C.Structure):
 class lsr_job_result(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("last_reduce", C.c_double), ("last_count", C.c_uint64),
                 ("converged", C.c_int32), ("status", C.c_int32), ("stable_run", C.c_int32),
-                ("reserved", C.c_int32), ("checks", C.c_int64), ("device_ms", C.c_double)]
+                ("reserved", C.c_int32), ("checks", C.c_int64), ("device_ms", C.c_double),
+                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -111,8 +113,9 @@ def lsr_version() -> str:
     return lib().lsr_version().decode()
 
 
-def lsr_create(device: int = 0, stream: int | None = None, hbm_budget_bytes: int = 0) -> int:
-    cfg = lsr_config(device=device, flags=0, stream=stream or None,
+def lsr_create(device: int = 0, stream: int | None = None, hbm_budget_bytes: int = 0,
+               flags: int = 0) -> int:
+    cfg = lsr_config(device=device, flags=flags, stream=stream or None,
                      hbm_budget_bytes=hbm_budget_bytes)
     out = C.c_void_p()
     _check(lib().lsr_create(C.byref(cfg), C.byref(out)))

@@ -110,6 +110,97 @@ __device__ __forceinline__ unsigned long long block_reduce_u64(unsigned long lon
 }
 
 // ---------------------------------------------------------------------------
+// Final fold of per-tile partials (the reduce's last level): thread t folds the
+// contiguous run [t*per, (t+1)*per) in index order with eight loads in flight,
+// then the fixed workgroup tree. The order depends only on the partial count.
+// The result is valid in thread 0.
+// ---------------------------------------------------------------------------
+template <int NTHREADS>
+__device__ inline double fold_partials(const double* __restrict__ p, int n, bool is_max,
+                                       double* lds) {
+    const int per = (n + NTHREADS - 1) / NTHREADS;
+    const int lo = min((int)threadIdx.x * per, n), hi = min(lo + per, n);
+    double acc = 0.0;
+    int i = lo;
+    for (; i + 8 <= hi; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[i + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc = is_max ? max_nan(acc, v[k]) : acc + v[k];
+    }
+    for (; i < hi; ++i) acc = is_max ? max_nan(acc, p[i]) : acc + p[i];
+    return block_reduce<NTHREADS / 64>(acc, is_max, lds);
+}
+
+template <int NTHREADS>
+__device__ inline unsigned long long fold_partials_u64(const unsigned long long* __restrict__ p, int n,
+                                                       unsigned long long* lds) {
+    const int per = (n + NTHREADS - 1) / NTHREADS;
+    const int lo = min((int)threadIdx.x * per, n), hi = min(lo + per, n);
+    unsigned long long acc = 0;
+    int i = lo;
+    for (; i + 8 <= hi; i += 8) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[i + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+    }
+    for (; i < hi; ++i) acc += p[i];
+    return block_reduce_u64<NTHREADS / 64>(acc, lds);
+}
+
+// One evaluation of the condition at check sweep n1 (the -s variant's update and
+// test): r = max | sqrt(sum) | sum/(rows*cols) | count;
+//   BELOW:      stop when r < threshold
+//   STABLE_FOR: run = (count == prev) ? run + 1 : 0; prev = count; stop when run >= window
+//   an FP reduce that is NaN or Inf stops the loop with a numeric status;
+//   n1 == max_iter always stops.
+__device__ inline void apply_check(JobState& s, const LoopCtl& c, int64_t n1, double rsum,
+                                   unsigned long long rcount) {
+    s.checks += 1;
+    s.n = n1;
+    bool stop = false;
+    if (c.reduce == RED_SUM) {
+        s.count = rcount;
+        s.r = (double)rcount;
+        s.run = (rcount == s.prev) ? s.run + 1 : 0;
+        s.prev = rcount;
+        if (c.cond == COND_STABLE_FOR && s.run >= c.stable_window) stop = true;
+    } else {
+        double r = rsum;
+        if (c.reduce == RED_L2) r = sqrt(r);
+        else if (c.reduce == RED_MEAN_ABS) r = r / c.mean_div;
+        s.r = r;
+        if (isnan(r) || isinf(r)) {
+            s.status = ST_NUMERIC;
+            s.done = 1;
+        } else if (c.cond == COND_BELOW && r < c.threshold) {
+            stop = true;
+        }
+    }
+    if (stop) {
+        s.converged = 1;
+        s.done = 1;
+    }
+    if (n1 == c.max_iter) s.done = 1;
+}
+
+// Writes the state, and mirrors it into pinned host memory once the loop has
+// stopped (the only transition a host driver waits for; the mirror starts
+// zeroed, so no host write is needed on the other checks).
+__device__ inline void publish_state(JobState* st, JobState* mirror, const JobState& s) {
+    *st = s;
+    if (mirror && s.done) {
+        volatile int64_t* m = reinterpret_cast<volatile int64_t*>(mirror);
+        const int64_t* v = reinterpret_cast<const int64_t*>(&s);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m[i] = v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // XCD-aware tile order. Workgroups are dealt to the 8 XCDs of the MI355X round
 // robin by workgroup id; remapping id -> logical tile so that each XCD gets one
 // contiguous run of logical tiles keeps neighbouring tiles (and their shared

@@ -2,35 +2,19 @@
 // the per-tile partials with the condition test (the part the paper's runtime
 // runs on the host after every iteration, Fig. 2), and cancellation.
 //
-// The finalize kernel is one workgroup. It walks the partials in index order
-// (thread t takes t, t+1024, ... in that order), folds the 1024 lanes with the
-// fixed wave/workgroup tree, then thread 0 updates the state:
-//   r = max | sqrt(sum) | sum/(rows*cols) | count
-//   BELOW:      stop when r < threshold
-//   STABLE_FOR: run = (count == prev) ? run + 1 : 0; prev = count; stop when run >= window
-//   any FP reduce that is NaN or Inf stops the loop with a numeric status
-//   n == max_iter always stops.
-// The state is mirrored into pinned host memory so the host driver can see the
-// stop without a copy on the stream.
+// The finalize kernel is one 1024-thread workgroup: fold_partials walks the
+// partials in index order (contiguous runs per thread, then the fixed tree),
+// apply_check evaluates the condition and updates the -s state, and
+// publish_state mirrors the state into pinned host memory once the loop stops,
+// so the host driver sees the stop without a copy on the stream. The job state
+// here counts sweeps per enqueued chunk: n_base advances by `chunk` at the
+// chunk's last check, and a sweep's number is n_base + offset + 1.
 #include "kernels.hpp"
 
 namespace lsr {
 namespace {
 
 constexpr int kFinThreads = 1024;
-
-// The host mirror starts zeroed (done == 0) and is written only once the loop
-// has stopped: that is the only transition the host driver waits for, and it
-// keeps a write to host memory off every other check.
-__device__ void publish(JobState* st, JobState* mirror, const JobState& s) {
-    *st = s;
-    if (mirror && s.done) {
-        volatile int64_t* m = reinterpret_cast<volatile int64_t*>(mirror);
-        const int64_t* v = reinterpret_cast<const int64_t*>(&s);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) m[i] = v[i];
-    }
-}
 
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(JobState* st, const void* partials,
                                                                LoopCtl c, int j, JobState* mirror) {
@@ -43,71 +27,19 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(JobState* st, con
     double rd = 0.0;
     unsigned long long ru = 0;
     if (check) {
-        // thread t folds the contiguous run [t*per, (t+1)*per) in index order,
-        // eight loads in flight at a time; then the fixed workgroup tree
-        const int per = (c.nparts + kFinThreads - 1) / kFinThreads;
-        const int lo = min((int)threadIdx.x * per, c.nparts), hi = min(lo + per, c.nparts);
-        if (c.reduce == RED_SUM) {
-            const unsigned long long* p = static_cast<const unsigned long long*>(partials);
-            unsigned long long acc = 0;
-            int i = lo;
-            for (; i + 8 <= hi; i += 8) {
-                unsigned long long v[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = p[i + k];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) acc += v[k];
-            }
-            for (; i < hi; ++i) acc += p[i];
-            ru = block_reduce_u64<kFinThreads / 64>(acc, lds_u);
-        } else {
-            const double* p = static_cast<const double*>(partials);
-            const bool is_max = c.reduce == RED_MAX_ABS;
-            double acc = 0.0;
-            int i = lo;
-            for (; i + 8 <= hi; i += 8) {
-                double v[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = p[i + k];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) acc = is_max ? max_nan(acc, v[k]) : acc + v[k];
-            }
-            for (; i < hi; ++i) acc = is_max ? max_nan(acc, p[i]) : acc + p[i];
-            rd = block_reduce<kFinThreads / 64>(acc, is_max, lds_d);
-        }
+        if (c.reduce == RED_SUM)
+            ru = fold_partials_u64<kFinThreads>(static_cast<const unsigned long long*>(partials),
+                                                c.nparts, lds_u);
+        else
+            rd = fold_partials<kFinThreads>(static_cast<const double*>(partials), c.nparts,
+                                            c.reduce == RED_MAX_ABS, lds_d);
     }
     if (threadIdx.x != 0) return;
     JobState s = *st;
-    if (check) {
-        s.checks += 1;
-        s.n = n1;
-        bool stop = false;
-        if (c.reduce == RED_SUM) {
-            s.count = ru;
-            s.r = (double)ru;
-            s.run = (ru == s.prev) ? s.run + 1 : 0;
-            s.prev = ru;
-            if (c.cond == COND_STABLE_FOR && s.run >= c.stable_window) stop = true;
-        } else {
-            double r = rd;
-            if (c.reduce == RED_L2) r = sqrt(r);
-            else if (c.reduce == RED_MEAN_ABS) r = r / c.mean_div;
-            s.r = r;
-            if (isnan(r) || isinf(r)) {
-                s.status = ST_NUMERIC;
-                s.done = 1;
-            } else if (c.cond == COND_BELOW && r < c.threshold) {
-                stop = true;
-            }
-        }
-        if (stop) {
-            s.converged = 1;
-            s.done = 1;
-        }
-        if (n1 == c.max_iter) s.done = 1;
-    }
+    if (check) apply_check(s, c, n1, rd, ru);
+    // the chunk's last sweep is always a check sweep (chunk % check_every == 0)
     if (!s.done && j == c.chunk - 1) s.n_base += c.chunk;
-    publish(st, mirror, s);
+    publish_state(st, mirror, s);
 }
 
 __global__ __launch_bounds__(256) void init_state_kernel(JobState* st, const unsigned long long* parts,
@@ -139,7 +71,7 @@ __global__ void cancel_kernel(JobState* st, JobState* mirror) {
         s.done = 1;
         s.status = ST_CANCELED;
     }
-    publish(st, mirror, s);
+    publish_state(st, mirror, s);
 }
 
 // Live-cell count of a u8 grid: one partial per workgroup of 256 threads, each

@@ -1,0 +1,367 @@
+// Batched engine (LSR_FLAG_BATCHED): continuous batching of many
+// loop-of-stencil-reduce jobs on one GPU, the single-device form of the paper's
+// stream of tasks (Sect. 3.2; the streaming experiments of Sect. 4 reuse device
+// memory across items).
+//
+// One engine thread per context owns the device tables and the context stream:
+//   admit  - queued jobs, in arrival order, get their scratch (ping-pong
+//            partner, partials, 64 B state) from the pool while the HBM budget
+//            allows; their initialisation (partner copy, initial live count,
+//            state) is enqueued on the stream after the caller's prior work.
+//   upload - when the active set changed, the job descriptors and the work list
+//            (one entry per tile, grouped by kernel family, band-major per job so
+//            that neighbouring tiles land on one XCD) are copied to the device
+//            through double-buffered pinned staging.
+//   window - R rounds are enqueued; a round is one sweep launch per kernel
+//            family present plus one finalize launch for all jobs. R is chosen
+//            so a window is ~1.5 ms of device time; two windows stay in flight.
+//   scan   - after a window completes, jobs whose pinned mirror shows `done`
+//            are retired: an odd final sweep count costs one D2D copy back into
+//            the caller's grid, their scratch returns to the pool (every later
+//            use of a block is ordered after the copy on the same stream), and
+//            the next arrivals can be admitted into the freed memory.
+// Nothing here blocks on the device except the window and retirement events.
+#include "runtime_internal.hpp"
+
+using namespace lsr_rt;
+
+namespace {
+
+constexpr int kMaxBatch = 4096;          // active jobs (the pinned mirror slots)
+constexpr int64_t kMaxWork = 1 << 21;    // tiles of all active jobs
+constexpr int kPad = 8 * (lsr::kBatchKinds + 1);
+constexpr double kWindowUs = 1500.0;     // device time per window of rounds
+constexpr double kRoundOverheadUs = 12.0;
+constexpr int kMaxRounds = 64;
+constexpr int kWindowsInFlight = 2;
+
+}  // namespace
+
+lsr_status lsr_ctx::engine_setup() {
+    HIP_TRY(hipMalloc(&d_jobs, sizeof(lsr::BatchJob) * kMaxBatch));
+    HIP_TRY(hipMalloc(&d_work, sizeof(lsr::WorkItem) * (kMaxWork + kPad)));
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipHostMalloc((void**)&h_jobs[i], sizeof(lsr::BatchJob) * kMaxBatch, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&h_work[i], sizeof(lsr::WorkItem) * (kMaxWork + kPad),
+                              hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&stage_ev[i], hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(stage_ev[i], stream));
+    }
+    return LSR_OK;
+}
+
+void lsr_ctx::engine_teardown() {
+    (void)hipStreamSynchronize(stream);
+    for (int i = 0; i < 2; ++i) {
+        if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
+        if (h_jobs[i]) (void)hipHostFree(h_jobs[i]);
+        if (h_work[i]) (void)hipHostFree(h_work[i]);
+    }
+    if (d_jobs) (void)hipFree(d_jobs);
+    if (d_work) (void)hipFree(d_work);
+}
+
+// Called by lsr_run (caller thread): fills the job's descriptor from its shape
+// and queues it.
+lsr_status lsr_ctx::engine_submit(Job* j) {
+    const lsr_grid& g = j->grid;
+    const bool life = j->stencil == LSR_ST_LIFE;
+    const bool f32 = g.dtype == LSR_F32;
+    lsr::BatchJob& d = j->desc;
+    d = lsr::BatchJob{};
+    d.buf[0] = g.data;
+    d.env = g.env0;
+    d.rows = g.rows;
+    d.cols = g.cols;
+    d.pitch = g.pitch;
+    d.helm = j->stencil == LSR_ST_HELMHOLTZ5;
+    d.torus = g.bc == LSR_BC_TORUS;
+    d.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
+    uintptr_t align = reinterpret_cast<uintptr_t>(g.data);
+    if (d.helm) align |= reinterpret_cast<uintptr_t>(g.env0);
+    lsr::batch_geometry(d, life, f32, align);
+    lsr::LoopCtl& c = d.ctl;
+    c.max_iter = j->max_iter;
+    c.check_every = j->cond.check_every;
+    c.chunk = 1;
+    c.reduce = j->ctl.reduce;
+    c.cond = j->cond.kind;
+    c.stable_window = j->cond.stable_window;
+    c.nparts = d.tiles;
+    c.threshold = j->cond.threshold;
+    c.mean_div = (double)g.rows * (double)g.cols;
+    const size_t esz = dtype_size(g.dtype);
+    j->bytes = (size_t)g.rows * (size_t)g.pitch * esz;
+    j->nparts_alloc = std::max(d.tiles, life ? lsr::count_u8_parts(g.rows, g.cols) : 1);
+    const double per_cell = life ? 2.0 : (double)esz * (d.helm ? 3.0 : 2.0);
+    j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
+    if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");
+    return LSR_OK;
+}
+
+void lsr_ctx::engine_finish(Job* j, lsr_status st) {
+    std::lock_guard<std::mutex> lk(mu);
+    j->result.status = st;
+    j->status = st;
+    j->result.queue_ms = ms_between(j->t_submit, j->t_admit);
+    j->result.latency_ms = ms_between(j->t_submit, j->t_done);
+    j->phase = Phase::Finished;
+    cv_done.notify_all();
+}
+
+lsr_status lsr_ctx::engine_admit() {
+    while (true) {
+        Job* j = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (pending.empty() || (int)active.size() >= kMaxBatch || free_slots.empty()) return LSR_OK;
+            j = pending.front();
+        }
+        if (j->cancel.load()) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                pending.pop_front();
+            }
+            j->t_admit = j->t_done = Clock::now();
+            engine_finish(j, LSR_ECANCELED);
+            continue;
+        }
+        if (work_items + j->desc.tiles > kMaxWork) return LSR_OK;
+        void* partner = nullptr;
+        void* parts = nullptr;
+        void* st = nullptr;
+        lsr_status s = pool.alloc(j->bytes, &partner);
+        if (s == LSR_OK) s = pool.alloc((size_t)j->nparts_alloc * 8, &parts);
+        if (s == LSR_OK) s = pool.alloc(sizeof(lsr::JobState), &st);
+        if (s != LSR_OK) {
+            pool.release(partner);
+            pool.release(parts);
+            pool.release(st);
+            if (!active.empty() || !retiring.empty()) return LSR_OK;  // wait for memory
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                pending.pop_front();
+            }
+            j->error = g_last_error;
+            j->t_admit = j->t_done = Clock::now();
+            engine_finish(j, s);  // cannot fit even on an idle device
+            continue;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            pending.pop_front();
+            j->slot = free_slots.back();
+            free_slots.pop_back();
+            j->phase = Phase::Running;
+        }
+        active.push_back(j);  // from here on a device failure also finishes this job
+        work_items += j->desc.tiles;
+        j->buf[1] = partner;
+        j->partials = parts;
+        j->st = static_cast<lsr::JobState*>(st);
+        j->mirror_host = mirrors_host + j->slot;
+        j->mirror_dev = mirrors_dev + j->slot;
+        std::memset((void*)j->mirror_host, 0, sizeof(lsr::JobState));
+        lsr::BatchJob& d = j->desc;
+        d.buf[1] = partner;
+        d.st = j->st;
+        d.partials = parts;
+        d.mirror = j->mirror_dev;
+        const lsr_grid& g = j->grid;
+        const size_t esz = dtype_size(g.dtype);
+        HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
+        HIP_TRY(hipEventRecord(j->ev_begin, stream));
+        if (j->stencil == LSR_ST_LIFE) {
+            int np = 0;
+            HIP_TRY(lsr::launch_count_u8(static_cast<const uint8_t*>(g.data), g.rows, g.cols, g.pitch,
+                                         parts, &np, stream));
+            HIP_TRY(lsr::launch_init_state(j->st, parts, np, stream));
+        } else {
+            HIP_TRY(hipMemcpy2DAsync(partner, g.pitch * esz, g.data, g.pitch * esz, g.cols * esz,
+                                     g.rows, hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream));
+        }
+        j->t_admit = Clock::now();
+        tables_dirty = true;
+    }
+}
+
+lsr_status lsr_ctx::engine_upload() {
+    const int s = stage;
+    HIP_TRY(hipEventSynchronize(stage_ev[s]));
+    lsr::BatchJob* hj = h_jobs[s];
+    lsr::WorkItem* hw = h_work[s];
+    const int n = (int)active.size();
+    for (int i = 0; i < n; ++i) hj[i] = active[i]->desc;
+    int64_t pos = 0;
+    for (int k = 1; k <= lsr::kBatchKinds; ++k) {
+        seg_off[k] = (int)pos;
+        for (int i = 0; i < n; ++i) {
+            if (hj[i].kind != k) continue;
+            for (int t = 0; t < hj[i].tiles; ++t) hw[pos++] = lsr::WorkItem{i, t};
+        }
+        while ((pos - seg_off[k]) % lsr::kXcds) hw[pos++] = lsr::WorkItem{-1, 0};
+        seg_len[k] = (int)(pos - seg_off[k]);
+    }
+    if (n > 0) HIP_TRY(hipMemcpyAsync(d_jobs, hj, sizeof(lsr::BatchJob) * n, hipMemcpyHostToDevice, stream));
+    if (pos > 0) HIP_TRY(hipMemcpyAsync(d_work, hw, sizeof(lsr::WorkItem) * pos, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(stage_ev[s], stream));
+    stage ^= 1;
+    tables_dirty = false;
+    return LSR_OK;
+}
+
+lsr_status lsr_ctx::engine_window() {
+    double round_us = kRoundOverheadUs;
+    for (Job* j : active) round_us += j->est_us;
+    const int rounds = (int)std::min<double>(kMaxRounds, std::max(1.0, std::floor(kWindowUs / round_us)));
+    const int n = (int)active.size();
+    for (int r = 0; r < rounds; ++r) {
+        for (int k = 1; k <= lsr::kBatchKinds; ++k) {
+            if (seg_len[k] == 0) continue;
+            HIP_TRY(lsr::launch_batch_sweep(d_jobs, d_work + seg_off[k], k, seg_len[k], stream));
+        }
+        HIP_TRY(lsr::launch_batch_finalize(d_jobs, n, stream));
+    }
+    return LSR_OK;
+}
+
+void lsr_ctx::engine_scan() {
+    std::vector<Job*> keep;
+    keep.reserve(active.size());
+    for (Job* j : active) {
+        volatile lsr::JobState* m = j->mirror_host;
+        if (!m->done) {
+            keep.push_back(j);
+            continue;
+        }
+        lsr::JobState fin;
+        std::memcpy(&fin, (const void*)m, sizeof fin);
+        const lsr_grid& g = j->grid;
+        const size_t esz = dtype_size(g.dtype);
+        hipError_t e = hipSuccess;
+        if (fin.n & 1)
+            e = hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipEventRecord(j->ev_end, stream);
+        lsr_job_result& r = j->result;
+        r.iterations = fin.n;
+        r.last_reduce = fin.r;
+        r.last_count = fin.count;
+        r.converged = fin.converged;
+        r.stable_run = fin.run;
+        r.checks = fin.checks;
+        r.status = fin.status == lsr::ST_NUMERIC ? LSR_ENUMERIC
+                 : fin.status == lsr::ST_CANCELED ? LSR_ECANCELED : LSR_OK;
+        if (e != hipSuccess) {
+            j->error = hipGetErrorString(e);
+            r.status = LSR_EDEVICE;
+        }
+        pool.release(j->buf[1]);
+        pool.release(j->partials);
+        pool.release(j->st);
+        j->buf[1] = j->partials = nullptr;
+        j->st = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            free_slots.push_back(j->slot);
+            j->slot = -1;
+        }
+        work_items -= j->desc.tiles;
+        retiring.push_back(j);
+        tables_dirty = true;
+    }
+    active.swap(keep);
+}
+
+void lsr_ctx::engine_poll_retiring(bool block) {
+    std::vector<Job*> keep;
+    for (Job* j : retiring) {
+        hipError_t e = block ? hipEventSynchronize(j->ev_end) : hipEventQuery(j->ev_end);
+        if (e == hipErrorNotReady) {
+            keep.push_back(j);
+            continue;
+        }
+        j->t_done = Clock::now();
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, j->ev_begin, j->ev_end);
+        j->result.device_ms = ms;
+        lsr_status st = (lsr_status)j->result.status;
+        if (e != hipSuccess) {
+            j->error = hipGetErrorString(e);
+            st = LSR_EDEVICE;
+        }
+        engine_finish(j, st);
+        block = false;  // one blocking wait per call is enough to make progress
+    }
+    retiring.swap(keep);
+}
+
+void lsr_ctx::serve() {
+    (void)hipSetDevice(device);
+    std::deque<hipEvent_t> inflight;
+    std::string fatal;
+    while (true) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            const bool idle = pending.empty() && active.empty() && retiring.empty() && inflight.empty();
+            if (idle) {
+                if (stopping) break;
+                cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
+                if (pending.empty()) continue;
+            }
+        }
+        lsr_status s = engine_admit();
+        for (Job* j : active) {
+            if (j->cancel.load() && !j->cancel_posted) {
+                j->cancel_posted = true;
+                if (lsr::launch_cancel(j->st, j->mirror_dev, stream) != hipSuccess)
+                    s = fail(LSR_EDEVICE, "cancel launch failed");
+            }
+        }
+        if (s == LSR_OK && tables_dirty) s = engine_upload();
+        if (s == LSR_OK && !active.empty()) {
+            s = engine_window();
+            if (s == LSR_OK) {
+                hipEvent_t ev = get_event();
+                if (!ev || hipEventRecord(ev, stream) != hipSuccess) s = fail(LSR_EDEVICE, "event record failed");
+                else inflight.push_back(ev);
+            }
+        }
+        if (s == LSR_OK && (inflight.size() >= (size_t)kWindowsInFlight || (active.empty() && !inflight.empty()))) {
+            hipEvent_t ev = inflight.front();
+            inflight.pop_front();
+            hipError_t e = hipEventSynchronize(ev);
+            put_event(ev);
+            if (e != hipSuccess) s = fail(LSR_EDEVICE, "window: %s", hipGetErrorString(e));
+            else engine_scan();
+        }
+        if (s == LSR_OK) {
+            const bool nothing_else = active.empty() && inflight.empty();
+            engine_poll_retiring(nothing_else && !retiring.empty());
+        }
+        if (s != LSR_OK && s != LSR_EBUSY) {
+            // a device failure ends every job of the context
+            fatal = g_last_error;
+            (void)hipStreamSynchronize(stream);
+            std::vector<Job*> all(active.begin(), active.end());
+            all.insert(all.end(), retiring.begin(), retiring.end());
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                all.insert(all.end(), pending.begin(), pending.end());
+                pending.clear();
+            }
+            active.clear();
+            retiring.clear();
+            for (Job* j : all) {
+                j->error = fatal;
+                j->t_done = Clock::now();
+                engine_finish(j, LSR_EDEVICE);
+            }
+        }
+    }
+    for (hipEvent_t ev : inflight) {
+        (void)hipEventSynchronize(ev);
+        put_event(ev);
+    }
+}

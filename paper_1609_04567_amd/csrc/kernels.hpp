@@ -67,6 +67,47 @@ hipError_t launch_restore(const RestoreArgs& a, const SweepGeom& g, JobState* st
 hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64_t pitch,
                              int w_max, uint8_t* mask, void* u_init, int u_dtype, hipStream_t s);
 
+// Batched execution ----------------------------------------------------------
+// Kernel family of one job inside a batch; every batch kernel uses 256-thread
+// workgroups (4 wavefronts).
+enum BatchKind : int32_t {
+    BK_JAC_F64_V2 = 1,   // FP64 Jacobi, 16-byte vector path
+    BK_JAC_F64_V1 = 2,   // FP64 Jacobi, scalar path (unaligned / odd pitch)
+    BK_JAC_F32_V4 = 3,   // FP32 Jacobi, vector path
+    BK_JAC_F32_V1 = 4,   // FP32 Jacobi, scalar path
+    BK_LIFE_SWAR = 5,    // Life, 16 cells per lane
+    BK_LIFE_GEN = 6      // Life, one cell per thread
+};
+
+// Device descriptor of one job of a batch. The job's completed-sweep count n
+// lives in its JobState; sweep n+1 reads buf[n % 2] and writes buf[(n+1) % 2].
+struct BatchJob {
+    const void* buf[2];
+    const void* env;       // Helmholtz g, or null
+    JobState* st;
+    void* partials;        // one 8-byte partial per tile
+    JobState* mirror;      // device pointer of the pinned host mirror
+    int64_t rows, cols, pitch;
+    double rd;
+    LoopCtl ctl;
+    int32_t kind, helm, torus, strips, tiles, tile_rows;
+};
+
+struct WorkItem {
+    int32_t job;   // index into the batch's job table, -1 = idle padding
+    int32_t tile;  // tile of that job
+};
+
+// Tile geometry a job gets inside a batch: a function of its shape, dtype and
+// buffer alignment only, so its reduce order is the same alone and in any mix.
+void batch_geometry(BatchJob& j, int stencil_kind_life, int f32, uintptr_t align_bits);
+constexpr int kBatchKinds = 6;
+// One launch per kernel family: `work` points at that family's segment of the
+// work list (nwork_padded entries, a multiple of 8, idle entries have job -1).
+hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
+                              int nwork_padded, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchJob* jobs, int njobs, hipStream_t s);
+
 // HBM copy probe: bytes must be a multiple of 16, buffers 16-byte aligned.
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 

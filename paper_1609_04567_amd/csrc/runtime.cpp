@@ -16,28 +16,9 @@
 //  * Each context owns one internal stream (default priority). A job starts
 //    after the work the caller had enqueued on its stream when lsr_run was
 //    called; lsr_result orders the caller's stream after the job's end.
-#include <hip/hip_runtime.h>
+#include "runtime_internal.hpp"
 
-#include <algorithm>
-#include <atomic>
-#include <cmath>
-#include <condition_variable>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <deque>
-#include <map>
-#include <memory>
-#include <mutex>
-#include <string>
-#include <thread>
-#include <unordered_map>
-#include <vector>
-
-#include "kernels.hpp"
-#include "lsr.h"
-
-namespace {
+namespace lsr_rt {
 
 thread_local std::string g_last_error = "";
 
@@ -51,166 +32,12 @@ lsr_status fail(lsr_status s, const char* fmt, ...) {
     return s;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess) return fail(LSR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace lsr_rt
 
-constexpr int kDepth = 3;          // chunks in flight per job
-constexpr int kMirrorSlots = 4096; // pinned state mirrors per context
-constexpr double kChunkTargetUs = 1500.0;
-constexpr int kMaxChunk = 512;
+using namespace lsr_rt;
 
-// ---------------------------------------------------------------------------
-// Caching pool. Sizes are rounded to a class (powers of two below 2 MiB,
-// multiples of 2 MiB above) and freed blocks are kept for reuse; live plus
-// cached bytes never exceed the budget (cached blocks are released first).
-// ---------------------------------------------------------------------------
-class Pool {
-  public:
-    void init(uint64_t budget) { budget_ = budget; }
-    static size_t size_class(size_t n) {
-        if (n < 4096) n = 4096;
-        if (n <= (2u << 20)) {
-            size_t p = 4096;
-            while (p < n) p <<= 1;
-            return p;
-        }
-        const size_t g = 2u << 20;
-        return (n + g - 1) / g * g;
-    }
-    lsr_status alloc(size_t n, void** out) {
-        std::lock_guard<std::mutex> lk(mu_);
-        const size_t sz = size_class(n);
-        auto it = free_.find(sz);
-        if (it != free_.end()) {
-            *out = it->second;
-            free_.erase(it);
-            cached_ -= sz;
-            live_[*out] = sz;
-            live_bytes_ += sz;
-            return LSR_OK;
-        }
-        if (live_bytes_ + cached_ + sz > budget_) trim_locked();
-        if (live_bytes_ + sz > budget_)
-            return fail(LSR_EBUSY, "scratch of %zu bytes exceeds the HBM budget (%llu live of %llu)",
-                        sz, (unsigned long long)live_bytes_, (unsigned long long)budget_);
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, sz);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            trim_locked();
-            e = hipMalloc(&p, sz);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(LSR_ENOMEM, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
-            }
-        }
-        live_[p] = sz;
-        live_bytes_ += sz;
-        *out = p;
-        return LSR_OK;
-    }
-    void release(void* p) {
-        if (!p) return;
-        std::lock_guard<std::mutex> lk(mu_);
-        auto it = live_.find(p);
-        if (it == live_.end()) return;
-        const size_t sz = it->second;
-        live_.erase(it);
-        live_bytes_ -= sz;
-        free_.emplace(sz, p);
-        cached_ += sz;
-    }
-    void trim() {
-        std::lock_guard<std::mutex> lk(mu_);
-        trim_locked();
-    }
-    void destroy() {
-        std::lock_guard<std::mutex> lk(mu_);
-        trim_locked();
-        for (auto& kv : live_) (void)hipFree(kv.first);
-        live_.clear();
-        live_bytes_ = 0;
-    }
-    uint64_t budget() const { return budget_; }
-
-  private:
-    void trim_locked() {
-        for (auto& kv : free_) (void)hipFree(kv.second);
-        free_.clear();
-        cached_ = 0;
-    }
-    std::mutex mu_;
-    std::multimap<size_t, void*> free_;
-    std::unordered_map<void*, size_t> live_;
-    uint64_t budget_ = 0, live_bytes_ = 0, cached_ = 0;
-};
-
-size_t dtype_size(int dt) { return dt == LSR_U8 ? 1 : dt == LSR_F32 ? 4 : 8; }
-
-enum class Phase { Queued, Running, Finished };
-
-struct Job {
-    lsr_job id = 0;
-    lsr_grid grid{};
-    int stencil = 0;
-    lsr_cond cond{};
-    int64_t max_iter = 0;
-    lsr::LoopCtl ctl{};
-    lsr::SweepGeom geom{};
-    void* buf[2] = {nullptr, nullptr};  // buf[0] = caller grid, buf[1] = partner
-    void* partials = nullptr;
-    lsr::JobState* st = nullptr;
-    int slot = -1;
-    lsr::JobState* mirror_host = nullptr;
-    lsr::JobState* mirror_dev = nullptr;
-    std::vector<char> fin_after;        // finalize after chunk offset j
-    hipEvent_t ev_user = nullptr, ev_begin = nullptr, ev_end = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool use_graph = true;
-    std::atomic<bool> cancel{false};
-    Phase phase = Phase::Queued;
-    lsr_job_result result{};
-    lsr_status status = LSR_OK;
-    std::string error;
-};
-
-}  // namespace
-
-struct lsr_ctx {
-    int device = 0;
-    hipStream_t user_stream = nullptr;
-    hipStream_t stream = nullptr;    // internal execution stream
-    hipStream_t capture = nullptr;   // stream used only for graph capture
-    Pool pool;
-    lsr_tuning tuning{};
-    lsr::JobState* mirrors_host = nullptr;
-    lsr::JobState* mirrors_dev = nullptr;
-    std::vector<int> free_slots;
-    std::vector<hipEvent_t> event_pool;
-
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Job*> queue;
-    std::unordered_map<lsr_job, std::unique_ptr<Job>> jobs;
-    lsr_job next_id = 1;
-    bool stopping = false;
-    std::thread driver;
-
-    void drive();
-    lsr_status run_job(Job* j);
-    lsr_status launch_sweep(Job* j, int off, hipStream_t s);
-    lsr_status enqueue_chunk_plain(Job* j, hipStream_t s);
-    hipEvent_t get_event();
-    void put_event(hipEvent_t e) { event_pool.push_back(e); }
-};
-
-namespace {
-
-lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* c, int64_t max_iter) {
+lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* c,
+                            int64_t max_iter) {
     if (!g || !c) return fail(LSR_EINVAL, "grid and cond must not be NULL");
     if (!g->data) return fail(LSR_EINVAL, "grid->data is NULL");
     if (g->pitch < g->cols) return fail(LSR_EINVAL, "pitch (%lld) < cols (%lld)", (long long)g->pitch, (long long)g->cols);
@@ -264,6 +91,8 @@ lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* 
         return fail(LSR_EINVAL, "threshold must be finite");
     return LSR_OK;
 }
+
+namespace {
 
 // Sweeps per chunk: a multiple of lcm(check_every, 2) that keeps a chunk near
 // kChunkTargetUs of device time at HBM speed, so the enqueue-ahead window stays
@@ -520,6 +349,7 @@ lsr_status lsr_check_args(const lsr_grid* grid, int32_t stencil_id, int32_t redu
 lsr_status lsr_create(const lsr_config* cfg, lsr_ctx** out) {
     if (!cfg || !out) return fail(LSR_EINVAL, "cfg and out must not be NULL");
     *out = nullptr;
+    if (cfg->flags & ~LSR_FLAG_BATCHED) return fail(LSR_EINVAL, "unknown flags 0x%x", cfg->flags);
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev == 0) return fail(LSR_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
@@ -542,8 +372,17 @@ lsr_status lsr_create(const lsr_config* cfg, lsr_ctx** out) {
     HIP_TRY(hipHostGetDevicePointer((void**)&c->mirrors_dev, c->mirrors_host, 0));
     std::memset(c->mirrors_host, 0, sizeof(lsr::JobState) * kMirrorSlots);
     for (int i = kMirrorSlots - 1; i >= 0; --i) c->free_slots.push_back(i);
+    c->batched = (cfg->flags & LSR_FLAG_BATCHED) != 0;
+    if (c->batched) {
+        lsr_status st = c->engine_setup();
+        if (st != LSR_OK) {
+            c->engine_teardown();
+            return st;
+        }
+    }
     lsr_ctx* raw = c.release();
-    raw->driver = std::thread([raw] { raw->drive(); });
+    if (raw->batched) raw->driver = std::thread([raw] { raw->serve(); });
+    else raw->driver = std::thread([raw] { raw->drive(); });
     *out = raw;
     return LSR_OK;
 }
@@ -569,6 +408,32 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     j->stencil = stencil_id;
     j->cond = *cond;
     j->max_iter = max_iter;
+    if (ctx->batched) {
+        if (stencil_id == LSR_ST_RESTORE)
+            return fail(LSR_EINVAL, "restoration jobs run on a plain (non-batched) context");
+        j->ctl.reduce = reduce_op;
+        lsr_status s = ctx->engine_submit(j.get());
+        if (s != LSR_OK) return s;
+        if (hipEventCreateWithFlags(&j->ev_user, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreate(&j->ev_begin) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+            hipEventRecord(j->ev_user, ctx->user_stream) != hipSuccess) {
+            if (j->ev_user) (void)hipEventDestroy(j->ev_user);
+            if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
+            if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+            return fail(LSR_EDEVICE, "event setup failed");
+        }
+        j->t_submit = j->t_admit = Clock::now();
+        Job* raw = j.get();
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            raw->id = ctx->next_id++;
+            ctx->jobs[raw->id] = std::move(j);
+            ctx->pending.push_back(raw);
+        }
+        ctx->cv_work.notify_one();
+        *job_out = raw->id;
+        return LSR_OK;
+    }
     lsr_tuning tun;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -762,6 +627,7 @@ lsr_status lsr_destroy(lsr_ctx* ctx) {
     if (ctx->driver.joinable()) ctx->driver.join();
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->batched) ctx->engine_teardown();
     for (auto& kv : ctx->jobs) {
         Job* j = kv.second.get();
         if (j->ev_user) (void)hipEventDestroy(j->ev_user);

@@ -1,0 +1,232 @@
+// Internal host-side definitions shared by the runtime (C ABI, plain driver)
+// and the batched engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lsr.h"
+
+namespace lsr_rt {
+
+// Thread-local text of the last error (lsr_last_error).
+extern thread_local std::string g_last_error;
+
+// Records a formatted message as the last error and returns the status.
+lsr_status fail(lsr_status s, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(LSR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kDepth = 3;          // chunks in flight per job
+constexpr int kMirrorSlots = 4096; // pinned state mirrors per context
+constexpr double kChunkTargetUs = 1500.0;
+constexpr int kMaxChunk = 512;
+
+// ---------------------------------------------------------------------------
+// Caching pool. Sizes are rounded to a class (powers of two below 2 MiB,
+// multiples of 2 MiB above) and freed blocks are kept for reuse; live plus
+// cached bytes never exceed the budget (cached blocks are released first).
+// ---------------------------------------------------------------------------
+class Pool {
+  public:
+    void init(uint64_t budget) { budget_ = budget; }
+    static size_t size_class(size_t n) {
+        if (n < 4096) n = 4096;
+        if (n <= (2u << 20)) {
+            size_t p = 4096;
+            while (p < n) p <<= 1;
+            return p;
+        }
+        const size_t g = 2u << 20;
+        return (n + g - 1) / g * g;
+    }
+    lsr_status alloc(size_t n, void** out) {
+        std::lock_guard<std::mutex> lk(mu_);
+        const size_t sz = size_class(n);
+        auto it = free_.find(sz);
+        if (it != free_.end()) {
+            *out = it->second;
+            free_.erase(it);
+            cached_ -= sz;
+            live_[*out] = sz;
+            live_bytes_ += sz;
+            return LSR_OK;
+        }
+        if (live_bytes_ + cached_ + sz > budget_) trim_locked();
+        if (live_bytes_ + sz > budget_)
+            return fail(LSR_EBUSY, "scratch of %zu bytes exceeds the HBM budget (%llu live of %llu)",
+                        sz, (unsigned long long)live_bytes_, (unsigned long long)budget_);
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim_locked();
+            e = hipMalloc(&p, sz);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(LSR_ENOMEM, "hipMalloc(%zu): %s", sz, hipGetErrorString(e));
+            }
+        }
+        live_[p] = sz;
+        live_bytes_ += sz;
+        *out = p;
+        return LSR_OK;
+    }
+    void release(void* p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = live_.find(p);
+        if (it == live_.end()) return;
+        const size_t sz = it->second;
+        live_.erase(it);
+        live_bytes_ -= sz;
+        free_.emplace(sz, p);
+        cached_ += sz;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked();
+    }
+    void destroy() {
+        std::lock_guard<std::mutex> lk(mu_);
+        trim_locked();
+        for (auto& kv : live_) (void)hipFree(kv.first);
+        live_.clear();
+        live_bytes_ = 0;
+    }
+    uint64_t budget() const { return budget_; }
+
+  private:
+    void trim_locked() {
+        for (auto& kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        cached_ = 0;
+    }
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> live_;
+    uint64_t budget_ = 0, live_bytes_ = 0, cached_ = 0;
+};
+
+inline size_t dtype_size(int dt) { return dt == LSR_U8 ? 1 : dt == LSR_F32 ? 4 : 8; }
+
+enum class Phase { Queued, Running, Finished };
+
+struct Job {
+    lsr_job id = 0;
+    lsr_grid grid{};
+    int stencil = 0;
+    lsr_cond cond{};
+    int64_t max_iter = 0;
+    lsr::LoopCtl ctl{};
+    lsr::SweepGeom geom{};
+    void* buf[2] = {nullptr, nullptr};  // buf[0] = caller grid, buf[1] = partner
+    void* partials = nullptr;
+    lsr::JobState* st = nullptr;
+    int slot = -1;
+    lsr::JobState* mirror_host = nullptr;
+    lsr::JobState* mirror_dev = nullptr;
+    std::vector<char> fin_after;        // finalize after chunk offset j
+    hipEvent_t ev_user = nullptr, ev_begin = nullptr, ev_end = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    std::atomic<bool> cancel{false};
+    Phase phase = Phase::Queued;
+    lsr_job_result result{};
+    lsr_status status = LSR_OK;
+    std::string error;
+    // batched engine
+    lsr::BatchJob desc{};               // device descriptor (valid once admitted)
+    size_t bytes = 0;                   // grid bytes (partner size)
+    int nparts_alloc = 0;               // partials allocated (tiles, or the initial count's)
+    double est_us = 0.0;                // estimated device time of one sweep
+    bool cancel_posted = false;         // a cancel kernel has been enqueued
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+};
+
+using Clock = std::chrono::steady_clock;
+inline double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// Argument validation shared by lsr_run and lsr_check_args.
+lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* c, int64_t max_iter);
+
+}  // namespace lsr_rt
+
+
+struct lsr_ctx {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t stream = nullptr;    // internal execution stream
+    hipStream_t capture = nullptr;   // stream used only for graph capture
+    lsr_rt::Pool pool;
+    lsr_tuning tuning{};
+    lsr::JobState* mirrors_host = nullptr;
+    lsr::JobState* mirrors_dev = nullptr;
+    std::vector<int> free_slots;
+    std::vector<hipEvent_t> event_pool;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<lsr_rt::Job*> queue;
+    std::unordered_map<lsr_job, std::unique_ptr<lsr_rt::Job>> jobs;
+    lsr_job next_id = 1;
+    bool stopping = false;
+    std::thread driver;
+
+    void drive();
+    lsr_status run_job(lsr_rt::Job* j);
+    lsr_status launch_sweep(lsr_rt::Job* j, int off, hipStream_t s);
+    lsr_status enqueue_chunk_plain(lsr_rt::Job* j, hipStream_t s);
+    hipEvent_t get_event();
+    void put_event(hipEvent_t e) { event_pool.push_back(e); }
+
+    // Batched engine (LSR_FLAG_BATCHED), see engine.cpp.
+    bool batched = false;
+    std::deque<lsr_rt::Job*> pending;   // submitted, waiting for admission (arrival order)
+    std::vector<lsr_rt::Job*> active;   // admitted, in the device tables
+    std::vector<lsr_rt::Job*> retiring; // stopped, waiting for their end event
+    lsr::BatchJob* d_jobs = nullptr;
+    lsr::WorkItem* d_work = nullptr;
+    lsr::BatchJob* h_jobs[2] = {nullptr, nullptr};
+    lsr::WorkItem* h_work[2] = {nullptr, nullptr};
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage = 0;
+    int seg_off[lsr::kBatchKinds + 1] = {};
+    int seg_len[lsr::kBatchKinds + 1] = {};
+    int64_t work_items = 0;
+    bool tables_dirty = false;
+    void serve();
+    lsr_status engine_submit(lsr_rt::Job* j);
+    lsr_status engine_admit();
+    lsr_status engine_upload();
+    lsr_status engine_window();
+    void engine_scan();
+    void engine_poll_retiring(bool block);
+    void engine_finish(lsr_rt::Job* j, lsr_status st);
+    lsr_status engine_setup();
+    void engine_teardown();
+};

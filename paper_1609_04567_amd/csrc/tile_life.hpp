@@ -1,0 +1,170 @@
+// Tile bodies of the Game of Life B3/S23 sweep (the elemental function of the
+// paper's Fig. 1) with the live-cell count fused in. Shared by the single-job
+// kernels (life.hip) and the batched kernel (batch.hip).
+//
+// SWAR tile (cols and pitch multiples of 16 bytes, 16-byte aligned buffers):
+// each lane owns 16 consecutive cells held as four 32-bit words, one byte per
+// cell. Per row it forms the byte-wise column sums V = up + mid + down (<= 3 per
+// byte, no carries), shifts V by one byte left and right (the missing edge
+// bytes come from the neighbouring lanes by cross-lane shuffles, or from a halo
+// byte loaded by the wavefront's edge lanes), and adds the three to get the 3x3
+// total T (<= 9). With the neighbour count being T - centre, the rule is
+//   alive' = (T == 3) || (T == 4 && alive)
+// evaluated on four bytes at once with a zero-byte test. The new word's
+// popcount is the cell count. Wavefronts stream down `tile_rows` rows.
+//
+// Generic tile (any shape/pitch): one thread per cell, nine byte loads.
+// Boundaries: torus wraps rows and columns; bottom treats outside cells as dead.
+#pragma once
+
+#include "common.hpp"
+
+namespace lsr {
+
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t x) {
+    // 0x01 in every byte that is non-zero, 0x00 elsewhere
+    return ((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) >> 7) & 0x01010101u;
+}
+
+__device__ __forceinline__ uint32_t zero_bytes_hi(uint32_t x) {
+    // 0x80 in every byte equal to zero, for byte values below 0x80
+    return ~(x + 0x7F7F7F7Fu) & 0x80808080u;
+}
+
+// Tile t (band-major over `strips` strips of NW*1024 columns); NW*64 threads.
+template <int NW, int U, bool NT>
+__device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, uint8_t* __restrict__ b,
+                                               int64_t rows, int64_t cols, int64_t pitch, int torus,
+                                               bool check, int t, int strips, int tile_rows,
+                                               unsigned long long* __restrict__ partials,
+                                               unsigned long long* lds) {
+    const int band = t / strips, strip = t - band * strips;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t cw = (int64_t)strip * (NW * 1024) + (int64_t)wave * 1024;
+    const int64_t c = cw + (int64_t)lane * 16;
+    const bool active = c < cols;
+    int nact = 0;
+    if (cw < cols) nact = (int)min<int64_t>(64, (cols - cw) / 16);
+    const int last = nact - 1;
+    int64_t wcol = cw - 1, ecol = cw + (int64_t)nact * 16;
+    bool has_w = (lane == 0) && nact > 0, has_e = (lane == last) && nact > 0;
+    if (wcol < 0) { if (torus) wcol += cols; else has_w = false; }
+    if (ecol >= cols) { if (torus) ecol -= cols; else has_e = false; }
+
+    const int64_t r0 = (int64_t)band * tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, rows);
+
+    auto load = [&](int64_t r, uint32_t (&w)[4], uint32_t& hw, uint32_t& he) {
+        w[0] = w[1] = w[2] = w[3] = 0;
+        hw = he = 0;
+        if (r < 0 || r >= rows) {
+            if (!torus) return;
+            r = (r + rows) % rows;
+        }
+        const uint8_t* p = a + r * pitch;
+        if (active) {
+            const uint4 x = *reinterpret_cast<const uint4*>(p + c);
+            w[0] = nz_bytes(x.x);
+            w[1] = nz_bytes(x.y);
+            w[2] = nz_bytes(x.z);
+            w[3] = nz_bytes(x.w);
+        }
+        if (has_w) hw = p[wcol] != 0;
+        if (has_e) he = p[ecol] != 0;
+    };
+
+    uint32_t up[4], mid[4], up_w, up_e, mid_w, mid_e;
+    load(r0 - 1, up, up_w, up_e);
+    load(r0, mid, mid_w, mid_e);
+    unsigned long long cnt = 0;
+
+    for (int64_t r = r0; r < r1; r += U) {
+        uint32_t dn[U][4], dn_w[U], dn_e[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (r + k < r1) load(r + k + 1, dn[k], dn_w[k], dn_e[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (r + k < r1) {
+                uint32_t V[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) V[m] = up[m] + mid[m] + dn[k][m];
+                const uint32_t vw_h = up_w + mid_w + dn_w[k];
+                const uint32_t ve_h = up_e + mid_e + dn_e[k];
+                uint32_t wv = __shfl_up(V[3], 1, 64) >> 24;
+                uint32_t ev = __shfl_down(V[0], 1, 64) & 0xFFu;
+                if (lane == 0) wv = vw_h;
+                if (lane == last) ev = ve_h;
+                uint32_t out[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t prev = (m > 0) ? (V[m - 1] >> 24) : wv;
+                    const uint32_t next = (m < 3) ? (V[m + 1] & 0xFFu) : ev;
+                    const uint32_t T = ((V[m] << 8) | prev) + V[m] + ((V[m] >> 8) | (next << 24));
+                    const uint32_t eq3 = zero_bytes_hi(T ^ 0x03030303u);
+                    const uint32_t eq4 = zero_bytes_hi(T ^ 0x04040404u);
+                    const uint32_t alive = eq3 | (eq4 & (mid[m] << 7));
+                    out[m] = alive >> 7;
+                    cnt += (unsigned)__popc(alive);
+                }
+                if (active) {
+                    typedef uint32_t W4 __attribute__((ext_vector_type(4)));
+                    W4 o;
+                    o[0] = out[0];
+                    o[1] = out[1];
+                    o[2] = out[2];
+                    o[3] = out[3];
+                    W4* dst = reinterpret_cast<W4*>(b + (r + k) * pitch + c);
+                    if (NT) __builtin_nontemporal_store(o, dst);
+                    else *dst = o;
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) { up[m] = mid[m]; mid[m] = dn[k][m]; }
+                up_w = mid_w; up_e = mid_e;
+                mid_w = dn_w[k]; mid_e = dn_e[k];
+            }
+        }
+    }
+    if (check) {
+        const unsigned long long v = block_reduce_u64<NW>(active ? cnt : 0ull, lds);
+        if (threadIdx.x == 0) partials[t] = v;
+    }
+}
+
+// Block blk of nblk 256-thread blocks covering the grid cell by cell.
+__device__ __forceinline__ void life_generic_tile(const uint8_t* __restrict__ a, uint8_t* __restrict__ b,
+                                                  int64_t rows, int64_t cols, int64_t pitch, int torus,
+                                                  bool check, int blk, int nblk,
+                                                  unsigned long long* __restrict__ partials,
+                                                  unsigned long long* lds) {
+    unsigned long long cnt = 0;
+    const int64_t total = rows * cols;
+    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < total;
+         i += (int64_t)nblk * 256) {
+        const int64_t r = i / cols, cc = i - r * cols;
+        int count = 0;
+        for (int di = -1; di <= 1; ++di) {
+            for (int dj = -1; dj <= 1; ++dj) {
+                if (di == 0 && dj == 0) continue;
+                int64_t rr = r + di, c2 = cc + dj;
+                if (torus) {
+                    rr = (rr + rows) % rows;
+                    c2 = (c2 + cols) % cols;
+                } else if (rr < 0 || c2 < 0 || rr >= rows || c2 >= cols) {
+                    continue;
+                }
+                count += a[rr * pitch + c2] != 0;
+            }
+        }
+        const int alive = a[r * pitch + cc] != 0;
+        const uint8_t v = (count == 3 || (alive && count == 2)) ? 1 : 0;
+        b[r * pitch + cc] = v;
+        cnt += v;
+    }
+    if (check) {
+        const unsigned long long v = block_reduce_u64<4>(cnt, lds);
+        if (threadIdx.x == 0) partials[blk] = v;
+    }
+}
+
+}  // namespace lsr

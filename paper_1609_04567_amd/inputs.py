@@ -69,15 +69,25 @@ def uniform01(seed: int, start: int, count: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Jacobi / Laplace: fixed boundary ring U[0,1), interior 0.
 # ---------------------------------------------------------------------------
+def uniform01_at(seed: int, index: np.ndarray) -> np.ndarray:
+    """Doubles in [0, 1) for arbitrary draw indices of the stream (counter-based)."""
+    s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    with np.errstate(over="ignore"):
+        x = _mix(s + (index.astype(np.uint64) + np.uint64(1)) * GAMMA)
+    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
 def laplace_input(rows: int, cols: int | None = None, seed: int = 1) -> np.ndarray:
     """FP64 grid; ring cells take draw (i*cols + j) of the stream, interior cells are 0.
 
     The side includes the ring, so only (rows-2) x (cols-2) cells are updated.
     """
     cols = rows if cols is None else cols
-    u = uniform01(seed, 0, rows * cols).reshape(rows, cols)
-    u[1:-1, 1:-1] = 0.0
-    return np.ascontiguousarray(u)
+    u = np.zeros((rows, cols), dtype=np.float64)
+    idx = np.arange(rows * cols, dtype=np.int64).reshape(rows, cols)
+    for sl in ((0, slice(None)), (rows - 1, slice(None)), (slice(None), 0), (slice(None), cols - 1)):
+        u[sl] = uniform01_at(seed, idx[sl])
+    return u
 
 
 def harmonic_input(rows: int, cols: int, kind: str) -> np.ndarray:

@@ -1,0 +1,187 @@
+"""GPU tests of the batched engine (continuous batching, LSR_FLAG_BATCHED).
+
+Every job of a mixed batch is compared with the oracle (FP64 Jacobi fields
+bit-identical, FP32 storage within 1e-5 of the FP64 oracle, Life bit-exact,
+iteration counts exact); a job's result is bit-identical alone and in a mix;
+jobs queue for memory under a small HBM budget and still finish correctly; a
+short job submitted while a long one runs finishes first.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1609_04567_amd as L
+from paper_1609_04567_amd import inputs as I
+from gpu_helpers import rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bctx():
+    import torch
+    c = L.Context(0, batched=True)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _job(kind, side, seed, f32=False, max_iter=None):
+    """(tensors, submit kwargs, oracle closure) for one job of the mixed stream recipe."""
+    import torch
+    dt = np.float32 if f32 else np.float64
+    if kind == "laplace":
+        a = I.laplace_input(side, seed=seed)
+        t = torch.from_numpy(a.astype(dt)).to("cuda:0")
+        mi = max_iter or 2000
+        kw = dict(stencil_id=L.LSR_ST_LAPLACE5, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), max_iter=mi, bc=L.LSR_BC_RING)
+        ora = lambda: O.jacobi_run(a, thr=1e-6, max_iter=mi)
+        return t, kw, ora, None
+    if kind == "helmholtz":
+        h = I.helmholtz_input(side)
+        t = torch.from_numpy(h.u0.astype(dt)).to("cuda:0")
+        g = torch.from_numpy(h.g.astype(dt)).to("cuda:0")
+        mi = max_iter or 5000
+        kw = dict(stencil_id=L.LSR_ST_HELMHOLTZ5, reduce_op=L.LSR_RED_L2_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), max_iter=mi, bc=L.LSR_BC_RING,
+                  env0=g, param=(h.alpha, h.h))
+        ora = lambda: O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                                   reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10, max_iter=mi)
+        return t, kw, ora, g
+    s = I.life_input(side, seed=seed)
+    t = torch.from_numpy(s).to("cuda:0")
+    mi = max_iter or 2000
+    kw = dict(stencil_id=L.LSR_ST_LIFE, reduce_op=L.LSR_RED_SUM,
+              cond=L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10), max_iter=mi, bc=L.LSR_BC_TORUS)
+    ora = lambda: O.life_run(s, stable_window=10, max_iter=mi)
+    return t, kw, ora, None
+
+
+def _submit(ctx, t, kw):
+    return ctx.submit(t, kw["stencil_id"], kw["reduce_op"], kw["cond"], kw["max_iter"], kw["bc"],
+                      env0=kw.get("env0"), param=kw.get("param", ()))
+
+
+MIX = [("laplace", 128, 1, False, 600), ("laplace", 200, 2, True, 600),
+       ("helmholtz", 129, 0, False, 700), ("helmholtz", 257, 0, True, 500),
+       ("life", 128, 3, False, 2000), ("life", 160, 4, False, 900), ("life", 130, 5, False, 500),
+       ("laplace", 333, 6, False, 300), ("laplace", 67, 7, True, 400)]
+
+
+def test_mixed_batch_matches_oracle(bctx):
+    import torch
+    say("batched mix vs oracle")
+    jobs = []
+    for kind, side, seed, f32, mi in MIX:
+        t, kw, ora, keep = _job(kind, side, seed, f32, mi)
+        jobs.append((kind, f32, t, ora, _submit(bctx, t, kw), keep))
+    for kind, f32, t, ora, job, _ in jobs:
+        r = bctx.result(job)
+        torch.cuda.synchronize()
+        o, ro = ora()
+        x = t.cpu().numpy()
+        assert r.status == L.LSR_OK, (kind, r.status)
+        assert r.iterations == ro.n, (kind, r.iterations, ro.n)
+        if kind == "life":
+            assert np.array_equal(x, o) and r.last_count == ro.count
+        elif f32:
+            assert rel_err(x, o) <= 1e-5
+        else:
+            assert np.array_equal(x, o)
+            assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
+        assert r.latency_ms >= r.queue_ms >= 0.0
+
+
+def test_alone_and_in_mix_are_identical(bctx):
+    import torch
+    say("alone vs mix")
+    target = ("helmholtz", 300, 0, True, 400)
+    t0, kw0, _, k0 = _job(*target)
+    r_alone = bctx.result(_submit(bctx, t0, kw0))
+    alone = t0.cpu().numpy().copy()
+    others = [_job(k, s, sd, f, mi) for (k, s, sd, f, mi) in MIX]
+    t1, kw1, _, k1 = _job(*target)
+    ids = [_submit(bctx, t, kw) for (t, kw, _, _) in others[:4]]
+    jid = _submit(bctx, t1, kw1)
+    ids += [_submit(bctx, t, kw) for (t, kw, _, _) in others[4:]]
+    r_mix = bctx.result(jid)
+    for i in ids:
+        bctx.result(i)
+    torch.cuda.synchronize()
+    assert np.array_equal(t1.cpu().numpy(), alone)
+    assert r_mix.iterations == r_alone.iterations and r_mix.last_reduce == r_alone.last_reduce
+
+
+def test_admission_waits_for_memory():
+    import torch
+    say("admission under a small budget")
+    side = 512
+    # pool blocks per job: partner 2 MiB, partials 4 KiB, state 4 KiB; the budget
+    # holds two jobs' scratch but not three
+    per_job = side * side * 8 + 4096 + 4096
+    with L.Context(0, hbm_budget_bytes=2 * per_job + 200_000, batched=True) as c:
+        ins = [I.laplace_input(side, seed=k) for k in range(5)]
+        ts = [torch.from_numpy(a).to("cuda:0") for a in ins]
+        ids = [c.submit(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                        L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), 200, L.LSR_BC_RING) for t in ts]
+        rs = [c.result(i) for i in ids]
+        torch.cuda.synchronize()
+        for a, t, r in zip(ins, ts, rs):
+            o, ro = O.jacobi_run(a, thr=1e-6, max_iter=200)
+            assert r.status == L.LSR_OK and r.iterations == ro.n and np.array_equal(t.cpu().numpy(), o)
+        # at most two jobs fit at once, so the later ones waited in the queue
+        assert max(r.queue_ms for r in rs[2:]) > min(r.queue_ms for r in rs[:2])
+
+
+def test_late_short_job_overtakes_long_job(bctx):
+    import torch
+    say("late arrival")
+    h = I.helmholtz_input(2048)
+    tl = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda:0")
+    g = torch.from_numpy(h.g.astype(np.float32)).to("cuda:0")
+    long_id = bctx.submit(tl, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                          L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 5000, L.LSR_BC_RING, env0=g,
+                          param=(h.alpha, h.h))
+    time.sleep(0.02)
+    a = I.laplace_input(96, seed=3)
+    ts = torch.from_numpy(a).to("cuda:0")
+    short_id = bctx.submit(ts, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                           L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), 300, L.LSR_BC_RING)
+    rs = bctx.result(short_id)
+    t_short = time.perf_counter()
+    rl = bctx.result(long_id)
+    t_long = time.perf_counter()
+    assert rs.status == L.LSR_OK and rl.status == L.LSR_OK and rl.iterations == 5000
+    assert t_short <= t_long and rs.latency_ms < rl.latency_ms
+    o, _ = O.jacobi_run(a, thr=1e-6, max_iter=300)
+    assert np.array_equal(ts.cpu().numpy(), o)
+
+
+def test_cancel_pending_and_running(bctx):
+    import torch
+    say("batched cancel")
+    h = I.helmholtz_input(1024)
+    t = torch.zeros((1024, 1024), dtype=torch.float64, device="cuda:0")
+    g = torch.from_numpy(h.g).to("cuda:0")
+    j1 = bctx.submit(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                     L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 5000, L.LSR_BC_RING, env0=g,
+                     param=(h.alpha, h.h))
+    bctx.cancel(j1)
+    r1 = bctx.result(j1)
+    assert r1.status in (L.LSR_ECANCELED, L.LSR_OK)
+    if r1.status == L.LSR_ECANCELED:
+        assert r1.iterations < 5000
+
+
+def test_restoration_rejected_on_batched_context(bctx):
+    import torch
+    say("restore on batched")
+    u = torch.zeros((16, 16), dtype=torch.float64, device="cuda:0")
+    m = torch.zeros((16, 16), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(L.LsrError) as ei:
+        bctx.submit(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA, L.make_cond(L.LSR_COND_BELOW, 0.1),
+                    10, L.LSR_BC_BOTTOM, env0=m, param=(100.0, 0.0))
+    assert ei.value.status == L.LSR_EINVAL

@@ -127,6 +127,32 @@ def test_f32_storage_within_1e5_of_f64_oracle(ctx, helm):
     assert abs(r.last_reduce - ro.r) / ro.r < 5e-2
 
 
+@pytest.mark.parametrize("n,sweeps", [(2049, 5000), (4096, 5000)])
+@pytest.mark.parametrize("batched", [False, True])
+def test_f32_helmholtz_large_within_1e5(ctx, n, sweeps, batched):
+    """The FP32 form at the largest Helmholtz size of the served stream, against the
+    closed form (which the FP64 oracle matches to ~1e-13 at every size tested)."""
+    import torch
+    say(f"f32 helmholtz N={n} sweeps={sweeps} batched={batched}")
+    h = I.helmholtz_input(n)
+    t = torch.zeros((n, n), dtype=torch.float32, device="cuda:0")
+    g = torch.from_numpy(h.g.astype(np.float32)).to("cuda:0")
+    c = L.Context(0, batched=True) if batched else ctx
+    try:
+        r = c.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, L.make_cond(L.LSR_COND_BELOW, 1e-9, 10),
+                  sweeps, L.LSR_BC_RING, env0=g, param=(h.alpha, h.h))
+    finally:
+        if batched:
+            c.close()
+    assert r.status == L.LSR_OK and r.iterations == sweeps
+    coef, dn = closed_form_helmholtz(n, 1.0, sweeps)
+    us = torch.from_numpy(h.ustar).to("cuda:0")
+    err = float((t.double() - coef * us).abs().max() / (coef * us).abs().max())
+    say(f"  rel err {err:.3e}")
+    assert err <= 1e-5
+    assert abs(r.last_reduce - dn) / dn < 5e-2
+
+
 def test_check_every_and_cap(ctx):
     say("check_every 10, cap 25")
     a = I.laplace_input(40, seed=2)
