@@ -40,7 +40,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash(files=("jacobi.hip", "tile_jacobi.hpp", "common.hpp", "kernels.hpp")) -> str:
+def kernel_source_hash(files=("jacobi.hip", "jacobi_tb.hip", "tile_jacobi.hpp", "common.hpp",
+                              "kernels.hpp")) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_1609_04567_amd", "csrc", f), "rb") as fh:
@@ -93,8 +94,8 @@ def run_helmholtz(args, L, I, torch):
     ustar = torch.from_numpy(h.ustar).to(dev)
     cond = L.make_cond(L.LSR_COND_BELOW, 1e-9, 10)
     ctx = L.Context(0)
-    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph, waves=args.waves,
-             unroll=args.unroll)
+    ctx.tune(tile_rows=args.tile_rows, tb_depth=args.tb, chunk=args.chunk, use_graph=args.graph,
+             waves=args.waves, unroll=args.unroll)
     copy_gbs = copy_probe(L, ctx, torch, dev)
 
     def step(t):
@@ -122,14 +123,17 @@ def run_helmholtz(args, L, I, torch):
     coef = (2 * math.pi ** 2 + 1.0) / (lam + 1.0) * -math.expm1(sweeps * math.log1p(-one_m_mu))
     err = float((grids[-1] - coef * ustar).abs().max() / (coef * ustar).abs().max())
     dev_ms = sum(r.device_ms for r in results)
-    per_launch_s = dev_ms * 1e-3 / (sweeps * args.steps)
+    spl = int(results[-1].sweeps_per_launch)   # sweeps fused per launch (1 = unfused)
+    per_launch_s = dev_ms * 1e-3 / (sweeps // spl * args.steps)
     out = base_line("GLUP/s", round(value, 3), "GLUP/s", args.steps, args.warmup,
                     round(wall / args.steps * 1e3, 3), "f64",
                     {"workload": f"helmholtz-jacobi5 {n}x{n} fp64, L2 of update every 10 sweeps, "
                                  f"stop <1e-9 or {sweeps} sweeps", "rows": n, "cols": n,
-                     "sweeps": sweeps, "check_every": 10, "parallelism": "single-gpu"})
-    out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s,
-                               measured_traffic(f"jacobi5_helmholtz_f64_{n}"))
+                     "sweeps": sweeps, "check_every": 10, "sweeps_per_launch": spl,
+                     "parallelism": "single-gpu"})
+    # a launch reads u and g and writes u once, whatever number of sweeps it fuses
+    kname = f"jacobi5_helmholtz_f64_{n}" if spl == 1 else f"jacobi5_tb{spl}_helmholtz_f64_{n}"
+    out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
     out["copy_probe_gbs"] = copy_gbs
     out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
                        "last_l2_update": results[-1].last_reduce}
@@ -153,8 +157,8 @@ def run_laplace(args, L, I, torch):
     a = I.laplace_input(n, seed=1)
     grids = [torch.from_numpy(a).to("cuda:0") for _ in range(args.steps + args.warmup)]
     ctx = L.Context(0)
-    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph, waves=args.waves,
-             unroll=args.unroll)
+    ctx.tune(tile_rows=args.tile_rows, tb_depth=args.tb, chunk=args.chunk, use_graph=args.graph,
+             waves=args.waves, unroll=args.unroll)
     cond = L.make_cond(L.LSR_COND_BELOW, 1e-6, 1)
     step = lambda t: ctx.run(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA, cond, sweeps,
                              L.LSR_BC_RING)
@@ -412,6 +416,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--tb", type=int, default=0, help="Jacobi sweeps fused per launch (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "

@@ -141,7 +141,8 @@ typedef struct {
     int32_t converged;      /* 1 if the condition held at the stop (0 if stopped by max_iter) */
     int32_t status;         /* lsr_status of the job */
     int32_t stable_run;     /* consecutive unchanged checks at the stop (Life) */
-    int32_t reserved;
+    int32_t sweeps_per_launch; /* sweeps each sweep-kernel launch advanced (the temporal
+                               blocking depth used; 1 when unfused) */
     int64_t checks;         /* number of reduce + condition evaluations */
     double device_ms;       /* device time from the job's first to its last kernel (batched: from
                                admission to retirement, shared with the other jobs of the batch) */
@@ -152,11 +153,17 @@ typedef struct {
 /* Tuning overrides; 0 in a field means "choose automatically". */
 typedef struct {
     int32_t tile_rows;      /* rows each workgroup streams through per sweep */
-    int32_t tb_depth;       /* sweeps fused per kernel (temporal blocking); 1 = off */
+    int32_t tb_depth;       /* Jacobi sweeps fused per launch (temporal blocking); 1 = off.
+                               Compiled depths are 2, 4 and 5; a depth is used only where it
+                               divides both check_every and max_iter and the grid is 16-byte
+                               aligned (pitch and buffers), else the job runs unfused. The
+                               field is a hint: results equal the unfused ones bit for bit
+                               apart from the order of the reduce's partial sums. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
     int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */
-    int32_t unroll;         /* Jacobi: rows loaded together per wavefront (4, 8 or 16) */
+    int32_t unroll;         /* Jacobi: rows loaded together per wavefront (4, 8 or 16;
+                               fused launches: 2 or 4) */
 } lsr_tuning;
 
 /* Creates a context on cfg->device. Returns EINVAL for a bad device, EDEVICE on HIP failure. */

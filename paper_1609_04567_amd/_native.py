@@ -45,11 +45,11 @@ class lsr_config(C.Structure):
 class lsr_job_result(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("last_reduce", C.c_double), ("last_count", C.c_uint64),
                 ("converged", C.c_int32), ("status", C.c_int32), ("stable_run", C.c_int32),
-                ("reserved", C.c_int32), ("checks", C.c_int64), ("device_ms", C.c_double),
-                ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("sweeps_per_launch", C.c_int32), ("checks", C.c_int64),
+                ("device_ms", C.c_double), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class lsr_tuning(C.Structure):

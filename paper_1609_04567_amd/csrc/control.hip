@@ -74,11 +74,13 @@ __global__ void cancel_kernel(JobState* st, JobState* mirror) {
     publish_state(st, mirror, s);
 }
 
-// Live-cell count of a u8 grid: one partial per workgroup of 256 threads, each
-// thread summing non-zero bytes of whole rows it strides over.
+// Live-cell count of a u8 grid before the first sweep (one partial per
+// 256-thread workgroup). A cell is alive iff its byte is non-zero; the pass also
+// rewrites every byte above 1 as 1 (in place, only those bytes), so the sweep
+// kernels can treat cells as 0/1 words.
 constexpr int kCountBlocks = 512;
 
-__global__ __launch_bounds__(256) void count_u8_kernel(const uint8_t* __restrict__ a, int64_t rows,
+__global__ __launch_bounds__(256) void count_u8_kernel(uint8_t* __restrict__ a, int64_t rows,
                                                        int64_t cols, int64_t pitch,
                                                        unsigned long long* __restrict__ parts) {
     __shared__ unsigned long long lds[4];
@@ -87,7 +89,9 @@ __global__ __launch_bounds__(256) void count_u8_kernel(const uint8_t* __restrict
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * 256) {
         const int64_t r = i / cols, c = i - r * cols;
-        acc += a[r * pitch + c] != 0;
+        const uint8_t v = a[r * pitch + c];
+        if (v > 1) a[r * pitch + c] = 1;
+        acc += v != 0;
     }
     acc = block_reduce_u64<4>(acc, lds);
     if (threadIdx.x == 0) parts[blockIdx.x] = acc;
@@ -100,7 +104,7 @@ int count_u8_parts(int64_t rows, int64_t cols) {
     return (int)(need < kCountBlocks ? need : kCountBlocks);
 }
 
-hipError_t launch_count_u8(const uint8_t* a, int64_t rows, int64_t cols, int64_t pitch,
+hipError_t launch_count_u8(uint8_t* a, int64_t rows, int64_t cols, int64_t pitch,
                            void* partials, int* nparts_out, hipStream_t s) {
     const int nb = count_u8_parts(rows, cols);
     hipLaunchKernelGGL(count_u8_kernel, dim3(nb), dim3(256), 0, s, a, rows, cols, pitch,

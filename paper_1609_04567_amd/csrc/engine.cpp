@@ -173,7 +173,7 @@ lsr_status lsr_ctx::engine_admit() {
         HIP_TRY(hipEventRecord(j->ev_begin, stream));
         if (j->stencil == LSR_ST_LIFE) {
             int np = 0;
-            HIP_TRY(lsr::launch_count_u8(static_cast<const uint8_t*>(g.data), g.rows, g.cols, g.pitch,
+            HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
                                          parts, &np, stream));
             HIP_TRY(lsr::launch_init_state(j->st, parts, np, stream));
         } else {
@@ -250,6 +250,7 @@ void lsr_ctx::engine_scan() {
         r.last_count = fin.count;
         r.converged = fin.converged;
         r.stable_run = fin.run;
+        r.sweeps_per_launch = 1;
         r.checks = fin.checks;
         r.status = fin.status == lsr::ST_NUMERIC ? LSR_ENUMERIC
                  : fin.status == lsr::ST_CANCELED ? LSR_ECANCELED : LSR_OK;

@@ -78,9 +78,13 @@ hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, v
 
 }  // namespace
 
-SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll) {
+SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll, int depth) {
     SweepGeom g;
     g.vec = pick_vec(a);
+    if (depth > 1 && g.vec > 1 && jacobi_tb_depth_ok(depth)) {
+        jacobi_tb_geom(a, depth, tile_rows, waves, unroll, g);
+        return g;
+    }
     if (g.vec == 1) {
         waves = 4;
         unroll = 4;
@@ -101,6 +105,7 @@ SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll)
 
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s) {
+    if (g.tb > 1) return launch_jacobi_tb(a, g, st, partials, c, j, s);
     if (a.f32) {
         if (a.helm) return g.vec == 4 ? launch_shape<float, true, 4>(a, g, st, partials, c, j, s)
                                       : launch_shape<float, true, 1>(a, g, st, partials, c, j, s);

@@ -1,0 +1,124 @@
+// Temporally blocked 5-point Jacobi kernel: one launch advances the field by K
+// sweeps (Sect. 3.1's loop body applied K times between two condition tests).
+// Every workgroup streams a band of rows through a register pipeline of K
+// levels (tile_jacobi.hpp, jacobi5_tb_tile); neighbouring windows overlap by K
+// columns and neighbouring bands by K rows, so tiles never exchange data and
+// each cell of every level is computed from exactly the operands a plain sweep
+// would read. Per K sweeps a cell is read once (plus the g term) and written
+// once, instead of K times each.
+//
+// Used only where K divides both the check period and the sweep cap, so every
+// condition test falls on a launch's last level and the stop sweep is exact.
+#include "kernels.hpp"
+#include "tile_jacobi.hpp"
+
+namespace lsr {
+namespace {
+
+template <typename T, bool HELM, int VEC, int NW, int K, int U>
+__global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
+    const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
+    int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
+    double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles, int tile_rows) {
+    __shared__ double lds[NW];
+    if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    // sweeps n1 .. n1 + K - 1; K divides the sweep cap, so all of them are due
+    const int64_t n1 = __hip_atomic_load(&st->n_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + j + 1;
+    if (n1 > ctl.max_iter) return;
+    const bool check = is_check_sweep(n1 + K - 1, ctl);
+    const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
+    if (t >= tiles) return;
+    jacobi5_tb_tile<T, HELM, VEC, NW, K, U, true, HELM>(a, b, g, rows, cols, pitch, rd, rd_lo,
+                                                        (uint32_t)n1, check, ctl.reduce, t, strips,
+                                                        tile_rows, partials, lds);
+}
+
+// Fused depths and launch shapes compiled for the vector (16-byte aligned) path.
+constexpr int kDepths[] = {2, 4, 5};
+struct Shape {
+    int waves, unroll;
+};
+constexpr Shape kShapes[] = {{1, 2}, {1, 4}, {2, 4}, {4, 4}};
+
+bool shape_ok(int waves, int unroll) {
+    for (const Shape& s : kShapes)
+        if (s.waves == waves && s.unroll == unroll) return true;
+    return false;
+}
+
+template <typename T, bool HELM, int VEC, int NW, int K, int U>
+hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                    const LoopCtl& c, int j, hipStream_t s) {
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, U>), dim3(g.blocks), dim3(NW * 64),
+                       0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
+                       static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
+                       T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,
+                       g.tiles, g.tile_rows);
+    return hipGetLastError();
+}
+
+template <typename T, bool HELM, int VEC, int K>
+hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                        const LoopCtl& c, int j, hipStream_t s) {
+    switch (g.waves * 100 + g.unroll) {
+        case 102: return launch_t<T, HELM, VEC, 1, K, 2>(a, g, st, partials, c, j, s);
+        case 104: return launch_t<T, HELM, VEC, 1, K, 4>(a, g, st, partials, c, j, s);
+        case 204: return launch_t<T, HELM, VEC, 2, K, 4>(a, g, st, partials, c, j, s);
+        case 404: return launch_t<T, HELM, VEC, 4, K, 4>(a, g, st, partials, c, j, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, bool HELM, int VEC>
+hipError_t launch_depth(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                        const LoopCtl& c, int j, hipStream_t s) {
+    switch (g.tb) {
+        case 2: return launch_shape<T, HELM, VEC, 2>(a, g, st, partials, c, j, s);
+        case 4: return launch_shape<T, HELM, VEC, 4>(a, g, st, partials, c, j, s);
+        case 5: return launch_shape<T, HELM, VEC, 5>(a, g, st, partials, c, j, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool jacobi_tb_depth_ok(int depth) {
+    for (int k : kDepths)
+        if (k == depth) return true;
+    return false;
+}
+
+void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
+                    SweepGeom& g) {
+    if (!shape_ok(waves, unroll)) {
+        waves = 1;
+        unroll = 4;
+    }
+    g.tb = depth;
+    g.waves = waves;
+    g.unroll = unroll;
+    g.tile_rows = tile_rows > 0 ? tile_rows : 64;
+    // windows of 64 * vec columns step by ow (a multiple of vec) and output the
+    // ow columns after their first `depth`; the first window outputs from column 1
+    const int64_t ow = (64 * g.vec - 2 * depth) / g.vec * g.vec;
+    const int64_t need = a.cols - 1 - depth;
+    const int64_t nwin = need > 0 ? (need + ow - 1) / ow : 1;
+    g.strips = (int)((nwin + waves - 1) / waves);
+    g.bands = (int)((a.rows - 2 + g.tile_rows - 1) / g.tile_rows);
+    g.tiles = g.strips * g.bands;
+    g.blocks = pad_to_xcds(g.tiles);
+}
+
+hipError_t launch_jacobi_tb(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                            const LoopCtl& c, int j, hipStream_t s) {
+    if (a.f32) {
+        if (g.vec != 4) return hipErrorInvalidValue;
+        return a.helm ? launch_depth<float, true, 4>(a, g, st, partials, c, j, s)
+                      : launch_depth<float, false, 4>(a, g, st, partials, c, j, s);
+    }
+    if (g.vec != 2) return hipErrorInvalidValue;
+    return a.helm ? launch_depth<double, true, 2>(a, g, st, partials, c, j, s)
+                  : launch_depth<double, false, 2>(a, g, st, partials, c, j, s);
+}
+
+}  // namespace lsr

@@ -19,6 +19,7 @@ struct SweepGeom {
     int bands = 0;       // row bands
     int tiles = 0;       // strips * bands (= partials per check sweep)
     int blocks = 0;      // tiles padded to a multiple of 8
+    int tb = 1;          // sweeps advanced per launch (temporal blocking depth)
 };
 
 // Jacobi 5-point (Laplace / Helmholtz) -------------------------------------
@@ -32,9 +33,19 @@ struct JacobiArgs {
     int f32;             // 0 FP64 storage, 1 FP32 storage
 };
 // tile_rows / waves / unroll of 0 (or an unsupported pair) select the measured default.
-SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves = 0, int unroll = 0);
+// depth > 1 selects the temporally blocked kernel (one launch = `depth` sweeps)
+// when it is a compiled depth and the grid takes the vector path; the caller
+// checks g.tb for what was chosen. With g.tb = K, launch_jacobi's j is the
+// offset of the launch's first sweep (a multiple of K) and the result lands in b.
+SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves = 0, int unroll = 0,
+                      int depth = 1);
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s);
+bool jacobi_tb_depth_ok(int depth);
+void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
+                    SweepGeom& g);
+hipError_t launch_jacobi_tb(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                            const LoopCtl& c, int j, hipStream_t s);
 
 // Game of Life B3/S23 --------------------------------------------------------
 struct LifeArgs {
@@ -46,8 +57,9 @@ struct LifeArgs {
 SweepGeom life_geom(const LifeArgs& a, int tile_rows);
 hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
                        const LoopCtl& c, int j, hipStream_t s);
-// Live-cell count of a u8 grid into partials (one per block); returns the partial count.
-hipError_t launch_count_u8(const uint8_t* a, int64_t rows, int64_t cols, int64_t pitch,
+// Live-cell count of a u8 grid into partials (one per block), normalising bytes
+// above 1 to 1 in place; returns the partial count.
+hipError_t launch_count_u8(uint8_t* a, int64_t rows, int64_t cols, int64_t pitch,
                            void* partials, int* nparts_out, hipStream_t s);
 int count_u8_parts(int64_t rows, int64_t cols);
 

@@ -94,11 +94,13 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
 
 namespace {
 
-// Sweeps per chunk: a multiple of lcm(check_every, 2) that keeps a chunk near
-// kChunkTargetUs of device time at HBM speed, so the enqueue-ahead window stays
-// a few milliseconds and the overshoot after a stop stays bounded.
-int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int override_chunk) {
-    const int base = check_every % 2 == 0 ? check_every : 2 * check_every;
+// Sweeps per chunk: a multiple of lcm(check_every, 2 * tb) that keeps a chunk
+// near kChunkTargetUs of device time at HBM speed, so the enqueue-ahead window
+// stays a few milliseconds and the overshoot after a stop stays bounded. A
+// chunk then ends on a check sweep and holds an even number of launches, so
+// every chunk (and every replay of a captured one) starts from buffer 0.
+int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int override_chunk, int tb) {
+    const int base = std::lcm(check_every, 2 * tb);
     int chunk;
     if (override_chunk > 0) {
         chunk = (override_chunk + base - 1) / base * base;
@@ -128,8 +130,11 @@ hipEvent_t lsr_ctx::get_event() {
 }
 
 lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
-    void* src = j->buf[off & 1];
-    void* dst = j->buf[(off + 1) & 1];
+    // one launch advances tb sweeps (off .. off + tb - 1 of the chunk)
+    const int tb = j->geom.tb;
+    const int launch = off / tb;
+    void* src = j->buf[launch & 1];
+    void* dst = j->buf[(launch + 1) & 1];
     hipError_t e = hipSuccess;
     const lsr_grid& g = j->grid;
     switch (j->stencil) {
@@ -175,15 +180,16 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
         }
     }
     if (e != hipSuccess) return fail(LSR_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
-    if (j->fin_after[off]) {
-        e = lsr::launch_finalize(j->st, j->partials, j->ctl, off, j->mirror_dev, s);
+    const int last = off + tb - 1;
+    if (j->fin_after[last]) {
+        e = lsr::launch_finalize(j->st, j->partials, j->ctl, last, j->mirror_dev, s);
         if (e != hipSuccess) return fail(LSR_EDEVICE, "finalize launch: %s", hipGetErrorString(e));
     }
     return LSR_OK;
 }
 
 lsr_status lsr_ctx::enqueue_chunk_plain(Job* j, hipStream_t s) {
-    for (int off = 0; off < j->ctl.chunk; ++off) {
+    for (int off = 0; off < j->ctl.chunk; off += j->geom.tb) {
         lsr_status st = launch_sweep(j, off, s);
         if (st != LSR_OK) return st;
     }
@@ -202,7 +208,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
                                  g.rows, hipMemcpyDeviceToDevice, stream));
     if (j->stencil == LSR_ST_LIFE) {
         int np = 0;
-        HIP_TRY(lsr::launch_count_u8(static_cast<const uint8_t*>(j->buf[0]), g.rows, g.cols, g.pitch,
+        HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(j->buf[0]), g.rows, g.cols, g.pitch,
                                      j->partials, &np, stream));
         HIP_TRY(lsr::launch_init_state(j->st, j->partials, np, stream));
     } else {
@@ -276,7 +282,8 @@ lsr_status lsr_ctx::run_job(Job* j) {
     if (status != LSR_OK) return status;
     lsr::JobState fin;
     std::memcpy(&fin, (const void*)mir, sizeof fin);
-    if (fin.n & 1)
+    // the stop sweep is a multiple of tb; launch parity says which buffer holds it
+    if ((fin.n / j->geom.tb) & 1)
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream));
     HIP_TRY(hipEventRecord(j->ev_end, stream));
@@ -289,6 +296,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
     r.last_count = fin.count;
     r.converged = fin.converged;
     r.stable_run = fin.run;
+    r.sweeps_per_launch = j->geom.tb;
     r.checks = fin.checks;
     r.device_ms = ms;
     r.status = fin.status == lsr::ST_NUMERIC ? LSR_ENUMERIC
@@ -464,7 +472,10 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
             a.pitch = grid->pitch;
             a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
             a.f32 = grid->dtype == LSR_F32;
-            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll);
+            // temporal blocking only where every check lands on a launch's last sweep
+            int depth = tun.tb_depth > 0 ? tun.tb_depth : kAutoDepth;
+            if (depth > 1 && (cond->check_every % depth != 0 || max_iter % depth != 0)) depth = 1;
+            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth);
             break;
         }
         case LSR_ST_LIFE: {
@@ -497,7 +508,7 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     lsr::LoopCtl& c = j->ctl;
     c.max_iter = max_iter;
     c.check_every = cond->check_every;
-    c.chunk = pick_chunk(grid, cond->check_every, max_iter, tun.chunk);
+    c.chunk = pick_chunk(grid, cond->check_every, max_iter, tun.chunk, j->geom.tb);
     c.reduce = reduce_op;
     c.cond = cond->kind;
     c.stable_window = cond->stable_window;

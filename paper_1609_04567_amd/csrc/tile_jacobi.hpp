@@ -94,6 +94,25 @@ __device__ __forceinline__ float add_round_stochastic(float p, float c, uint32_t
     return (fabsf(rem) > u * ulp) ? hi + copysignf(ulp, rem) : hi;
 }
 
+// The 5-point update of one cell (row, col) at sweep number `sweep`; the only
+// place the expression is written, shared by the plain and the blocked tiles.
+template <typename T, bool HELM>
+__device__ __forceinline__ T jacobi_update(T N, T S, T W, T E, T gv, T rd, T rd_lo, int64_t row,
+                                           int64_t col, uint32_t sweep) {
+    if constexpr (HELM && sizeof(T) == 8) {
+        return (((N + S) + (W + E)) + gv) * rd;
+    } else if constexpr (HELM) {
+        const T sn = (N + S) + (W + E);
+        const T tt = sn + gv, bb = tt - sn;
+        const T te = (sn - (tt - bb)) + (gv - bb);  // exact: sn + gv = tt + te
+        const uint32_t key = (uint32_t)row * 0x9e3779b1u ^ (uint32_t)col * 0x85ebca77u ^
+                             sweep * 0xc2b2ae3du;
+        return add_round_stochastic(T(0.25) * tt, T(0.25) * te - rd_lo * tt, hash32(key));
+    } else {
+        return T(0.25) * ((N + S) + (W + E));
+    }
+}
+
 __device__ __forceinline__ double jacobi_accum(int red, double acc, double d) {
     if (red == RED_MAX_ABS) return max_nan(acc, fabs(d));
     if (red == RED_L2) return acc + d * d;
@@ -154,20 +173,8 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
                     const T W = (e > 0) ? mid[e - 1] : wl;
                     const T E = (e < VEC - 1) ? mid[e + 1] : er;
                     const T N = up[e], S = dn[k][e];
-                    T nv;
-                    if constexpr (HELM && sizeof(T) == 8) {
-                        nv = (((N + S) + (W + E)) + gr[k][e]) * rd;
-                    } else if constexpr (HELM) {
-                        const T sn = (N + S) + (W + E), gv = gr[k][e];
-                        const T tt = sn + gv, bb = tt - sn;
-                        const T te = (sn - (tt - bb)) + (gv - bb);  // exact: sn + gv = tt + te
-                        const uint32_t key = (uint32_t)(r + k) * 0x9e3779b1u ^
-                                             (uint32_t)(c + e) * 0x85ebca77u ^ sweep * 0xc2b2ae3du;
-                        nv = add_round_stochastic(T(0.25) * tt, T(0.25) * te - rd_lo * tt,
-                                                  hash32(key));
-                    } else {
-                        nv = T(0.25) * ((N + S) + (W + E));
-                    }
+                    const T nv = jacobi_update<T, HELM>(N, S, W, E, HELM ? gr[k][e] : T(0), rd,
+                                                        rd_lo, r + k, c + e, sweep);
                     const int64_t col = c + e;
                     const bool inner = col >= 1 && col <= cols - 2;
                     out[e] = inner ? nv : mid[e];
@@ -178,6 +185,169 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
                 for (int e = 0; e < VEC; ++e) { up[e] = mid[e]; mid[e] = dn[k][e]; }
                 mid_w = dn_w[k];
                 mid_e = dn_e[k];
+            }
+        }
+    }
+    if (check) {
+        const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
+        if (threadIdx.x == 0) partials[t] = v;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Temporally blocked tile: K sweeps per launch (read u and g once, write the
+// K-th iterate once: 24/K bytes per cell update in FP64).
+//
+// Each wavefront loads a window of 64*VEC columns starting at a 16-byte aligned
+// column and writes only part of it: values next to a window edge that lies
+// inside the grid are wrong after each level, and the wrong region grows by one
+// column per level, so window w (starting at column w*OW, OW = 64*VEC - 2K
+// rounded down to a multiple of VEC) writes columns [w*OW + K, w*OW + K + OW);
+// consecutive windows overlap by 2K columns and tile the row exactly. A window
+// that contains the boundary ring (column 0 or cols-1) writes up to it: ring
+// cells keep their value at every level, so nothing spreads across them.
+// Rows stream downwards: after level-0 row i is loaded, level j (1..K) computes
+// its row i-j from the last three rows of level j-1, each level keeping its own
+// three rows in registers, plus a ring of the last K rows of g. Level K rows in
+// [r0, r1) are stored (and reduced on a check sweep, against level K-1, the
+// previous sweep). Each level evaluates jacobi_update with that level's sweep
+// number, so the K-th iterate is bit-identical to K single sweeps. Rows and
+// columns outside the grid are zero-filled and never loaded; like the windows'
+// inner edges they cannot reach an interior cell through the fixed ring.
+template <int VEC, int K>
+constexpr int tb_out_width() { return (64 * VEC - 2 * K) / VEC * VEC; }
+
+template <typename T, bool HELM, int VEC, int NW, int K, int U, bool NT, bool NTG>
+__device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
+                                                const T* __restrict__ g, int64_t rows,
+                                                int64_t cols, int64_t pitch, T rd, T rd_lo,
+                                                uint32_t sweep0, bool check, int red, int t,
+                                                int strips, int tile_rows,
+                                                double* __restrict__ partials, double* lds) {
+    constexpr int OW = tb_out_width<VEC, K>();
+    const int band = t / strips, strip = t - band * strips;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t cw = ((int64_t)strip * NW + wave) * OW;       // window start (aligned)
+    const int64_t c = cw + (int64_t)lane * VEC;
+    const int64_t olo = (cw == 0) ? 1 : cw + K;                  // output columns [olo, ohi)
+    const int64_t ohi = min(cw + K + (int64_t)OW, cols - 1);
+    const int64_t r0 = 1 + (int64_t)band * tile_rows;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, rows - 1);
+
+    // window element e of this lane is at column c + e; loads only inside the grid
+    auto load = [&](const T* __restrict__ base, int64_t row, T (&v)[VEC], bool nt) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = T(0);
+        if (row < 0 || row >= rows) return;
+        const T* p = base + row * pitch;
+        if (VEC > 1 && c >= 0 && c + VEC <= cols) {
+            typedef T V __attribute__((ext_vector_type(VEC)));
+            V x = nt ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p + c))
+                     : *reinterpret_cast<const V*>(p + c);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = x[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (c + e >= 0 && c + e < cols) v[e] = p[c + e];
+        }
+    };
+
+    T Wn[K][3][VEC];   // level j: rows (newest - 2, newest - 1, newest)
+    T G[K][VEC];       // G[m] = g row (i - 1 - m) at step i
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            Wn[j][0][e] = Wn[j][1][e] = Wn[j][2][e] = T(0);
+            G[j][e] = T(0);
+        }
+
+    double acc = 0.0;
+    const int64_t i_beg = r0 - K, i_end = r1 + K;   // level-0 rows streamed
+    for (int64_t i0 = i_beg; i0 < i_end; i0 += U) {
+        T in[U][VEC], gin[U][VEC];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (i0 + q < i_end) {
+                load(a, i0 + q, in[q], false);
+                if (HELM) load(g, i0 + q - 1, gin[q], NTG);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t i = i0 + q;
+            if (i >= i_end) break;
+            // shift in level-0 row i and g row i-1
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                Wn[0][0][e] = Wn[0][1][e];
+                Wn[0][1][e] = Wn[0][2][e];
+                Wn[0][2][e] = in[q][e];
+            }
+            if (HELM) {
+#pragma unroll
+                for (int m = K - 1; m > 0; --m)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) G[m][e] = G[m - 1][e];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) G[0][e] = gin[q][e];
+            }
+            // level j computes row i - j from level j-1 (centre row i - j)
+#pragma unroll
+            for (int j = 1; j <= K; ++j) {
+                const int64_t row = i - j;
+                const T(&src)[3][VEC] = Wn[j - 1];
+                T wl = __shfl_up(src[1][VEC - 1], 1, 64);
+                T er = __shfl_down(src[1][0], 1, 64);
+                if (lane == 0) wl = T(0);
+                if (lane == 63) er = T(0);
+                T nv[VEC];
+                const bool row_inner = row >= 1 && row <= rows - 2;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const T Wv = (e > 0) ? src[1][e - 1] : wl;
+                    const T Ev = (e < VEC - 1) ? src[1][e + 1] : er;
+                    const int64_t col = c + e;
+                    const bool inner = row_inner && col >= 1 && col <= cols - 2;
+                    const T upd = jacobi_update<T, HELM>(src[0][e], src[2][e], Wv, Ev,
+                                                         HELM ? G[j - 1][e] : T(0), rd, rd_lo, row,
+                                                         col, sweep0 + (uint32_t)(j - 1));
+                    nv[e] = inner ? upd : src[1][e];
+                }
+                if (j < K) {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        Wn[j][0][e] = Wn[j][1][e];
+                        Wn[j][1][e] = Wn[j][2][e];
+                        Wn[j][2][e] = nv[e];
+                    }
+                } else if (row >= r0 && row < r1) {
+                    T* p = b + row * pitch;
+                    if (VEC > 1 && c >= olo && c + VEC <= ohi) {
+                        typedef T V __attribute__((ext_vector_type(VEC)));
+                        V x;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) x[e] = nv[e];
+                        if (NT) __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + c));
+                        else *reinterpret_cast<V*>(p + c) = x;
+                        if (check) {
+#pragma unroll
+                            for (int e = 0; e < VEC; ++e)
+                                acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[1][e]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) {
+                            const int64_t col = c + e;
+                            if (col >= olo && col < ohi) {
+                                p[col] = nv[e];
+                                if (check) acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[1][e]);
+                            }
+                        }
+                    }
+                }
             }
         }
     }

@@ -14,6 +14,8 @@
 // popcount is the cell count. Wavefronts stream down `tile_rows` rows.
 //
 // Generic tile (any shape/pitch): one thread per cell, nine byte loads.
+// Both tiles expect cells of 0 or 1: the job's initial live-count pass rewrites
+// any other non-zero byte as 1 (a cell is alive iff its byte is non-zero).
 // Boundaries: torus wraps rows and columns; bottom treats outside cells as dead.
 #pragma once
 
@@ -21,17 +23,15 @@
 
 namespace lsr {
 
-__device__ __forceinline__ uint32_t nz_bytes(uint32_t x) {
-    // 0x01 in every byte that is non-zero, 0x00 elsewhere
-    return ((((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) >> 7) & 0x01010101u;
-}
-
 __device__ __forceinline__ uint32_t zero_bytes_hi(uint32_t x) {
     // 0x80 in every byte equal to zero, for byte values below 0x80
     return ~(x + 0x7F7F7F7Fu) & 0x80808080u;
 }
 
 // Tile t (band-major over `strips` strips of NW*1024 columns); NW*64 threads.
+// Cells must hold 0 or 1 (the job's first pass normalises the input in place).
+// With count = T - centre, B3/S23 is exactly (count | centre) == 3: a dead cell
+// is born on 3, a live one survives on 2 or 3.
 template <int NW, int U, bool NT>
 __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, uint8_t* __restrict__ b,
                                                int64_t rows, int64_t cols, int64_t pitch, int torus,
@@ -54,23 +54,28 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
     const int64_t r0 = (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows);
 
+    // rows r0-1 .. r1 are touched, so one step of wrap is enough on a torus;
+    // outside rows of a bottom boundary are dead (all zero)
     auto load = [&](int64_t r, uint32_t (&w)[4], uint32_t& hw, uint32_t& he) {
         w[0] = w[1] = w[2] = w[3] = 0;
         hw = he = 0;
-        if (r < 0 || r >= rows) {
+        if (r < 0) {
             if (!torus) return;
-            r = (r + rows) % rows;
+            r += rows;
+        } else if (r >= rows) {
+            if (!torus) return;
+            r -= rows;
         }
         const uint8_t* p = a + r * pitch;
         if (active) {
             const uint4 x = *reinterpret_cast<const uint4*>(p + c);
-            w[0] = nz_bytes(x.x);
-            w[1] = nz_bytes(x.y);
-            w[2] = nz_bytes(x.z);
-            w[3] = nz_bytes(x.w);
+            w[0] = x.x;
+            w[1] = x.y;
+            w[2] = x.z;
+            w[3] = x.w;
         }
-        if (has_w) hw = p[wcol] != 0;
-        if (has_e) he = p[ecol] != 0;
+        if (has_w) hw = p[wcol];
+        if (has_e) he = p[ecol];
     };
 
     uint32_t up[4], mid[4], up_w, up_e, mid_w, mid_e;
@@ -101,9 +106,7 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
                     const uint32_t prev = (m > 0) ? (V[m - 1] >> 24) : wv;
                     const uint32_t next = (m < 3) ? (V[m + 1] & 0xFFu) : ev;
                     const uint32_t T = ((V[m] << 8) | prev) + V[m] + ((V[m] >> 8) | (next << 24));
-                    const uint32_t eq3 = zero_bytes_hi(T ^ 0x03030303u);
-                    const uint32_t eq4 = zero_bytes_hi(T ^ 0x04040404u);
-                    const uint32_t alive = eq3 | (eq4 & (mid[m] << 7));
+                    const uint32_t alive = zero_bytes_hi(((T - mid[m]) | mid[m]) ^ 0x03030303u);
                     out[m] = alive >> 7;
                     cnt += (unsigned)__popc(alive);
                 }

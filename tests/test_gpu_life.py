@@ -108,3 +108,14 @@ def test_full_16384_run_is_deterministic(ctx):
                     300, L.LSR_BC_TORUS)
         outs.append((t.cpu().numpy(), r.last_count, r.iterations))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (17, 13), (64, 1040)])
+def test_nonzero_bytes_are_alive(ctx, shape):
+    """Bytes other than 0/1 count as alive (the first pass normalises them in place)."""
+    say(f"life non-0/1 bytes {shape}")
+    rng = np.random.default_rng(9)
+    a = I.life_input(*shape, seed=6) * rng.integers(1, 256, size=shape).astype(np.uint8)
+    o, ro = O.life_run(a, bc=O.BC_TORUS, cond=O.COND_NEVER, max_iter=7)
+    x, r = run_life(ctx, a, cond=L.LSR_COND_NEVER, max_iter=7)
+    assert np.array_equal(x, o) and r.last_count == ro.count

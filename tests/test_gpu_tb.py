@@ -1,0 +1,117 @@
+"""GPU parity of the temporally blocked Jacobi path (tb_depth > 1).
+
+A fused launch computes every cell of every sweep from the same operands, in the
+same expression order, as the unfused kernel, so the FP64 field must equal the
+oracle bit for bit and the FP32 field must equal the unfused FP32 field bit for
+bit (same stochastic-rounding keys). Stop sweeps are exact; the reduce value
+matches to 1e-12 relative (only the partial-sum grouping differs).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1609_04567_amd as L
+from paper_1609_04567_amd import inputs as I
+from gpu_helpers import closed_form_helmholtz, run_jacobi, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _tuned(ctx, fn, **tune):
+    ctx.tune(**tune)
+    try:
+        return fn()
+    finally:
+        ctx.tune()
+
+
+@pytest.mark.parametrize("depth", [2, 4, 5])
+@pytest.mark.parametrize("shape", [(3, 4), (8, 8), (130, 1030), (257, 260), (70, 250)])
+def test_laplace_f64_fused_matches_oracle(ctx, depth, shape):
+    say(f"tb laplace f64 depth={depth} shape={shape}")
+    a = I.laplace_input(*shape, seed=11)
+    ce, mi, thr = 20, 400, 2e-4
+    o, ro = O.jacobi_run(a, thr=thr, check_every=ce, max_iter=mi)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=thr, check_every=ce, max_iter=mi),
+                  tb_depth=depth)
+    assert r.iterations == ro.n and bool(r.converged) == ro.converged
+    assert np.array_equal(x, o)
+    assert abs(r.last_reduce - ro.r) <= 1e-12 * abs(ro.r)
+
+
+@pytest.mark.parametrize("depth", [2, 4, 5])
+@pytest.mark.parametrize("tile_rows,waves,unroll", [(0, 0, 0), (8, 1, 2), (17, 2, 4), (64, 4, 4)])
+def test_helmholtz_f64_fused_matches_oracle(ctx, depth, tile_rows, waves, unroll):
+    say(f"tb helmholtz f64 depth={depth} tiles={tile_rows} shape={waves}x{unroll}")
+    h = I.helmholtz_input(300)
+    o, ro = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=1.0, h=h.h,
+                         reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=20, max_iter=160)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, h.u0, helm=True, g=h.g, alpha=1.0, h=h.h,
+                                          reduce_op=L.LSR_RED_L2_DELTA, thr=1e-9, check_every=20,
+                                          max_iter=160),
+                  tb_depth=depth, tile_rows=tile_rows, waves=waves, unroll=unroll)
+    assert r.iterations == 160 and np.array_equal(x, o)
+    assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
+
+
+@pytest.mark.parametrize("depth", [2, 4])
+@pytest.mark.parametrize("chunk,graph", [(0, 0), (8, -1), (40, 1)])
+def test_fused_chunking_and_graphs(ctx, depth, chunk, graph):
+    say(f"tb chunk={chunk} graph={graph} depth={depth}")
+    a = I.laplace_input(200, 264, seed=12)
+    o, ro = O.jacobi_run(a, thr=1e-4, check_every=4, max_iter=1000)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=1e-4, check_every=4, max_iter=1000),
+                  tb_depth=depth, chunk=chunk, use_graph=graph)
+    assert r.iterations == ro.n and r.converged == ro.converged and np.array_equal(x, o)
+
+
+@pytest.mark.parametrize("depth,view", [(4, {}), (5, dict(pitch=1031, offset=1)), (3, {})])
+def test_depth_that_cannot_be_used_falls_back(ctx, depth, view):
+    """A depth that does not divide check_every, an unaligned view and a depth that
+    is not compiled all run unfused, with the same result."""
+    say(f"tb fallback depth={depth} view={view}")
+    a = I.laplace_input(70, 1030, seed=6)
+    o, ro = O.jacobi_run(a, thr=1e-6, check_every=10, max_iter=150)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=1e-6, check_every=10, max_iter=150, **view),
+                  tb_depth=depth)
+    assert r.iterations == ro.n and np.array_equal(x, o)
+
+
+@pytest.mark.parametrize("helm", [False, True])
+@pytest.mark.parametrize("depth", [2, 5])
+def test_f32_fused_equals_unfused(ctx, helm, depth):
+    say(f"tb f32 helm={helm} depth={depth}")
+    if helm:
+        h = I.helmholtz_input(260)
+        a, g, alpha, hh = h.u0, h.g, h.alpha, h.h
+    else:
+        a, g, alpha, hh = I.laplace_input(256, 260, seed=1), None, 0.0, 1.0
+    kw = dict(helm=helm, g=g, alpha=alpha, h=hh, f32=True, reduce_op=L.LSR_RED_L2_DELTA,
+              thr=1e-9, check_every=10, max_iter=500)
+    x1, r1 = _tuned(ctx, lambda: run_jacobi(ctx, a, **kw), tb_depth=1)
+    xk, rk = _tuned(ctx, lambda: run_jacobi(ctx, a, **kw), tb_depth=depth)
+    assert rk.iterations == r1.iterations and np.array_equal(xk, x1)
+    assert abs(rk.last_reduce - r1.last_reduce) <= 1e-12 * abs(r1.last_reduce)
+
+
+@pytest.mark.parametrize("depth", [2, 5])
+def test_helmholtz_8192_fused_closed_form(ctx, depth):
+    """The benchmarked workload (8192^2 FP64, L2 every 10 sweeps, cap 5000) fused."""
+    import torch
+    say(f"tb helmholtz f64 8192^2 depth={depth}")
+    n, sweeps = 8192, 5000
+    h = I.helmholtz_input(n)
+    t = torch.zeros((n, n), dtype=torch.float64, device="cuda:0")
+    g = torch.from_numpy(h.g).to("cuda:0")
+    r = _tuned(ctx, lambda: ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                                    L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), sweeps,
+                                    L.LSR_BC_RING, env0=g, param=(1.0, h.h)),
+               tb_depth=depth)
+    assert r.status == L.LSR_OK and r.iterations == sweeps and r.checks == sweeps // 10
+    coef, dn = closed_form_helmholtz(n, 1.0, sweeps)
+    us = torch.from_numpy(h.ustar).to("cuda:0")
+    err = float((t - coef * us).abs().max() / (coef * us).abs().max())
+    say(f"  rel err {err:.3e}")
+    assert err < 1e-11, err
+    assert abs(r.last_reduce - dn) / dn < 1e-8
+    assert float(t[0].abs().max()) == 0.0 and float(t[:, -1].abs().max()) == 0.0

@@ -107,7 +107,7 @@ def _life_accesses(rows, cols, nw, tile_rows, torus):
                 if r < 0 or r >= rows:
                     if not torus:
                         continue
-                    rr = (r + rows) % rows
+                    rr = r + rows if r < 0 else r - rows  # the kernel wraps one step only
                 if not (0 <= rr < rows):
                     bad.append(("row", t, w, r))
             for r in range(r0, r1):
@@ -133,3 +133,106 @@ def test_model_flags_the_unguarded_west_halo():
     assert cw >= cols and cw < span
     # with the guard cw < cols removed, the halo column would be cw - 1 >= cols
     assert not (0 <= cw - 1 < cols)
+
+
+# ---------------------------------------------------------------------------
+# Temporally blocked Jacobi kernel (jacobi5_tb_kernel): a launch advances K
+# sweeps. Each wavefront owns a window of 64 * vec columns starting at
+# cw = window * ow, ow = (64 * vec - 2K) rounded down to a multiple of vec;
+# it streams rows r0 - K .. r1 + K - 1 of the band through K levels and stores
+# level K for rows [r0, r1), columns [olo, ohi). The model below replays that
+# schedule on the CPU (zeros outside the grid and before the stream start, a
+# zero west neighbour at lane 0 and east neighbour at lane 63, boundary cells
+# carried unchanged) and checks that the stored cells cover the interior
+# exactly once and equal K plain sweeps.
+# ---------------------------------------------------------------------------
+
+def _tb_geometry(rows, cols, vec, nw, k, tile_rows):
+    ow = (64 * vec - 2 * k) // vec * vec
+    need = cols - 1 - k
+    nwin = -(-need // ow) if need > 0 else 1
+    strips = -(-nwin // nw)
+    bands = -(-(rows - 2) // tile_rows)
+    return ow, strips, bands
+
+
+def _tb_model(u, k, vec, nw, tile_rows):
+    rows, cols = u.shape
+    ow, strips, bands = _tb_geometry(rows, cols, vec, nw, k, tile_rows)
+    out = u.copy()                       # the partner buffer starts as a copy
+    written = np.zeros(u.shape, dtype=np.int64)
+    width = 64 * vec
+    loads_ok = True
+    for t in range(strips * bands):
+        band, strip = divmod(t, strips)
+        r0 = 1 + band * tile_rows
+        r1 = min(r0 + tile_rows, rows - 1)
+        for w in range(nw):
+            cw = (strip * nw + w) * ow
+            cidx = cw + np.arange(width)
+            inside = cidx < cols
+            olo = 1 if cw == 0 else cw + k
+            ohi = min(cw + k + ow, cols - 1)
+            if vec > 1 and cw % vec:
+                loads_ok = False         # windows must start 16-byte aligned
+            level = {}
+            for i in range(r0 - k, r1 + k):
+                row = np.zeros(width)
+                if 0 <= i < rows:
+                    row[inside] = u[i, cidx[inside]]
+                level[i] = row
+            col_inner = (cidx >= 1) & (cidx <= cols - 2)
+            for j in range(1, k + 1):
+                prev = level
+                level = {}
+                for i in range(r0 - k, r1 + k):
+                    r = i - j
+                    zero = np.zeros(width)
+                    n, c, s = prev.get(r - 1, zero), prev.get(r, zero), prev.get(r + 1, zero)
+                    wv = np.concatenate([[0.0], c[:-1]])
+                    ev = np.concatenate([c[1:], [0.0]])
+                    upd = 0.25 * ((n + s) + (wv + ev))
+                    inner = col_inner & (1 <= r <= rows - 2)
+                    level[r] = np.where(inner, upd, c)
+            for r in range(r0, r1):
+                sel = (cidx >= olo) & (cidx < ohi)
+                out[r, cidx[sel]] = level[r][sel]
+                written[r, cidx[sel]] += 1
+    return out, written, loads_ok
+
+
+@pytest.mark.parametrize("rows,cols", [(3, 3), (4, 5), (9, 130), (40, 131), (37, 260), (20, 517),
+                                       (70, 250)])
+@pytest.mark.parametrize("vec", [2, 4])
+@pytest.mark.parametrize("k", [2, 4, 5])
+@pytest.mark.parametrize("nw,tile_rows", [(1, 8), (2, 16), (4, 64)])
+def test_tb_schedule_covers_interior_and_matches_k_sweeps(rows, cols, vec, k, nw, tile_rows):
+    rng = np.random.default_rng(rows * 1000 + cols)
+    u = rng.standard_normal((rows, cols))
+    out, written, loads_ok = _tb_model(u, k, vec, nw, tile_rows)
+    assert loads_ok
+    want_written = np.zeros_like(written)
+    want_written[1:-1, 1:-1] = 1
+    assert np.array_equal(written, want_written)
+    ref = u.copy()
+    for _ in range(k):
+        nxt = ref.copy()
+        nxt[1:-1, 1:-1] = 0.25 * ((ref[:-2, 1:-1] + ref[2:, 1:-1]) + (ref[1:-1, :-2] + ref[1:-1, 2:]))
+        ref = nxt
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("rows,cols", [(8192, 8192), (4096, 4096), (8191, 8190), (2049, 2049)])
+@pytest.mark.parametrize("vec", [2, 4])
+@pytest.mark.parametrize("k", [2, 4, 5])
+def test_tb_stores_stay_in_interior_at_full_size(rows, cols, vec, k):
+    """Window arithmetic at the benchmark sizes: stores inside [1, cols-1), loads aligned."""
+    ow, strips, bands = _tb_geometry(rows, cols, vec, 1, k, 64)
+    cws = np.arange(strips) * ow
+    olo = np.where(cws == 0, 1, cws + k)
+    ohi = np.minimum(cws + k + ow, cols - 1)
+    assert (cws % vec == 0).all()
+    assert olo.min() >= 1 and ohi.max() <= cols - 1
+    live = olo < ohi
+    # consecutive output ranges abut: no column is skipped or written twice
+    assert (olo[live][1:] == ohi[live][:-1]).all() and ohi[live][-1] == cols - 1
