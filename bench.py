@@ -135,6 +135,8 @@ def run_helmholtz(args, L, I, torch):
     kname = f"jacobi5_helmholtz_f64_{n}" if spl == 1 else f"jacobi5_tb{spl}_helmholtz_f64_{n}"
     out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
     out["copy_probe_gbs"] = copy_gbs
+    # bytes an unfused sweep would move per update, at the achieved update rate
+    out["effective_gbs"] = round(value * 24.0, 1)
     out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
                        "last_l2_update": results[-1].last_reduce}
     if not args.no_cpu:
@@ -409,7 +411,7 @@ def main():
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--sweeps", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=200)
-    ap.add_argument("--cpu-sweeps", type=int, default=20)
+    ap.add_argument("--cpu-sweeps", type=int, default=600)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)

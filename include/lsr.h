@@ -153,17 +153,18 @@ typedef struct {
 /* Tuning overrides; 0 in a field means "choose automatically". */
 typedef struct {
     int32_t tile_rows;      /* rows each workgroup streams through per sweep */
-    int32_t tb_depth;       /* Jacobi sweeps fused per launch (temporal blocking); 1 = off.
-                               Compiled depths are 2, 4 and 5; a depth is used only where it
-                               divides both check_every and max_iter and the grid is 16-byte
-                               aligned (pitch and buffers), else the job runs unfused. The
-                               field is a hint: results equal the unfused ones bit for bit
-                               apart from the order of the reduce's partial sums. */
+    int32_t tb_depth;       /* Jacobi sweeps fused per launch (temporal blocking); 1 = off,
+                               0 = the measured best compiled depth (2, 4, 5, 8, 10) that divides
+                               both check_every and max_iter. A depth is used only where it
+                               divides both and the grid is 16-byte aligned (pitch and
+                               buffers), else the job runs unfused. Fields are bit for bit
+                               those of unfused sweeps; the reduce value differs at most in
+                               the order of its partial sums. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
     int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */
     int32_t unroll;         /* Jacobi: rows loaded together per wavefront (4, 8 or 16;
-                               fused launches: 2 or 4) */
+                               fused launches always load 3) */
 } lsr_tuning;
 
 /* Creates a context on cfg->device. Returns EINVAL for a bad device, EDEVICE on HIP failure. */

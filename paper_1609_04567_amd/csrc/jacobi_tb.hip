@@ -15,12 +15,13 @@
 namespace lsr {
 namespace {
 
-template <typename T, bool HELM, int VEC, int NW, int K, int U>
+template <typename T, bool HELM, int VEC, int NW, int K>
 __global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
     double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles, int tile_rows) {
     __shared__ double lds[NW];
+    __shared__ __attribute__((aligned(16))) T gring[HELM ? tb_gring_elems<VEC, NW, K>() : 1];
     if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     // sweeps n1 .. n1 + K - 1; K divides the sweep cap, so all of them are due
     const int64_t n1 = __hip_atomic_load(&st->n_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + j + 1;
@@ -28,29 +29,22 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
     const bool check = is_check_sweep(n1 + K - 1, ctl);
     const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
     if (t >= tiles) return;
-    jacobi5_tb_tile<T, HELM, VEC, NW, K, U, true, HELM>(a, b, g, rows, cols, pitch, rd, rd_lo,
-                                                        (uint32_t)n1, check, ctl.reduce, t, strips,
-                                                        tile_rows, partials, lds);
+    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM>(a, b, g, rows, cols, pitch, rd, rd_lo,
+                                                     (uint32_t)n1, check, ctl.reduce, t, strips,
+                                                     tile_rows, partials, lds, gring);
 }
 
-// Fused depths and launch shapes compiled for the vector (16-byte aligned) path.
-constexpr int kDepths[] = {2, 4, 5};
-struct Shape {
-    int waves, unroll;
-};
-constexpr Shape kShapes[] = {{1, 2}, {1, 4}, {2, 4}, {4, 4}};
+// Fused depths and wavefronts per workgroup compiled for the vector (16-byte
+// aligned) path; rows stream three at a time (one load group per iteration).
+constexpr int kDepths[] = {2, 4, 5, 8, 10};
 
-bool shape_ok(int waves, int unroll) {
-    for (const Shape& s : kShapes)
-        if (s.waves == waves && s.unroll == unroll) return true;
-    return false;
-}
+bool waves_ok(int waves) { return waves == 1 || waves == 2 || waves == 4; }
 
-template <typename T, bool HELM, int VEC, int NW, int K, int U>
+template <typename T, bool HELM, int VEC, int NW, int K>
 hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, U>), dim3(g.blocks), dim3(NW * 64),
-                       0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K>), dim3(g.blocks), dim3(NW * 64), 0,
+                       s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
                        T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,
                        g.tiles, g.tile_rows);
@@ -60,11 +54,10 @@ hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void*
 template <typename T, bool HELM, int VEC, int K>
 hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                         const LoopCtl& c, int j, hipStream_t s) {
-    switch (g.waves * 100 + g.unroll) {
-        case 102: return launch_t<T, HELM, VEC, 1, K, 2>(a, g, st, partials, c, j, s);
-        case 104: return launch_t<T, HELM, VEC, 1, K, 4>(a, g, st, partials, c, j, s);
-        case 204: return launch_t<T, HELM, VEC, 2, K, 4>(a, g, st, partials, c, j, s);
-        case 404: return launch_t<T, HELM, VEC, 4, K, 4>(a, g, st, partials, c, j, s);
+    switch (g.waves) {
+        case 1: return launch_t<T, HELM, VEC, 1, K>(a, g, st, partials, c, j, s);
+        case 2: return launch_t<T, HELM, VEC, 2, K>(a, g, st, partials, c, j, s);
+        case 4: return launch_t<T, HELM, VEC, 4, K>(a, g, st, partials, c, j, s);
     }
     return hipErrorInvalidValue;
 }
@@ -76,6 +69,8 @@ hipError_t launch_depth(const JacobiArgs& a, const SweepGeom& g, JobState* st, v
         case 2: return launch_shape<T, HELM, VEC, 2>(a, g, st, partials, c, j, s);
         case 4: return launch_shape<T, HELM, VEC, 4>(a, g, st, partials, c, j, s);
         case 5: return launch_shape<T, HELM, VEC, 5>(a, g, st, partials, c, j, s);
+        case 8: return launch_shape<T, HELM, VEC, 8>(a, g, st, partials, c, j, s);
+        case 10: return launch_shape<T, HELM, VEC, 10>(a, g, st, partials, c, j, s);
     }
     return hipErrorInvalidValue;
 }
@@ -88,16 +83,27 @@ bool jacobi_tb_depth_ok(int depth) {
     return false;
 }
 
+// Depth preference measured on the MI355X at 8192^2 (GLUP/s of the whole job,
+// 1000 sweeps, L2 check every 10): FP64 K=10 1160, K=5 887 (HBM-bound), unfused
+// 254; FP32 (compensated, stochastically rounded update, ALU-heavy) K=5 685,
+// K=10 628, unfused 435.
+int jacobi_tb_auto_depth(const JacobiArgs& a, int check_every, int64_t max_iter) {
+    static constexpr int kPrefF64[] = {10, 8, 5, 4, 2};
+    static constexpr int kPrefF32[] = {5, 4, 10, 8, 2};
+    for (int k : (a.f32 ? kPrefF32 : kPrefF64))
+        if (check_every % k == 0 && max_iter % k == 0) return k;
+    return 1;
+}
+
 void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
                     SweepGeom& g) {
-    if (!shape_ok(waves, unroll)) {
-        waves = 1;
-        unroll = 4;
-    }
+    (void)unroll;   // rows always stream in groups of three
+    if (!waves_ok(waves)) waves = 2;
     g.tb = depth;
     g.waves = waves;
-    g.unroll = unroll;
-    g.tile_rows = tile_rows > 0 ? tile_rows : 64;
+    g.unroll = 3;
+    // deeper blocks want taller bands (the 2K halo rows are re-read per band)
+    g.tile_rows = tile_rows > 0 ? tile_rows : (depth >= 8 ? 48 : 32);
     // windows of 64 * vec columns step by ow (a multiple of vec) and output the
     // ow columns after their first `depth`; the first window outputs from column 1
     const int64_t ow = (64 * g.vec - 2 * depth) / g.vec * g.vec;

@@ -42,6 +42,8 @@ SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves = 0, int unr
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s);
 bool jacobi_tb_depth_ok(int depth);
+// The measured best compiled depth dividing both check_every and max_iter (1 if none).
+int jacobi_tb_auto_depth(const JacobiArgs& a, int check_every, int64_t max_iter);
 void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
                     SweepGeom& g);
 hipError_t launch_jacobi_tb(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,

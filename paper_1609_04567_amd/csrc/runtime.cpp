@@ -473,7 +473,8 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
             a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
             a.f32 = grid->dtype == LSR_F32;
             // temporal blocking only where every check lands on a launch's last sweep
-            int depth = tun.tb_depth > 0 ? tun.tb_depth : kAutoDepth;
+            int depth = tun.tb_depth > 0 ? tun.tb_depth
+                                         : lsr::jacobi_tb_auto_depth(a, cond->check_every, max_iter);
             if (depth > 1 && (cond->check_every % depth != 0 || max_iter % depth != 0)) depth = 1;
             j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth);
             break;

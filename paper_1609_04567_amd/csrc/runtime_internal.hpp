@@ -43,9 +43,6 @@ constexpr int kDepth = 3;          // chunks in flight per job
 constexpr int kMirrorSlots = 4096; // pinned state mirrors per context
 constexpr double kChunkTargetUs = 1500.0;
 constexpr int kMaxChunk = 512;
-// Jacobi sweeps fused per launch when the tuning leaves the depth open (it is
-// still used only where it divides the check period and the sweep cap).
-constexpr int kAutoDepth = 1;
 
 // ---------------------------------------------------------------------------
 // Caching pool. Sizes are rounded to a class (powers of two below 2 MiB,

@@ -33,6 +33,8 @@
 // fixed order and writes one partial per tile.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace lsr {
@@ -209,22 +211,55 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
 // cells keep their value at every level, so nothing spreads across them.
 // Rows stream downwards: after level-0 row i is loaded, level j (1..K) computes
 // its row i-j from the last three rows of level j-1, each level keeping its own
-// three rows in registers, plus a ring of the last K rows of g. Level K rows in
-// [r0, r1) are stored (and reduced on a check sweep, against level K-1, the
-// previous sweep). Each level evaluates jacobi_update with that level's sweep
-// number, so the K-th iterate is bit-identical to K single sweeps. Rows and
-// columns outside the grid are zero-filled and never loaded; like the windows'
-// inner edges they cannot reach an interior cell through the fixed ring.
+// three rows in registers. The g rows go through a per-wavefront ring of K rows
+// in LDS (level j reads g row i-j), which keeps register moves out of the row
+// loop. Level K rows in [r0, r1) are stored (and reduced on a check sweep,
+// against level K-1, the previous sweep). Each level evaluates jacobi_update
+// with that level's sweep number, so the K-th iterate is bit-identical to K
+// single sweeps. Rows and columns outside the grid are zero-filled and never
+// loaded; like the windows' inner edges they cannot reach an interior cell
+// through the fixed ring.
+//
+// Horizontal neighbours move between lanes with DPP wave shifts (gfx9
+// wave_shr:1 / wave_shl:1, a VALU move with no LDS round trip); lane 0 gets 0
+// from the west and lane 63 gets 0 from the east, which only feeds columns that
+// are never stored. Per-lane selects for the ring columns are only evaluated in
+// the two windows that hold column 0 or cols-1; elsewhere a row is either
+// updated or carried unchanged as a whole.
 template <int VEC, int K>
 constexpr int tb_out_width() { return (64 * VEC - 2 * K) / VEC * VEC; }
 
-template <typename T, bool HELM, int VEC, int NW, int K, int U, bool NT, bool NTG>
+constexpr int kDppWaveShr1 = 0x138;  // lane l receives lane l-1
+constexpr int kDppWaveShl1 = 0x130;  // lane l receives lane l+1
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float x) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// LDS the tile needs for the g ring, in elements of T.
+template <int VEC, int NW, int K>
+constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
+
+template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
                                                 uint32_t sweep0, bool check, int red, int t,
                                                 int strips, int tile_rows,
-                                                double* __restrict__ partials, double* lds) {
+                                                double* __restrict__ partials, double* lds,
+                                                T* gring) {
+    typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
     const int band = t / strips, strip = t - band * strips;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -234,123 +269,162 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     const int64_t ohi = min(cw + K + (int64_t)OW, cols - 1);
     const int64_t r0 = 1 + (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows - 1);
+    // level-0 rows r0-K .. r1+K-1 stream through, three per iteration (the
+    // rows past r1+K-1 that round the count up are computed and never stored)
+    const int64_t i_beg = r0 - K;
+    const int64_t i_end = i_beg + (r1 + K - i_beg + 2) / 3 * 3;
+    // the window holds a ring column: per-lane selects needed
+    const bool edge = (cw == 0) || (cw + 64 * VEC > cols - 1);
+    // every row a level computes (r0-2K .. i_end-2) is interior and every
+    // level-0 row loaded is in the grid: no row or column tests at all
+    const bool fast = !edge && r0 - 2 * K >= 1 && i_end <= rows;
+    const bool vec_ok = c + VEC <= cols;
+    const bool store_vec = c >= olo && c + VEC <= ohi;
+    V* ring = reinterpret_cast<V*>(gring) + (size_t)wave * K * 64 + lane;  // slot s at ring[s * 64]
 
-    // window element e of this lane is at column c + e; loads only inside the grid
-    auto load = [&](const T* __restrict__ base, int64_t row, T (&v)[VEC], bool nt) {
+    // W[j][s]: three rows of level j in registers; the slot that receives a
+    // level's new row rotates with the row index (phase P = step % 3), so the
+    // rows never move between registers
+    T W[K][3][VEC];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) W[j][s2][e] = T(0);
+    if (HELM) {
+        V z;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) z[e] = T(0);
+#pragma unroll
+        for (int s2 = 0; s2 < K; ++s2) ring[s2 * 64] = z;
+    }
+    double acc = 0.0;
+    int slot = 0;   // ring slot of g row (i - 1) at step i
+
+    auto load = [&](auto fast_tag, const T* __restrict__ base, int64_t row, T (&v)[VEC], bool nt) {
+        constexpr bool FAST = decltype(fast_tag)::value;
+        const T* p = base + row * pitch;
+        if (FAST) {
+            const V x = nt ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p + c))
+                           : *reinterpret_cast<const V*>(p + c);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = x[e];
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < VEC; ++e) v[e] = T(0);
         if (row < 0 || row >= rows) return;
-        const T* p = base + row * pitch;
-        if (VEC > 1 && c >= 0 && c + VEC <= cols) {
-            typedef T V __attribute__((ext_vector_type(VEC)));
-            V x = nt ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p + c))
-                     : *reinterpret_cast<const V*>(p + c);
+        if (vec_ok) {
+            const V x = nt ? __builtin_nontemporal_load(reinterpret_cast<const V*>(p + c))
+                           : *reinterpret_cast<const V*>(p + c);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) v[e] = x[e];
         } else {
 #pragma unroll
             for (int e = 0; e < VEC; ++e)
-                if (c + e >= 0 && c + e < cols) v[e] = p[c + e];
+                if (c + e < cols) v[e] = p[c + e];
         }
     };
 
-    T Wn[K][3][VEC];   // level j: rows (newest - 2, newest - 1, newest)
-    T G[K][VEC];       // G[m] = g row (i - 1 - m) at step i
+    // one stream step: level-0 row i arrives in slot P of every level's triple
+    auto step = [&](auto fast_tag, auto phase, int64_t i, const T (&inrow)[VEC],
+                    const T (&grow)[VEC]) {
+        constexpr bool FAST = decltype(fast_tag)::value;
+        constexpr int P = decltype(phase)::value;
+        constexpr int PN = (P + 1) % 3, PC = (P + 2) % 3;   // older rows: north, centre
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+        for (int e = 0; e < VEC; ++e) W[0][P][e] = inrow[e];
+        if (HELM) {
+            V x;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            Wn[j][0][e] = Wn[j][1][e] = Wn[j][2][e] = T(0);
-            G[j][e] = T(0);
-        }
-
-    double acc = 0.0;
-    const int64_t i_beg = r0 - K, i_end = r1 + K;   // level-0 rows streamed
-    for (int64_t i0 = i_beg; i0 < i_end; i0 += U) {
-        T in[U][VEC], gin[U][VEC];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (i0 + q < i_end) {
-                load(a, i0 + q, in[q], false);
-                if (HELM) load(g, i0 + q - 1, gin[q], NTG);
-            }
+            for (int e = 0; e < VEC; ++e) x[e] = grow[e];
+            ring[slot * 64] = x;   // g row i-1
         }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int64_t i = i0 + q;
-            if (i >= i_end) break;
-            // shift in level-0 row i and g row i-1
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                Wn[0][0][e] = Wn[0][1][e];
-                Wn[0][1][e] = Wn[0][2][e];
-                Wn[0][2][e] = in[q][e];
-            }
+        for (int j = 1; j <= K; ++j) {
+            const int64_t row = i - j;
+            const T(&src)[3][VEC] = W[j - 1];
+            const T wl = lane_shift<kDppWaveShr1>(src[PC][VEC - 1]);
+            const T er = lane_shift<kDppWaveShl1>(src[PC][0]);
+            T gv[VEC];
             if (HELM) {
+                int s2 = slot - (j - 1);
+                if (s2 < 0) s2 += K;
+                const V x = ring[s2 * 64];   // g row i - j
 #pragma unroll
-                for (int m = K - 1; m > 0; --m)
+                for (int e = 0; e < VEC; ++e) gv[e] = x[e];
+            } else {
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) G[m][e] = G[m - 1][e];
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) G[0][e] = gin[q][e];
+                for (int e = 0; e < VEC; ++e) gv[e] = T(0);
             }
-            // level j computes row i - j from level j-1 (centre row i - j)
-#pragma unroll
-            for (int j = 1; j <= K; ++j) {
-                const int64_t row = i - j;
-                const T(&src)[3][VEC] = Wn[j - 1];
-                T wl = __shfl_up(src[1][VEC - 1], 1, 64);
-                T er = __shfl_down(src[1][0], 1, 64);
-                if (lane == 0) wl = T(0);
-                if (lane == 63) er = T(0);
-                T nv[VEC];
-                const bool row_inner = row >= 1 && row <= rows - 2;
+            T nv[VEC];
+            if (FAST || (row >= 1 && row <= rows - 2)) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
-                    const T Wv = (e > 0) ? src[1][e - 1] : wl;
-                    const T Ev = (e < VEC - 1) ? src[1][e + 1] : er;
-                    const int64_t col = c + e;
-                    const bool inner = row_inner && col >= 1 && col <= cols - 2;
-                    const T upd = jacobi_update<T, HELM>(src[0][e], src[2][e], Wv, Ev,
-                                                         HELM ? G[j - 1][e] : T(0), rd, rd_lo, row,
-                                                         col, sweep0 + (uint32_t)(j - 1));
-                    nv[e] = inner ? upd : src[1][e];
+                    const T Wv = (e > 0) ? src[PC][e - 1] : wl;
+                    const T Ev = (e < VEC - 1) ? src[PC][e + 1] : er;
+                    nv[e] = jacobi_update<T, HELM>(src[PN][e], src[P][e], Wv, Ev, gv[e], rd, rd_lo,
+                                                   row, c + e, sweep0 + (uint32_t)(j - 1));
                 }
-                if (j < K) {
+                if (!FAST && edge) {
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        Wn[j][0][e] = Wn[j][1][e];
-                        Wn[j][1][e] = Wn[j][2][e];
-                        Wn[j][2][e] = nv[e];
+                        const int64_t col = c + e;
+                        if (col < 1 || col > cols - 2) nv[e] = src[PC][e];
                     }
-                } else if (row >= r0 && row < r1) {
-                    T* p = b + row * pitch;
-                    if (VEC > 1 && c >= olo && c + VEC <= ohi) {
-                        typedef T V __attribute__((ext_vector_type(VEC)));
-                        V x;
+                }
+            } else {
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) x[e] = nv[e];
-                        if (NT) __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + c));
-                        else *reinterpret_cast<V*>(p + c) = x;
-                        if (check) {
+                for (int e = 0; e < VEC; ++e) nv[e] = src[PC][e];
+            }
+            if (j < K) {
 #pragma unroll
-                            for (int e = 0; e < VEC; ++e)
-                                acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[1][e]);
-                        }
-                    } else {
+                for (int e = 0; e < VEC; ++e) W[j][P][e] = nv[e];
+            } else if (row >= r0 && row < r1) {
+                T* p = b + row * pitch;
+                if (store_vec) {
+                    V x;
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) {
-                            const int64_t col = c + e;
-                            if (col >= olo && col < ohi) {
-                                p[col] = nv[e];
-                                if (check) acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[1][e]);
-                            }
+                    for (int e = 0; e < VEC; ++e) x[e] = nv[e];
+                    if (NT) __builtin_nontemporal_store(x, reinterpret_cast<V*>(p + c));
+                    else *reinterpret_cast<V*>(p + c) = x;
+                    if (check) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[PC][e]);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const int64_t col = c + e;
+                        if (col >= olo && col < ohi) {
+                            p[col] = nv[e];
+                            if (check) acc = jacobi_accum(red, acc, (double)nv[e] - (double)src[PC][e]);
                         }
                     }
                 }
             }
         }
-    }
+        slot = (slot + 1 == K) ? 0 : slot + 1;
+    };
+
+    auto stream = [&](auto fast_tag) {
+        for (int64_t i0 = i_beg; i0 < i_end; i0 += 3) {
+            T in[3][VEC], gin[3][VEC];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                load(fast_tag, a, i0 + q, in[q], false);
+                if (HELM) load(fast_tag, g, i0 + q - 1, gin[q], NTG);
+            }
+            step(fast_tag, std::integral_constant<int, 0>{}, i0, in[0], gin[0]);
+            step(fast_tag, std::integral_constant<int, 1>{}, i0 + 1, in[1], gin[1]);
+            step(fast_tag, std::integral_constant<int, 2>{}, i0 + 2, in[2], gin[2]);
+        }
+    };
+    if (fast) stream(std::true_type{});
+    else stream(std::false_type{});
+
     if (check) {
         const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
         if (threadIdx.x == 0) partials[t] = v;

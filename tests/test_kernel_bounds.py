@@ -175,6 +175,14 @@ def _tb_model(u, k, vec, nw, tile_rows):
             ohi = min(cw + k + ow, cols - 1)
             if vec > 1 and cw % vec:
                 loads_ok = False         # windows must start 16-byte aligned
+            # rows stream in groups of three; the unguarded (fast) path must only
+            # touch rows and columns inside the grid
+            i_beg = r0 - k
+            i_end = i_beg + (r1 + k - i_beg + 2) // 3 * 3
+            edge = cw == 0 or cw + width > cols - 1
+            fast = not edge and r0 - 2 * k >= 1 and i_end <= rows
+            if fast and not (i_beg - 1 >= 0 and i_end <= rows and cw + width <= cols):
+                loads_ok = False
             level = {}
             for i in range(r0 - k, r1 + k):
                 row = np.zeros(width)
@@ -204,8 +212,8 @@ def _tb_model(u, k, vec, nw, tile_rows):
 @pytest.mark.parametrize("rows,cols", [(3, 3), (4, 5), (9, 130), (40, 131), (37, 260), (20, 517),
                                        (70, 250)])
 @pytest.mark.parametrize("vec", [2, 4])
-@pytest.mark.parametrize("k", [2, 4, 5])
-@pytest.mark.parametrize("nw,tile_rows", [(1, 8), (2, 16), (4, 64)])
+@pytest.mark.parametrize("k", [2, 4, 5, 8, 10])
+@pytest.mark.parametrize("nw,tile_rows", [(1, 5), (2, 16), (4, 64)])
 def test_tb_schedule_covers_interior_and_matches_k_sweeps(rows, cols, vec, k, nw, tile_rows):
     rng = np.random.default_rng(rows * 1000 + cols)
     u = rng.standard_normal((rows, cols))
@@ -224,7 +232,7 @@ def test_tb_schedule_covers_interior_and_matches_k_sweeps(rows, cols, vec, k, nw
 
 @pytest.mark.parametrize("rows,cols", [(8192, 8192), (4096, 4096), (8191, 8190), (2049, 2049)])
 @pytest.mark.parametrize("vec", [2, 4])
-@pytest.mark.parametrize("k", [2, 4, 5])
+@pytest.mark.parametrize("k", [2, 4, 5, 8, 10])
 def test_tb_stores_stay_in_interior_at_full_size(rows, cols, vec, k):
     """Window arithmetic at the benchmark sizes: stores inside [1, cols-1), loads aligned."""
     ow, strips, bands = _tb_geometry(rows, cols, vec, 1, k, 64)
