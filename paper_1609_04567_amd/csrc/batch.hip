@@ -1,14 +1,18 @@
 // Batched execution of many grids of uneven size: one launch sweeps every tile
 // of every active job, one launch then folds each job's partials and evaluates
 // its condition. A "round" is these two launches; every active job advances by
-// one sweep per round, finished jobs' tiles exit at entry, and the host engine
-// rebuilds the work list between windows of rounds (continuous batching).
+// its step (1 sweep, or K sweeps for a job on a fused-depth family), finished
+// jobs' tiles exit at entry, and the host engine rebuilds the work list between
+// windows of rounds (continuous batching).
 //
-// Each job keeps its own state (completed sweeps n, reduce value, stop flags),
-// its own partials and its own ping-pong parity (sweep n+1 reads buf[n % 2]).
-// A job's tile geometry depends only on its shape, dtype and alignment (see
-// batch_geometry), never on the batch it shares, so the fold order of its reduce
-// and hence every result is the same alone and in a mix.
+// A tile belongs to one wavefront: a workgroup of four wavefronts runs four work
+// items, possibly of four different jobs, so a narrow grid occupies only the
+// wavefronts its columns need. Each job keeps its own state (completed sweeps n,
+// reduce value, stop flags), its own partials and its own ping-pong parity
+// (its launch number n / step selects the source buffer). A job's tile geometry
+// and family depend only on its shape, dtype and condition (see
+// batch_geometry), never on the batch it shares, so the fold order of its
+// reduce and hence every result is the same alone and in a mix.
 #include "kernels.hpp"
 #include "tile_jacobi.hpp"
 #include "tile_life.hpp"
@@ -17,67 +21,100 @@ namespace lsr {
 namespace {
 
 constexpr int kBatchThreads = 256;
+constexpr int kWavesPerGroup = kBatchThreads / 64;
 constexpr int kJacTileRows = 8;
 constexpr int kLifeTileRows = 32;
-constexpr int kLifeGenericMax = 2048;
 
-template <typename T, int VEC, int U, bool NT>
+template <typename T, int VEC>
 __device__ __forceinline__ void jac_tile(const BatchJob& J, const void* src, void* dst, bool check,
-                                         uint32_t sweep, int t, double* lds) {
+                                         uint32_t sweep, int t) {
     const T* a = static_cast<const T*>(src);
     T* b = static_cast<T*>(dst);
     const T* g = static_cast<const T*>(J.env);
     double* parts = static_cast<double*>(J.partials);
     if (J.helm)
-        jacobi5_tile<T, true, VEC, 4, U, NT, NT>(a, b, g, J.rows, J.cols, J.pitch, (T)J.rd,
-                                                 (T)(0.25 - J.rd), sweep, check,
-                                                 J.ctl.reduce, t, J.strips, J.tile_rows, parts, lds);
+        jacobi5_tile<T, true, VEC, 1, 4, true, true, false, true>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep, check,
+            J.ctl.reduce, t, J.strips, J.tile_rows, parts, nullptr);
     else
-        jacobi5_tile<T, false, VEC, 4, U, NT, false>(a, b, g, J.rows, J.cols, J.pitch, (T)J.rd,
-                                                     (T)0, sweep, check, J.ctl.reduce, t, J.strips, J.tile_rows,
-                                                     parts, lds);
+        jacobi5_tile<T, false, VEC, 1, 4, true, false, false, true>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep, check, J.ctl.reduce, t,
+            J.strips, J.tile_rows, parts, nullptr);
 }
 
-// Tiles of one kernel family; the work list segment of this launch holds only
+template <typename T, int VEC, int K>
+__device__ __forceinline__ void jac_tb_tile(const BatchJob& J, const void* src, void* dst,
+                                            bool check, uint32_t sweep0, int t, T* gring) {
+    const T* a = static_cast<const T*>(src);
+    T* b = static_cast<T*>(dst);
+    const T* g = static_cast<const T*>(J.env);
+    double* parts = static_cast<double*>(J.partials);
+    if (J.helm)
+        jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, check,
+            J.ctl.reduce, t, J.strips, J.tile_rows, parts, nullptr, gring);
+    else
+        jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, check, J.ctl.reduce, t,
+            J.strips, J.tile_rows, parts, nullptr, gring);
+}
+
+template <int KIND> struct KindInfo {
+    static constexpr int step = 1;
+    static constexpr int ring = 1;   // LDS elements of T for the g rings
+};
+template <> struct KindInfo<BK_JAC_F64_TB10> { static constexpr int step = 10, ring = tb_gring_elems<2, kWavesPerGroup, 10>(); };
+template <> struct KindInfo<BK_JAC_F64_TB5> { static constexpr int step = 5, ring = tb_gring_elems<2, kWavesPerGroup, 5>(); };
+template <> struct KindInfo<BK_JAC_F64_TB2> { static constexpr int step = 2, ring = tb_gring_elems<2, kWavesPerGroup, 2>(); };
+template <> struct KindInfo<BK_JAC_F32_TB5> { static constexpr int step = 5, ring = tb_gring_elems<4, kWavesPerGroup, 5>(); };
+template <> struct KindInfo<BK_JAC_F32_TB2> { static constexpr int step = 2, ring = tb_gring_elems<4, kWavesPerGroup, 2>(); };
+
+// Work items of one kernel family; the work list segment of this launch holds only
 // jobs of that family (one launch per family keeps each its own register budget).
 template <int KIND>
 __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJob* __restrict__ jobs,
                                                                     const WorkItem* __restrict__ work) {
-    __shared__ double lds_d[kBatchThreads / 64];
-    __shared__ unsigned long long lds_u[kBatchThreads / 64];
-    const WorkItem w = work[xcd_logical_tile(blockIdx.x, gridDim.x)];
+    constexpr int STEP = KindInfo<KIND>::step;
+    constexpr bool F64TB = KIND == BK_JAC_F64_TB10 || KIND == BK_JAC_F64_TB5 || KIND == BK_JAC_F64_TB2;
+    constexpr bool F32TB = KIND == BK_JAC_F32_TB5 || KIND == BK_JAC_F32_TB2;
+    __shared__ __attribute__((aligned(16))) double ring_d[F64TB ? KindInfo<KIND>::ring : 1];
+    __shared__ __attribute__((aligned(16))) float ring_f[F32TB ? KindInfo<KIND>::ring : 1];
+    const int wave = threadIdx.x >> 6;
+    const WorkItem w = work[xcd_logical_tile(blockIdx.x, gridDim.x) * kWavesPerGroup + wave];
     if (w.job < 0) return;
     const BatchJob& J = jobs[w.job];
     if (__hip_atomic_load(&J.st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int64_t n = __hip_atomic_load(&J.st->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (n >= J.ctl.max_iter) return;
-    const bool check = is_check_sweep(n + 1, J.ctl);
-    const void* src = J.buf[n & 1];
-    void* dst = const_cast<void*>(J.buf[(n + 1) & 1]);
+    // sweeps n+1 .. n+STEP (STEP divides the check period and the cap)
+    const bool check = is_check_sweep(n + STEP, J.ctl);
+    const int64_t launch = n / STEP;
+    const void* src = J.buf[launch & 1];
+    void* dst = const_cast<void*>(J.buf[(launch + 1) & 1]);
     const uint32_t sw = (uint32_t)(n + 1);
-    if (KIND == BK_JAC_F64_V2) jac_tile<double, 2, 8, true>(J, src, dst, check, sw, w.tile, lds_d);
-    if (KIND == BK_JAC_F64_V1) jac_tile<double, 1, 4, false>(J, src, dst, check, sw, w.tile, lds_d);
-    if (KIND == BK_JAC_F32_V4) jac_tile<float, 4, 8, true>(J, src, dst, check, sw, w.tile, lds_d);
-    if (KIND == BK_JAC_F32_V1) jac_tile<float, 1, 4, false>(J, src, dst, check, sw, w.tile, lds_d);
+    if (KIND == BK_JAC_F64_V2) jac_tile<double, 2>(J, src, dst, check, sw, w.tile);
+    if (KIND == BK_JAC_F32_V4) jac_tile<float, 4>(J, src, dst, check, sw, w.tile);
+    if (KIND == BK_JAC_F64_TB10) jac_tb_tile<double, 2, 10>(J, src, dst, check, sw, w.tile, ring_d);
+    if (KIND == BK_JAC_F64_TB5) jac_tb_tile<double, 2, 5>(J, src, dst, check, sw, w.tile, ring_d);
+    if (KIND == BK_JAC_F64_TB2) jac_tb_tile<double, 2, 2>(J, src, dst, check, sw, w.tile, ring_d);
+    if (KIND == BK_JAC_F32_TB5) jac_tb_tile<float, 4, 5>(J, src, dst, check, sw, w.tile, ring_f);
+    if (KIND == BK_JAC_F32_TB2) jac_tb_tile<float, 4, 2>(J, src, dst, check, sw, w.tile, ring_f);
     if (KIND == BK_LIFE_SWAR)
-        life_swar_tile<4, 2, true>(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst),
-                                   J.rows, J.cols, J.pitch, J.torus, check, w.tile, J.strips,
-                                   J.tile_rows, static_cast<unsigned long long*>(J.partials), lds_u);
-    if (KIND == BK_LIFE_GEN)
-        life_generic_tile(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), J.rows,
-                          J.cols, J.pitch, J.torus, check, w.tile, J.tiles,
-                          static_cast<unsigned long long*>(J.partials), lds_u);
+        life_swar_tile<1, 8, true, true>(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst),
+                                         J.rows, J.cols, J.pitch, J.torus, check, w.tile, J.strips,
+                                         J.tile_rows, static_cast<unsigned long long*>(J.partials),
+                                         nullptr);
 }
 
-// One workgroup per job: count the sweep, and on a check sweep fold the job's
-// partials in index order and evaluate its condition.
+// One workgroup per job: count the job's step, and on a check sweep fold the
+// job's partials in index order and evaluate its condition.
 __global__ __launch_bounds__(kBatchThreads) void batch_finalize_kernel(const BatchJob* __restrict__ jobs) {
     __shared__ double lds_d[kBatchThreads / 64];
     __shared__ unsigned long long lds_u[kBatchThreads / 64];
     const BatchJob& J = jobs[blockIdx.x];
     JobState* st = J.st;
     if (st->done) return;
-    const int64_t n1 = st->n + 1;
+    const int64_t n1 = st->n + J.step;
     if (n1 > J.ctl.max_iter) return;
     const bool check = is_check_sweep(n1, J.ctl);
     double rd = 0.0;
@@ -97,47 +134,58 @@ __global__ __launch_bounds__(kBatchThreads) void batch_finalize_kernel(const Bat
     publish_state(st, J.mirror, s);
 }
 
+template <int KIND>
+void launch_kind(const BatchJob* jobs, const WorkItem* work, int groups, hipStream_t s) {
+    hipLaunchKernelGGL(batch_sweep_kernel<KIND>, dim3(groups), dim3(kBatchThreads), 0, s, jobs, work);
+}
+
 }  // namespace
 
-void batch_geometry(BatchJob& j, int is_life, int f32, uintptr_t align_bits) {
-    const bool aligned16 = (align_bits & 15) == 0;
+void batch_geometry(BatchJob& j, int is_life, int f32) {
+    j.step = 1;
     if (is_life) {
-        if (j.cols % 16 == 0 && j.pitch % 16 == 0 && aligned16) {
-            j.kind = BK_LIFE_SWAR;
-            j.tile_rows = kLifeTileRows;
-            const int64_t span = 4 * 1024;
-            j.strips = (int)((j.cols + span - 1) / span);
-            j.tiles = j.strips * (int)((j.rows + kLifeTileRows - 1) / kLifeTileRows);
-        } else {
-            j.kind = BK_LIFE_GEN;
-            j.tile_rows = 0;
-            j.strips = 0;
-            const int64_t need = (j.rows * j.cols + 255) / 256;
-            j.tiles = (int)(need < kLifeGenericMax ? need : kLifeGenericMax);
-        }
+        // rows are 16-byte aligned with zeroed padding to a multiple of 16 cells
+        j.kind = BK_LIFE_SWAR;
+        j.tile_rows = kLifeTileRows;
+        j.strips = (int)((j.cols + 1023) / 1024);
+        j.tiles = j.strips * (int)((j.rows + kLifeTileRows - 1) / kLifeTileRows);
         return;
     }
-    const int esz = f32 ? 4 : 8;
-    const int want = f32 ? 4 : 2;
-    const int vec = ((j.pitch * esz) % 16 == 0 && aligned16) ? want : 1;
-    j.kind = f32 ? (vec > 1 ? BK_JAC_F32_V4 : BK_JAC_F32_V1) : (vec > 1 ? BK_JAC_F64_V2 : BK_JAC_F64_V1);
-    j.tile_rows = kJacTileRows;
-    const int64_t span = (int64_t)4 * 64 * vec;
-    j.strips = (int)((j.cols + span - 1) / span);
-    j.tiles = j.strips * (int)((j.rows - 2 + kJacTileRows - 1) / kJacTileRows);
+    // rows are 16-byte aligned (the engine stages any other grid)
+    const int vec = f32 ? 4 : 2;
+    int depth = 1;
+    for (int k : f32 ? std::initializer_list<int>{5, 2} : std::initializer_list<int>{10, 5, 2})
+        if (j.ctl.check_every % k == 0 && j.ctl.max_iter % k == 0) { depth = k; break; }
+    if (depth == 1) {
+        j.kind = f32 ? BK_JAC_F32_V4 : BK_JAC_F64_V2;
+        j.tile_rows = kJacTileRows;
+        j.strips = (int)((j.cols + 64 * vec - 1) / (64 * vec));
+    } else {
+        j.kind = f32 ? (depth == 5 ? BK_JAC_F32_TB5 : BK_JAC_F32_TB2)
+                     : (depth == 10 ? BK_JAC_F64_TB10 : depth == 5 ? BK_JAC_F64_TB5 : BK_JAC_F64_TB2);
+        j.step = depth;
+        j.tile_rows = depth >= 8 ? 48 : 32;
+        const int64_t ow = (64 * vec - 2 * depth) / vec * vec;
+        const int64_t need = j.cols - 1 - depth;
+        j.strips = (int)(need > 0 ? (need + ow - 1) / ow : 1);
+    }
+    j.tiles = j.strips * (int)((j.rows - 2 + j.tile_rows - 1) / j.tile_rows);
 }
 
 hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
                               int nwork_padded, hipStream_t s) {
     if (nwork_padded <= 0) return hipSuccess;
-    const dim3 g(nwork_padded), b(kBatchThreads);
+    if (nwork_padded % (kWavesPerGroup * kXcds)) return hipErrorInvalidValue;
+    const int groups = nwork_padded / kWavesPerGroup;
     switch (kind) {
-        case BK_JAC_F64_V2: hipLaunchKernelGGL(batch_sweep_kernel<BK_JAC_F64_V2>, g, b, 0, s, jobs, work); break;
-        case BK_JAC_F64_V1: hipLaunchKernelGGL(batch_sweep_kernel<BK_JAC_F64_V1>, g, b, 0, s, jobs, work); break;
-        case BK_JAC_F32_V4: hipLaunchKernelGGL(batch_sweep_kernel<BK_JAC_F32_V4>, g, b, 0, s, jobs, work); break;
-        case BK_JAC_F32_V1: hipLaunchKernelGGL(batch_sweep_kernel<BK_JAC_F32_V1>, g, b, 0, s, jobs, work); break;
-        case BK_LIFE_SWAR: hipLaunchKernelGGL(batch_sweep_kernel<BK_LIFE_SWAR>, g, b, 0, s, jobs, work); break;
-        case BK_LIFE_GEN: hipLaunchKernelGGL(batch_sweep_kernel<BK_LIFE_GEN>, g, b, 0, s, jobs, work); break;
+        case BK_JAC_F64_V2: launch_kind<BK_JAC_F64_V2>(jobs, work, groups, s); break;
+        case BK_JAC_F32_V4: launch_kind<BK_JAC_F32_V4>(jobs, work, groups, s); break;
+        case BK_JAC_F64_TB10: launch_kind<BK_JAC_F64_TB10>(jobs, work, groups, s); break;
+        case BK_JAC_F64_TB5: launch_kind<BK_JAC_F64_TB5>(jobs, work, groups, s); break;
+        case BK_JAC_F64_TB2: launch_kind<BK_JAC_F64_TB2>(jobs, work, groups, s); break;
+        case BK_JAC_F32_TB5: launch_kind<BK_JAC_F32_TB5>(jobs, work, groups, s); break;
+        case BK_JAC_F32_TB2: launch_kind<BK_JAC_F32_TB2>(jobs, work, groups, s); break;
+        case BK_LIFE_SWAR: launch_kind<BK_LIFE_SWAR>(jobs, work, groups, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

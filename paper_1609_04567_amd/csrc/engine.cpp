@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kMaxBatch = 4096;          // active jobs (the pinned mirror slots)
 constexpr int64_t kMaxWork = 1 << 21;    // tiles of all active jobs
-constexpr int kPad = 8 * (lsr::kBatchKinds + 1);
+constexpr int kPad = lsr::kBatchWorkQuantum * (lsr::kBatchKinds + 1);
 constexpr double kWindowUs = 1500.0;     // device time per window of rounds
 constexpr double kRoundOverheadUs = 12.0;
 constexpr int kMaxRounds = 64;
@@ -67,19 +67,19 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     const lsr_grid& g = j->grid;
     const bool life = j->stencil == LSR_ST_LIFE;
     const bool f32 = g.dtype == LSR_F32;
+    j->xgrid = g;
+    j->staged = needs_staging(g, j->stencil);
+    if (j->staged) j->xgrid.pitch = stage_pitch(g);   // buffers assigned at admission
     lsr::BatchJob& d = j->desc;
     d = lsr::BatchJob{};
-    d.buf[0] = g.data;
-    d.env = g.env0;
+    d.buf[0] = j->staged ? nullptr : g.data;
+    d.env = j->staged ? nullptr : g.env0;
     d.rows = g.rows;
     d.cols = g.cols;
-    d.pitch = g.pitch;
+    d.pitch = j->xgrid.pitch;
     d.helm = j->stencil == LSR_ST_HELMHOLTZ5;
     d.torus = g.bc == LSR_BC_TORUS;
     d.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
-    uintptr_t align = reinterpret_cast<uintptr_t>(g.data);
-    if (d.helm) align |= reinterpret_cast<uintptr_t>(g.env0);
-    lsr::batch_geometry(d, life, f32, align);
     lsr::LoopCtl& c = d.ctl;
     c.max_iter = j->max_iter;
     c.check_every = j->cond.check_every;
@@ -87,11 +87,13 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     c.reduce = j->ctl.reduce;
     c.cond = j->cond.kind;
     c.stable_window = j->cond.stable_window;
-    c.nparts = d.tiles;
     c.threshold = j->cond.threshold;
     c.mean_div = (double)g.rows * (double)g.cols;
+    // rows are aligned (or staged into aligned copies, 256-byte aligned pool blocks)
+    lsr::batch_geometry(d, life, f32);
+    c.nparts = d.tiles;
     const size_t esz = dtype_size(g.dtype);
-    j->bytes = (size_t)g.rows * (size_t)g.pitch * esz;
+    j->bytes = (size_t)g.rows * (size_t)j->xgrid.pitch * esz;
     j->nparts_alloc = std::max(d.tiles, life ? lsr::count_u8_parts(g.rows, g.cols) : 1);
     const double per_cell = life ? 2.0 : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
@@ -130,13 +132,19 @@ lsr_status lsr_ctx::engine_admit() {
         void* partner = nullptr;
         void* parts = nullptr;
         void* st = nullptr;
+        void* s0 = nullptr;
+        void* senv = nullptr;
         lsr_status s = pool.alloc(j->bytes, &partner);
         if (s == LSR_OK) s = pool.alloc((size_t)j->nparts_alloc * 8, &parts);
         if (s == LSR_OK) s = pool.alloc(sizeof(lsr::JobState), &st);
+        if (s == LSR_OK && j->staged) s = pool.alloc(j->bytes, &s0);
+        if (s == LSR_OK && j->staged && j->desc.helm) s = pool.alloc(j->bytes, &senv);
         if (s != LSR_OK) {
             pool.release(partner);
             pool.release(parts);
             pool.release(st);
+            pool.release(s0);
+            pool.release(senv);
             if (!active.empty() || !retiring.empty()) return LSR_OK;  // wait for memory
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -159,6 +167,16 @@ lsr_status lsr_ctx::engine_admit() {
         j->buf[1] = partner;
         j->partials = parts;
         j->st = static_cast<lsr::JobState*>(st);
+        if (j->staged) {
+            j->buf[0] = s0;
+            j->stage_env = senv;
+            j->xgrid.data = s0;
+            j->xgrid.env0 = senv;
+            j->desc.buf[0] = s0;
+            j->desc.env = senv;
+        } else {
+            j->buf[0] = j->grid.data;
+        }
         j->mirror_host = mirrors_host + j->slot;
         j->mirror_dev = mirrors_dev + j->slot;
         std::memset((void*)j->mirror_host, 0, sizeof(lsr::JobState));
@@ -167,10 +185,22 @@ lsr_status lsr_ctx::engine_admit() {
         d.st = j->st;
         d.partials = parts;
         d.mirror = j->mirror_dev;
-        const lsr_grid& g = j->grid;
+        const lsr_grid& g = j->xgrid;
+        const lsr_grid& ug = j->grid;
         const size_t esz = dtype_size(g.dtype);
         HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
         HIP_TRY(hipEventRecord(j->ev_begin, stream));
+        if (j->staged) {
+            if (j->stencil == LSR_ST_LIFE) {   // padding cells start (and stay) 0/1
+                HIP_TRY(hipMemsetAsync(s0, 0, (size_t)g.rows * g.pitch * esz, stream));
+                HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, stream));
+            }
+            HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
+                                     g.rows, hipMemcpyDeviceToDevice, stream));
+            if (senv)
+                HIP_TRY(hipMemcpy2DAsync(senv, g.pitch * esz, ug.env0, ug.pitch * esz, g.cols * esz,
+                                         g.rows, hipMemcpyDeviceToDevice, stream));
+        }
         if (j->stencil == LSR_ST_LIFE) {
             int np = 0;
             HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
@@ -200,7 +230,7 @@ lsr_status lsr_ctx::engine_upload() {
             if (hj[i].kind != k) continue;
             for (int t = 0; t < hj[i].tiles; ++t) hw[pos++] = lsr::WorkItem{i, t};
         }
-        while ((pos - seg_off[k]) % lsr::kXcds) hw[pos++] = lsr::WorkItem{-1, 0};
+        while ((pos - seg_off[k]) % lsr::kBatchWorkQuantum) hw[pos++] = lsr::WorkItem{-1, 0};
         seg_len[k] = (int)(pos - seg_off[k]);
     }
     if (n > 0) HIP_TRY(hipMemcpyAsync(d_jobs, hj, sizeof(lsr::BatchJob) * n, hipMemcpyHostToDevice, stream));
@@ -237,10 +267,15 @@ void lsr_ctx::engine_scan() {
         }
         lsr::JobState fin;
         std::memcpy(&fin, (const void*)m, sizeof fin);
-        const lsr_grid& g = j->grid;
+        const lsr_grid& g = j->xgrid;
+        const lsr_grid& ug = j->grid;
         const size_t esz = dtype_size(g.dtype);
         hipError_t e = hipSuccess;
-        if (fin.n & 1)
+        const int last = (int)((fin.n / j->desc.step) & 1);   // buffer holding sweep n
+        if (j->staged)
+            e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream);
+        else if (last)
             e = hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream);
         if (e == hipSuccess) e = hipEventRecord(j->ev_end, stream);
@@ -250,7 +285,7 @@ void lsr_ctx::engine_scan() {
         r.last_count = fin.count;
         r.converged = fin.converged;
         r.stable_run = fin.run;
-        r.sweeps_per_launch = 1;
+        r.sweeps_per_launch = j->desc.step;
         r.checks = fin.checks;
         r.status = fin.status == lsr::ST_NUMERIC ? LSR_ENUMERIC
                  : fin.status == lsr::ST_CANCELED ? LSR_ECANCELED : LSR_OK;
@@ -258,11 +293,7 @@ void lsr_ctx::engine_scan() {
             j->error = hipGetErrorString(e);
             r.status = LSR_EDEVICE;
         }
-        pool.release(j->buf[1]);
-        pool.release(j->partials);
-        pool.release(j->st);
-        j->buf[1] = j->partials = nullptr;
-        j->st = nullptr;
+        j->release_scratch(pool);
         {
             std::lock_guard<std::mutex> lk(mu);
             free_slots.push_back(j->slot);

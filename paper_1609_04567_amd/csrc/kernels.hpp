@@ -55,7 +55,11 @@ struct LifeArgs {
     uint8_t* b;
     int64_t rows, cols, pitch;
     int torus;
+    int padded;          // rows hold round_up(cols, 16) bytes, the padding zero at start
 };
+// Rows the SWAR kernel can sweep: 16-byte aligned, and a multiple of 16 cells
+// or padded. launch_life rejects anything else.
+bool life_rows_ok(const LifeArgs& a);
 SweepGeom life_geom(const LifeArgs& a, int tile_rows);
 hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
                        const LoopCtl& c, int j, hipStream_t s);
@@ -85,16 +89,22 @@ hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64
 // Kernel family of one job inside a batch; every batch kernel uses 256-thread
 // workgroups (4 wavefronts).
 enum BatchKind : int32_t {
-    BK_JAC_F64_V2 = 1,   // FP64 Jacobi, 16-byte vector path
-    BK_JAC_F64_V1 = 2,   // FP64 Jacobi, scalar path (unaligned / odd pitch)
-    BK_JAC_F32_V4 = 3,   // FP32 Jacobi, vector path
-    BK_JAC_F32_V1 = 4,   // FP32 Jacobi, scalar path
-    BK_LIFE_SWAR = 5,    // Life, 16 cells per lane
-    BK_LIFE_GEN = 6      // Life, one cell per thread
+    BK_JAC_F64_V2 = 1,     // FP64 Jacobi, one sweep per round
+    BK_JAC_F32_V4 = 2,     // FP32 Jacobi, one sweep per round
+    BK_JAC_F64_TB10 = 3,   // FP64 Jacobi, 10 fused sweeps per round
+    BK_JAC_F64_TB5 = 4,
+    BK_JAC_F64_TB2 = 5,
+    BK_JAC_F32_TB5 = 6,    // FP32 Jacobi, 5 fused sweeps per round
+    BK_JAC_F32_TB2 = 7,
+    BK_LIFE_SWAR = 8       // Life, 16 cells per lane
 };
+constexpr int kBatchKinds = 8;
 
 // Device descriptor of one job of a batch. The job's completed-sweep count n
-// lives in its JobState; sweep n+1 reads buf[n % 2] and writes buf[(n+1) % 2].
+// lives in its JobState; a round advances it by `step` sweeps, reading
+// buf[(n / step) % 2] and writing the other buffer. Rows of both buffers (and
+// env) are 16-byte aligned; Life rows hold round_up(cols, 16) bytes with the
+// padding starting at zero.
 struct BatchJob {
     const void* buf[2];
     const void* env;       // Helmholtz g, or null
@@ -104,20 +114,23 @@ struct BatchJob {
     int64_t rows, cols, pitch;
     double rd;
     LoopCtl ctl;
-    int32_t kind, helm, torus, strips, tiles, tile_rows;
+    int32_t kind, helm, torus, strips, tiles, tile_rows, step, pad_;
 };
 
 struct WorkItem {
     int32_t job;   // index into the batch's job table, -1 = idle padding
-    int32_t tile;  // tile of that job
+    int32_t tile;  // tile of that job (one wavefront's work)
 };
 
-// Tile geometry a job gets inside a batch: a function of its shape, dtype and
-// buffer alignment only, so its reduce order is the same alone and in any mix.
-void batch_geometry(BatchJob& j, int stencil_kind_life, int f32, uintptr_t align_bits);
-constexpr int kBatchKinds = 6;
+// Family, step and tile geometry a job gets inside a batch: a function of its
+// shape, dtype and loop control only (j.ctl must be set), so its reduce order is
+// the same alone and in any mix. Jacobi jobs take the deepest fused depth that
+// divides both the check period and the cap.
+void batch_geometry(BatchJob& j, int is_life, int f32);
 // One launch per kernel family: `work` points at that family's segment of the
-// work list (nwork_padded entries, a multiple of 8, idle entries have job -1).
+// work list (nwork_padded entries, a multiple of 32; idle entries have job -1).
+// A workgroup runs four consecutive entries, one per wavefront.
+constexpr int kBatchWorkQuantum = 32;
 hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
                               int nwork_padded, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchJob* jobs, int njobs, hipStream_t s);

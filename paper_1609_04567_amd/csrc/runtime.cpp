@@ -136,7 +136,7 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     void* src = j->buf[launch & 1];
     void* dst = j->buf[(launch + 1) & 1];
     hipError_t e = hipSuccess;
-    const lsr_grid& g = j->grid;
+    const lsr_grid& g = j->xgrid;
     switch (j->stencil) {
         case LSR_ST_LAPLACE5:
         case LSR_ST_HELMHOLTZ5: {
@@ -199,8 +199,20 @@ lsr_status lsr_ctx::enqueue_chunk_plain(Job* j, hipStream_t s) {
 lsr_status lsr_ctx::run_job(Job* j) {
     HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
     HIP_TRY(hipEventRecord(j->ev_begin, stream));
-    const lsr_grid& g = j->grid;
+    const lsr_grid& g = j->xgrid;
+    const lsr_grid& ug = j->grid;   // the caller's grid
     const size_t esz = dtype_size(g.dtype);
+    if (j->staged) {
+        if (j->stencil == LSR_ST_LIFE) {   // padding cells start (and stay) 0/1
+            HIP_TRY(hipMemsetAsync(j->buf[0], 0, (size_t)g.rows * g.pitch * esz, stream));
+            HIP_TRY(hipMemsetAsync(j->buf[1], 0, (size_t)g.rows * g.pitch * esz, stream));
+        }
+        HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+        if (j->stage_env)
+            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * esz, ug.env0, ug.pitch * esz,
+                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream));
+    }
     // Partner buffer starts as a copy: boundary ring (Jacobi) and unflagged
     // pixels (restoration) are never rewritten, so both buffers must hold them.
     if (j->stencil != LSR_ST_LIFE)
@@ -283,7 +295,11 @@ lsr_status lsr_ctx::run_job(Job* j) {
     lsr::JobState fin;
     std::memcpy(&fin, (const void*)mir, sizeof fin);
     // the stop sweep is a multiple of tb; launch parity says which buffer holds it
-    if ((fin.n / j->geom.tb) & 1)
+    const int last = (int)((fin.n / j->geom.tb) & 1);
+    if (j->staged)
+        HIP_TRY(hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+    else if (last)
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream));
     HIP_TRY(hipEventRecord(j->ev_end, stream));
@@ -328,11 +344,7 @@ void lsr_ctx::drive() {
         if (j->graph) (void)hipGraphDestroy(j->graph);
         j->exec = nullptr;
         j->graph = nullptr;
-        pool.release(j->buf[1]);
-        pool.release(j->partials);
-        pool.release(j->st);
-        j->buf[1] = j->partials = nullptr;
-        j->st = nullptr;
+        j->release_scratch(pool);
         {
             std::lock_guard<std::mutex> lk(mu);
             if (j->slot >= 0) free_slots.push_back(j->slot);
@@ -413,6 +425,7 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<Job> j(new Job());
     j->grid = *grid;
+    j->xgrid = *grid;
     j->stencil = stencil_id;
     j->cond = *cond;
     j->max_iter = max_iter;
@@ -455,21 +468,39 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
         ctx->free_slots.push_back(j->slot);
     };
     const size_t esz = dtype_size(grid->dtype);
-    const size_t bytes = (size_t)grid->rows * (size_t)grid->pitch * esz;
-    j->buf[0] = grid->data;
+    j->staged = needs_staging(*grid, stencil_id);
+    if (j->staged) j->xgrid.pitch = stage_pitch(*grid);
+    const size_t bytes = (size_t)grid->rows * (size_t)j->xgrid.pitch * esz;
     // geometry needs both buffers' alignment; the pool returns 256-byte aligned blocks
-    lsr_status st = ctx->pool.alloc(bytes, &j->buf[1]);
-    if (st != LSR_OK) { give_back(); return st; }
+    lsr_status st = LSR_OK;
+    if (j->staged) {
+        st = ctx->pool.alloc(bytes, &j->buf[0]);
+        if (st == LSR_OK && stencil_id == LSR_ST_HELMHOLTZ5) st = ctx->pool.alloc(bytes, &j->stage_env);
+        j->xgrid.data = j->buf[0];
+        j->xgrid.env0 = j->stage_env;
+    } else {
+        j->buf[0] = grid->data;
+    }
+    if (st == LSR_OK) st = ctx->pool.alloc(bytes, &j->buf[1]);
+    if (st != LSR_OK) {
+        if (j->staged) {
+            ctx->pool.release(j->buf[0]);
+            ctx->pool.release(j->stage_env);
+        }
+        ctx->pool.release(j->buf[1]);
+        give_back();
+        return st;
+    }
     switch (stencil_id) {
         case LSR_ST_LAPLACE5:
         case LSR_ST_HELMHOLTZ5: {
             lsr::JacobiArgs a{};
             a.a = j->buf[0];
             a.b = j->buf[1];
-            a.g = grid->env0;
+            a.g = j->xgrid.env0;
             a.rows = grid->rows;
             a.cols = grid->cols;
-            a.pitch = grid->pitch;
+            a.pitch = j->xgrid.pitch;
             a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
             a.f32 = grid->dtype == LSR_F32;
             // temporal blocking only where every check lands on a launch's last sweep
@@ -485,7 +516,9 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
             a.b = static_cast<uint8_t*>(j->buf[1]);
             a.rows = grid->rows;
             a.cols = grid->cols;
-            a.pitch = grid->pitch;
+            a.pitch = j->xgrid.pitch;
+            a.torus = grid->bc == LSR_BC_TORUS;
+            a.padded = j->staged;
             j->geom = lsr::life_geom(a, tun.tile_rows);
             break;
         }
@@ -501,8 +534,7 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     st = ctx->pool.alloc((size_t)std::max(nparts, 1) * 8, &j->partials);
     if (st == LSR_OK) st = ctx->pool.alloc(sizeof(lsr::JobState), (void**)&j->st);
     if (st != LSR_OK) {
-        ctx->pool.release(j->buf[1]);
-        ctx->pool.release(j->partials);
+        j->release_scratch(ctx->pool);
         give_back();
         return st;
     }
@@ -525,9 +557,7 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     j->mirror_dev = ctx->mirrors_dev + j->slot;
     std::memset((void*)j->mirror_host, 0, sizeof(lsr::JobState));
     auto cleanup = [&] {
-        ctx->pool.release(j->buf[1]);
-        ctx->pool.release(j->partials);
-        ctx->pool.release(j->st);
+        j->release_scratch(ctx->pool);
         if (j->ev_user) (void)hipEventDestroy(j->ev_user);
         if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
         if (j->ev_end) (void)hipEventDestroy(j->ev_end);

@@ -132,6 +132,35 @@ class Pool {
 
 inline size_t dtype_size(int dt) { return dt == LSR_U8 ? 1 : dt == LSR_F32 ? 4 : 8; }
 
+// True when every row of a Jacobi grid (and its env) starts 16-byte aligned,
+// the condition of the vector sweep kernels.
+inline bool jacobi_rows_aligned(const lsr_grid& g, int stencil) {
+    const size_t esz = dtype_size(g.dtype);
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    bool ok = (g.pitch * esz) % 16 == 0 && al(g.data);
+    if (stencil == LSR_ST_HELMHOLTZ5) ok = ok && al(g.env0);
+    return ok;
+}
+
+// True when the SWAR Life kernel can sweep the caller's grid in place: 16-byte
+// aligned rows of a multiple of 16 cells (no padding to keep at zero).
+inline bool life_rows_direct(const lsr_grid& g) {
+    return g.cols % 16 == 0 && g.pitch % 16 == 0 && (reinterpret_cast<uintptr_t>(g.data) & 15) == 0;
+}
+
+// True when a job runs on staged copies (see Job::staged).
+inline bool needs_staging(const lsr_grid& g, int stencil) {
+    if (stencil == LSR_ST_LAPLACE5 || stencil == LSR_ST_HELMHOLTZ5) return !jacobi_rows_aligned(g, stencil);
+    if (stencil == LSR_ST_LIFE) return !life_rows_direct(g);
+    return false;
+}
+
+// Row pitch (elements) of a staged copy: rows padded to 128 bytes.
+inline int64_t stage_pitch(const lsr_grid& g) {
+    const int64_t esz = (int64_t)dtype_size(g.dtype);
+    return (g.cols * esz + 127) / 128 * 128 / esz;
+}
+
 enum class Phase { Queued, Running, Finished };
 
 struct Job {
@@ -142,7 +171,15 @@ struct Job {
     int64_t max_iter = 0;
     lsr::LoopCtl ctl{};
     lsr::SweepGeom geom{};
-    void* buf[2] = {nullptr, nullptr};  // buf[0] = caller grid, buf[1] = partner
+    lsr_grid xgrid{};                   // the grid the kernels sweep (staged copy or the caller's)
+    void* buf[2] = {nullptr, nullptr};  // buf[0] = exec grid, buf[1] = partner
+    // A Jacobi grid whose rows are not 16-byte aligned (pitch or base), or a Life
+    // grid whose rows are not aligned runs of 16 cells, runs on private copies
+    // with a 128-byte row pitch (both buffers and env; Life padding zeroed), so
+    // it takes the vector / SWAR kernels; the result is copied back into the
+    // caller's grid.
+    bool staged = false;
+    void* stage_env = nullptr;
     void* partials = nullptr;
     lsr::JobState* st = nullptr;
     int slot = -1;
@@ -165,6 +202,20 @@ struct Job {
     double est_us = 0.0;                // estimated device time of one sweep
     bool cancel_posted = false;         // a cancel kernel has been enqueued
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+
+    // Returns the job's scratch (partner, staged copies, partials, state) to the pool.
+    void release_scratch(Pool& pool) {
+        pool.release(buf[1]);
+        pool.release(partials);
+        pool.release(st);
+        if (staged) {
+            pool.release(buf[0]);
+            pool.release(stage_env);
+            buf[0] = stage_env = nullptr;
+        }
+        buf[1] = partials = nullptr;
+        st = nullptr;
+    }
 };
 
 using Clock = std::chrono::steady_clock;

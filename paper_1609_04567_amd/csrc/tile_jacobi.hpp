@@ -123,15 +123,20 @@ __device__ __forceinline__ double jacobi_accum(int red, double acc, double d) {
 
 // Tile t of a grid split into `strips` column strips and bands of `tile_rows`
 // rows (band-major). The workgroup must have NW*64 threads; lds holds NW doubles.
-template <typename T, bool HELM, int VEC, int NW, int U, bool NT, bool NTG, bool NTU = false>
+// WT (wavefront tile): the calling wavefront alone owns tile t (NW must be 1);
+// other wavefronts of the workgroup may run other tiles, so the reduce stays
+// inside the wavefront and its lane 0 writes the partial.
+template <typename T, bool HELM, int VEC, int NW, int U, bool NT, bool NTG, bool NTU = false,
+          bool WT = false>
 __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restrict__ b,
                                              const T* __restrict__ g, int64_t rows, int64_t cols,
                                              int64_t pitch, T rd, T rd_lo, uint32_t sweep,
                                              bool check, int red, int t,
                                              int strips, int tile_rows,
                                              double* __restrict__ partials, double* lds) {
+    static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     const int band = t / strips, strip = t - band * strips;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = WT ? 0 : threadIdx.x >> 6;
     const int64_t cw = (int64_t)strip * (NW * 64 * VEC) + (int64_t)wave * (64 * VEC);
     const int64_t c = cw + (int64_t)lane * VEC;
     const int64_t r0 = 1 + (int64_t)band * tile_rows;
@@ -191,8 +196,13 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
         }
     }
     if (check) {
-        const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
-        if (threadIdx.x == 0) partials[t] = v;
+        if (WT) {
+            const double v = red == RED_MAX_ABS ? wave_max(acc) : wave_sum(acc);
+            if (lane == 0) partials[t] = v;
+        } else {
+            const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
+            if (threadIdx.x == 0) partials[t] = v;
+        }
     }
 }
 
@@ -251,7 +261,10 @@ __device__ __forceinline__ double lane_shift(double x) {
 template <int VEC, int NW, int K>
 constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 
-template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG>
+// WT as for jacobi5_tile: the calling wavefront alone owns tile t (NW = 1); its
+// g ring is still the slot of its own wavefront in the workgroup (gring holds
+// one ring per wavefront of the workgroup).
+template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
@@ -259,10 +272,12 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
                                                 int strips, int tile_rows,
                                                 double* __restrict__ partials, double* lds,
                                                 T* gring) {
+    static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
     const int band = t / strips, strip = t - band * strips;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, hw_wave = threadIdx.x >> 6;
+    const int wave = WT ? 0 : hw_wave;
     const int64_t cw = ((int64_t)strip * NW + wave) * OW;       // window start (aligned)
     const int64_t c = cw + (int64_t)lane * VEC;
     const int64_t olo = (cw == 0) ? 1 : cw + K;                  // output columns [olo, ohi)
@@ -280,7 +295,7 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     const bool fast = !edge && r0 - 2 * K >= 1 && i_end <= rows;
     const bool vec_ok = c + VEC <= cols;
     const bool store_vec = c >= olo && c + VEC <= ohi;
-    V* ring = reinterpret_cast<V*>(gring) + (size_t)wave * K * 64 + lane;  // slot s at ring[s * 64]
+    V* ring = reinterpret_cast<V*>(gring) + (size_t)hw_wave * K * 64 + lane;  // slot s at ring[s * 64]
 
     // W[j][s]: three rows of level j in registers; the slot that receives a
     // level's new row rotates with the row index (phase P = step % 3), so the
@@ -426,8 +441,13 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     else stream(std::false_type{});
 
     if (check) {
-        const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
-        if (threadIdx.x == 0) partials[t] = v;
+        if (WT) {
+            const double v = red == RED_MAX_ABS ? wave_max(acc) : wave_sum(acc);
+            if (lane == 0) partials[t] = v;
+        } else {
+            const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
+            if (threadIdx.x == 0) partials[t] = v;
+        }
     }
 }
 

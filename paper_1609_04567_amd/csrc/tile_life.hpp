@@ -2,8 +2,8 @@
 // paper's Fig. 1) with the live-cell count fused in. Shared by the single-job
 // kernels (life.hip) and the batched kernel (batch.hip).
 //
-// SWAR tile (cols and pitch multiples of 16 bytes, 16-byte aligned buffers):
-// each lane owns 16 consecutive cells held as four 32-bit words, one byte per
+// SWAR tile (16-byte aligned rows of a multiple of 16 bytes, see below for other
+// widths): each lane owns 16 consecutive cells held as four 32-bit words, one byte per
 // cell. Per row it forms the byte-wise column sums V = up + mid + down (<= 3 per
 // byte, no carries), shifts V by one byte left and right (the missing edge
 // bytes come from the neighbouring lanes by cross-lane shuffles, or from a halo
@@ -13,8 +13,7 @@
 // evaluated on four bytes at once with a zero-byte test. The new word's
 // popcount is the cell count. Wavefronts stream down `tile_rows` rows.
 //
-// Generic tile (any shape/pitch): one thread per cell, nine byte loads.
-// Both tiles expect cells of 0 or 1: the job's initial live-count pass rewrites
+// The tile expects cells of 0 or 1: the job's initial live-count pass rewrites
 // any other non-zero byte as 1 (a cell is alive iff its byte is non-zero).
 // Boundaries: torus wraps rows and columns; bottom treats outside cells as dead.
 #pragma once
@@ -32,24 +31,42 @@ __device__ __forceinline__ uint32_t zero_bytes_hi(uint32_t x) {
 // Cells must hold 0 or 1 (the job's first pass normalises the input in place).
 // With count = T - centre, B3/S23 is exactly (count | centre) == 3: a dead cell
 // is born on 3, a live one survives on 2 or 3.
-template <int NW, int U, bool NT>
+// Rows must be 16-byte aligned and hold round_up(cols, 16) bytes, the bytes
+// past cols starting at zero. When cols is not a multiple of 16 the last lane
+// with cells owns q < 16 of them: the byte after its last cell takes the east
+// neighbour's column sum, and the cells past cols are computed (0 or 1, so no
+// byte sum carries into the next) and stored into the padding but neither
+// counted nor read as anyone's neighbour.
+// WT (wavefront tile): the calling wavefront alone owns tile t (NW must be 1)
+// and reduces its count by itself; lane 0 writes the partial.
+template <int NW, int U, bool NT, bool WT = false>
 __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, uint8_t* __restrict__ b,
                                                int64_t rows, int64_t cols, int64_t pitch, int torus,
                                                bool check, int t, int strips, int tile_rows,
                                                unsigned long long* __restrict__ partials,
                                                unsigned long long* lds) {
+    static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     const int band = t / strips, strip = t - band * strips;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = WT ? 0 : threadIdx.x >> 6;
     const int64_t cw = (int64_t)strip * (NW * 1024) + (int64_t)wave * 1024;
     const int64_t c = cw + (int64_t)lane * 16;
     const bool active = c < cols;
-    int nact = 0;
-    if (cw < cols) nact = (int)min<int64_t>(64, (cols - cw) / 16);
+    int nact = 0;   // lanes of this wavefront that own cells
+    if (cw < cols) nact = (int)min<int64_t>(64, (cols - cw + 15) / 16);
     const int last = nact - 1;
-    int64_t wcol = cw - 1, ecol = cw + (int64_t)nact * 16;
+    const int q = active ? (int)min<int64_t>(16, cols - c) : 0;   // cells of this lane
+    const bool part = q > 0 && q < 16;                            // only lane `last`
+    int64_t wcol = cw - 1, ecol = min(cw + (int64_t)nact * 16, cols);
     bool has_w = (lane == 0) && nact > 0, has_e = (lane == last) && nact > 0;
     if (wcol < 0) { if (torus) wcol += cols; else has_w = false; }
     if (ecol >= cols) { if (torus) ecol -= cols; else has_e = false; }
+    // count mask (0x80 per counted cell) of each word
+    uint32_t cm[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int k = q - 4 * m;   // cells of this lane in word m
+        cm[m] = k >= 4 ? 0x80808080u : k <= 0 ? 0u : (0x80808080u & ((1u << (8 * k)) - 1u));
+    }
 
     const int64_t r0 = (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows);
@@ -100,6 +117,13 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
                 uint32_t ev = __shfl_down(V[0], 1, 64) & 0xFFu;
                 if (lane == 0) wv = vw_h;
                 if (lane == last) ev = ve_h;
+                if (part) {
+                    // the east neighbour of the last cell is byte q of this lane
+                    const int sh = (q & 3) * 8;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        if (m == (q >> 2)) V[m] = (V[m] & ~(0xFFu << sh)) | (ve_h << sh);
+                }
                 uint32_t out[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
@@ -108,7 +132,7 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
                     const uint32_t T = ((V[m] << 8) | prev) + V[m] + ((V[m] >> 8) | (next << 24));
                     const uint32_t alive = zero_bytes_hi(((T - mid[m]) | mid[m]) ^ 0x03030303u);
                     out[m] = alive >> 7;
-                    cnt += (unsigned)__popc(alive);
+                    cnt += (unsigned)__popc(alive & cm[m]);
                 }
                 if (active) {
                     typedef uint32_t W4 __attribute__((ext_vector_type(4)));
@@ -129,44 +153,13 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
         }
     }
     if (check) {
-        const unsigned long long v = block_reduce_u64<NW>(active ? cnt : 0ull, lds);
-        if (threadIdx.x == 0) partials[t] = v;
-    }
-}
-
-// Block blk of nblk 256-thread blocks covering the grid cell by cell.
-__device__ __forceinline__ void life_generic_tile(const uint8_t* __restrict__ a, uint8_t* __restrict__ b,
-                                                  int64_t rows, int64_t cols, int64_t pitch, int torus,
-                                                  bool check, int blk, int nblk,
-                                                  unsigned long long* __restrict__ partials,
-                                                  unsigned long long* lds) {
-    unsigned long long cnt = 0;
-    const int64_t total = rows * cols;
-    for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < total;
-         i += (int64_t)nblk * 256) {
-        const int64_t r = i / cols, cc = i - r * cols;
-        int count = 0;
-        for (int di = -1; di <= 1; ++di) {
-            for (int dj = -1; dj <= 1; ++dj) {
-                if (di == 0 && dj == 0) continue;
-                int64_t rr = r + di, c2 = cc + dj;
-                if (torus) {
-                    rr = (rr + rows) % rows;
-                    c2 = (c2 + cols) % cols;
-                } else if (rr < 0 || c2 < 0 || rr >= rows || c2 >= cols) {
-                    continue;
-                }
-                count += a[rr * pitch + c2] != 0;
-            }
+        if (WT) {
+            const unsigned long long v = wave_sum_u64(cnt);
+            if (lane == 0) partials[t] = v;
+        } else {
+            const unsigned long long v = block_reduce_u64<NW>(cnt, lds);
+            if (threadIdx.x == 0) partials[t] = v;
         }
-        const int alive = a[r * pitch + cc] != 0;
-        const uint8_t v = (count == 3 || (alive && count == 2)) ? 1 : 0;
-        b[r * pitch + cc] = v;
-        cnt += v;
-    }
-    if (check) {
-        const unsigned long long v = block_reduce_u64<4>(cnt, lds);
-        if (threadIdx.x == 0) partials[blk] = v;
     }
 }
 

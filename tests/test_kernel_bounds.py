@@ -68,10 +68,39 @@ def test_jacobi_edges_of_large_grids():
         assert _jacobi_accesses(rows, cols, vec, nw, unroll, 8, edge_tiles) == []
 
 
-def _life_accesses(rows, cols, nw, tile_rows, torus):
-    assert cols % 16 == 0
+def _life_pitch(cols):
+    """Row pitch the runtime gives a Life grid: the caller's when cols is a multiple
+    of 16 (the direct case), else a staged copy padded to 128 bytes."""
+    return cols if cols % 16 == 0 else -(-cols // 128) * 128
+
+
+def _life_geometry(cols, nw, lane_range=64):
     span = nw * 1024
-    strips = -(-cols // span)
+    return span, -(-cols // span)
+
+
+def _life_wave(cols, cw, torus):
+    """(nact, last, wcol, has_w, ecol, has_e) as life_swar_tile computes them."""
+    nact = min(64, -(-(cols - cw) // 16)) if cw < cols else 0
+    last = nact - 1
+    wcol, ecol = cw - 1, min(cw + nact * 16, cols)
+    has_w = has_e = nact > 0
+    if wcol < 0:
+        if torus:
+            wcol += cols
+        else:
+            has_w = False
+    if ecol >= cols:
+        if torus:
+            ecol -= cols
+        else:
+            has_e = False
+    return nact, last, wcol, has_w, ecol, has_e
+
+
+def _life_accesses(rows, cols, nw, tile_rows, torus):
+    pitch = _life_pitch(cols)
+    span, strips = _life_geometry(cols, nw)
     bands = -(-rows // tile_rows)
     bad = []
     for t in range(strips * bands):
@@ -80,24 +109,12 @@ def _life_accesses(rows, cols, nw, tile_rows, torus):
         r1 = min(r0 + tile_rows, rows)
         for w in range(nw):
             cw = strip * span + w * 1024
-            nact = min(64, (cols - cw) // 16) if cw < cols else 0
+            nact, last, wcol, has_w, ecol, has_e = _life_wave(cols, cw, torus)
             c = cw + np.arange(64) * 16
             active = c < cols
-            if active.any() and (c[active] + 15).max() >= cols:
+            # 16-byte words are loaded and stored whole: they must fit in the row pitch
+            if active.any() and (c[active] + 15).max() >= pitch:
                 bad.append(("word", t, w))
-            wcol, ecol = cw - 1, cw + nact * 16
-            has_w = nact > 0
-            has_e = nact > 0
-            if wcol < 0:
-                if torus:
-                    wcol += cols
-                else:
-                    has_w = False
-            if ecol >= cols:
-                if torus:
-                    ecol -= cols
-                else:
-                    has_e = False
             if has_w and not (0 <= wcol < cols):
                 bad.append(("west", t, w, wcol))
             if has_e and not (0 <= ecol < cols):
@@ -117,12 +134,106 @@ def _life_accesses(rows, cols, nw, tile_rows, torus):
 
 
 @pytest.mark.parametrize("rows,cols", [(1, 16), (16, 16), (64, 48), (130, 1040), (257, 2048),
-                                       (33, 4112), (5, 5008)])
+                                       (33, 4112), (5, 5008), (1, 1), (17, 13), (9, 1027),
+                                       (3, 4097)])
 @pytest.mark.parametrize("nw", [1, 2, 4, 8])
 @pytest.mark.parametrize("tile_rows", [16, 64])
 @pytest.mark.parametrize("torus", [True, False])
 def test_life_accesses_stay_in_grid(rows, cols, nw, tile_rows, torus):
     assert _life_accesses(rows, cols, nw, tile_rows, torus) == []
+
+
+def _zero_bytes_hi(x):
+    return ~(x + np.uint32(0x7F7F7F7F)) & np.uint32(0x80808080)
+
+
+def _swar_generation(buf, rows, cols, torus, nw, tile_rows):
+    """One generation of life_swar_tile, replayed word by word on the CPU (buf is
+    the padded rows x pitch byte array; returns the new array and the count)."""
+    pitch = buf.shape[1]
+    out = np.zeros_like(buf)
+    words = buf.view(np.uint32)             # rows x pitch/4
+    span, strips = _life_geometry(cols, nw)
+    bands = -(-rows // tile_rows)
+    total = 0
+    lanes = np.arange(64)
+    for t in range(strips * bands):
+        band, strip = divmod(t, strips)
+        r0, r1 = band * tile_rows, min(band * tile_rows + tile_rows, rows)
+        for w in range(nw):
+            cw = strip * span + w * 1024
+            nact, last, wcol, has_w, ecol, has_e = _life_wave(cols, cw, torus)
+            c = cw + lanes * 16
+            active = c < cols
+            q = np.where(active, np.minimum(16, cols - c), 0)
+            part = (q > 0) & (q < 16)
+
+            def load(r):
+                W = np.zeros((64, 4), np.uint32)
+                hw = he = 0
+                if r < 0 or r >= rows:
+                    if not torus:
+                        return W, 0, 0
+                    r = r + rows if r < 0 else r - rows
+                for ln in np.nonzero(active)[0]:
+                    W[ln] = words[r, (c[ln] // 4):(c[ln] // 4) + 4]
+                if has_w:
+                    hw = int(buf[r, wcol])
+                if has_e:
+                    he = int(buf[r, ecol])
+                return W, hw, he
+
+            for r in range(r0, r1):
+                up, uw, ue = load(r - 1)
+                mid, mw, me = load(r)
+                dn, dw, de = load(r + 1)
+                V = (up + mid + dn).astype(np.uint32)
+                vw_h, ve_h = uw + mw + dw, ue + me + de
+                for ln in range(64):
+                    if not active[ln]:
+                        continue
+                    Vl = V[ln].copy()
+                    wv = int(V[ln - 1][3] >> np.uint32(24)) if ln > 0 else vw_h
+                    ev = int(V[ln + 1][0] & np.uint32(0xFF)) if ln < 63 else int(V[ln][0] & 0xFF)
+                    if ln == last:
+                        ev = ve_h
+                    if part[ln]:
+                        m, sh = int(q[ln]) >> 2, (int(q[ln]) & 3) * 8
+                        Vl[m] = (Vl[m] & np.uint32(~(0xFF << sh) & 0xFFFFFFFF)) | np.uint32(ve_h << sh)
+                    o = np.zeros(4, np.uint32)
+                    for m in range(4):
+                        prev = int(Vl[m - 1] >> np.uint32(24)) if m > 0 else wv
+                        nxt = int(Vl[m + 1] & np.uint32(0xFF)) if m < 3 else ev
+                        T = (((Vl[m] << np.uint32(8)) | np.uint32(prev)) + Vl[m]
+                             + ((Vl[m] >> np.uint32(8)) | np.uint32(nxt << 24))).astype(np.uint32)
+                        alive = _zero_bytes_hi(((T - mid[ln][m]) | mid[ln][m]) ^ np.uint32(0x03030303))
+                        o[m] = alive >> np.uint32(7)
+                        k = int(q[ln]) - 4 * m
+                        cm = 0x80808080 if k >= 4 else 0 if k <= 0 else 0x80808080 & ((1 << (8 * k)) - 1)
+                        total += bin(int(alive) & cm).count("1")
+                    out[r, c[ln]:c[ln] + 16] = o.view(np.uint8)
+    return out, total
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 1), (3, 5), (17, 13), (20, 31), (9, 33), (12, 48),
+                                       (6, 1027)])
+@pytest.mark.parametrize("torus", [True, False])
+def test_life_swar_model_matches_oracle_on_padded_rows(rows, cols, torus):
+    """The word arithmetic of the SWAR tile, including the partial last lane of a
+    padded row, against the oracle over three generations."""
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    a = I.life_input(rows, cols, seed=rows * 100 + cols)
+    pitch = _life_pitch(cols)
+    buf = np.zeros((rows, pitch), np.uint8)
+    buf[:, :cols] = a
+    for gen in range(1, 4):
+        buf, count = _swar_generation(buf, rows, cols, torus, 1, 8)
+        o, ro = O.life_run(a, bc=O.BC_TORUS if torus else O.BC_BOTTOM, cond=O.COND_NEVER,
+                           max_iter=gen)
+        assert np.array_equal(buf[:, :cols], o), gen
+        assert count == ro.count, gen
+        assert buf.max() <= 1   # padding stays 0/1, so column sums never carry
 
 
 def test_model_flags_the_unguarded_west_halo():
