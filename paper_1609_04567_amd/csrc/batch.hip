@@ -22,63 +22,45 @@ namespace {
 
 constexpr int kBatchThreads = 256;
 constexpr int kWavesPerGroup = kBatchThreads / 64;
-constexpr int kJacTileRows = 8;
 constexpr int kLifeTileRows = 32;
 
-template <typename T, int VEC>
-__device__ __forceinline__ void jac_tile(const BatchJob& J, const void* src, void* dst, bool check,
-                                         uint32_t sweep, int t) {
-    const T* a = static_cast<const T*>(src);
-    T* b = static_cast<T*>(dst);
-    const T* g = static_cast<const T*>(J.env);
-    double* parts = static_cast<double*>(J.partials);
-    if (J.helm)
-        jacobi5_tile<T, true, VEC, 1, 4, true, true, false, true>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep, check,
-            J.ctl.reduce, t, J.strips, J.tile_rows, parts, nullptr);
-    else
-        jacobi5_tile<T, false, VEC, 1, 4, true, false, false, true>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep, check, J.ctl.reduce, t,
-            J.strips, J.tile_rows, parts, nullptr);
-}
-
-template <typename T, int VEC, int K>
+template <typename T, int VEC, int K, bool MC>
 __device__ __forceinline__ void jac_tb_tile(const BatchJob& J, const void* src, void* dst,
-                                            bool check, uint32_t sweep0, int t, T* gring) {
+                                            uint32_t mask, uint32_t sweep0, int t, T* gring) {
     const T* a = static_cast<const T*>(src);
     T* b = static_cast<T*>(dst);
     const T* g = static_cast<const T*>(J.env);
     double* parts = static_cast<double*>(J.partials);
     if (J.helm)
-        jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, check,
-            J.ctl.reduce, t, J.strips, J.tile_rows, parts, nullptr, gring);
+        jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true, MC>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, mask,
+            J.ctl.reduce, t, J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
     else
-        jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, check, J.ctl.reduce, t,
-            J.strips, J.tile_rows, parts, nullptr, gring);
+        jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true, MC>(
+            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, mask, J.ctl.reduce, t,
+            J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
 }
 
-template <int KIND> struct KindInfo {
-    static constexpr int step = 1;
-    static constexpr int ring = 1;   // LDS elements of T for the g rings
-};
-template <> struct KindInfo<BK_JAC_F64_TB10> { static constexpr int step = 10, ring = tb_gring_elems<2, kWavesPerGroup, 10>(); };
-template <> struct KindInfo<BK_JAC_F64_TB5> { static constexpr int step = 5, ring = tb_gring_elems<2, kWavesPerGroup, 5>(); };
-template <> struct KindInfo<BK_JAC_F64_TB2> { static constexpr int step = 2, ring = tb_gring_elems<2, kWavesPerGroup, 2>(); };
-template <> struct KindInfo<BK_JAC_F32_TB5> { static constexpr int step = 5, ring = tb_gring_elems<4, kWavesPerGroup, 5>(); };
-template <> struct KindInfo<BK_JAC_F32_TB2> { static constexpr int step = 2, ring = tb_gring_elems<4, kWavesPerGroup, 2>(); };
+// Per family: sweeps per round, element type width (0 = Life), and whether a
+// round may hold several checks.
+template <int KIND> struct KindInfo { static constexpr int step = 1, vec = 0; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F64_TB10> { static constexpr int step = 10, vec = 2; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F64_TB5> { static constexpr int step = 5, vec = 2; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F64_TB2> { static constexpr int step = 2, vec = 2; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F32_TB5> { static constexpr int step = 5, vec = 4; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F32_TB2> { static constexpr int step = 2, vec = 4; static constexpr bool mc = false; };
+template <> struct KindInfo<BK_JAC_F64_TB5_MC> { static constexpr int step = 5, vec = 2; static constexpr bool mc = true; };
+template <> struct KindInfo<BK_JAC_F32_TB5_MC> { static constexpr int step = 5, vec = 4; static constexpr bool mc = true; };
 
 // Work items of one kernel family; the work list segment of this launch holds only
 // jobs of that family (one launch per family keeps each its own register budget).
 template <int KIND>
 __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJob* __restrict__ jobs,
                                                                     const WorkItem* __restrict__ work) {
-    constexpr int STEP = KindInfo<KIND>::step;
-    constexpr bool F64TB = KIND == BK_JAC_F64_TB10 || KIND == BK_JAC_F64_TB5 || KIND == BK_JAC_F64_TB2;
-    constexpr bool F32TB = KIND == BK_JAC_F32_TB5 || KIND == BK_JAC_F32_TB2;
-    __shared__ __attribute__((aligned(16))) double ring_d[F64TB ? KindInfo<KIND>::ring : 1];
-    __shared__ __attribute__((aligned(16))) float ring_f[F32TB ? KindInfo<KIND>::ring : 1];
+    constexpr int STEP = KindInfo<KIND>::step, VEC = KindInfo<KIND>::vec;
+    constexpr bool MC = KindInfo<KIND>::mc;
+    __shared__ __attribute__((aligned(16))) double ring_d[VEC == 2 ? tb_gring_elems<2, kWavesPerGroup, STEP>() : 1];
+    __shared__ __attribute__((aligned(16))) float ring_f[VEC == 4 ? tb_gring_elems<4, kWavesPerGroup, STEP>() : 1];
     const int wave = threadIdx.x >> 6;
     const WorkItem w = work[xcd_logical_tile(blockIdx.x, gridDim.x) * kWavesPerGroup + wave];
     if (w.job < 0) return;
@@ -86,51 +68,61 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
     if (__hip_atomic_load(&J.st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     const int64_t n = __hip_atomic_load(&J.st->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (n >= J.ctl.max_iter) return;
-    // sweeps n+1 .. n+STEP (STEP divides the check period and the cap)
-    const bool check = is_check_sweep(n + STEP, J.ctl);
+    // sweeps n+1 .. n+STEP; without MC, STEP divides the check period and the cap
+    uint32_t mask = 0;
+#pragma unroll
+    for (int lev = 1; lev <= STEP; ++lev)
+        if (n + lev <= J.ctl.max_iter && is_check_sweep(n + lev, J.ctl)) mask |= 1u << (lev - 1);
+    if (!MC) mask &= 1u << (STEP - 1);
     const int64_t launch = n / STEP;
     const void* src = J.buf[launch & 1];
     void* dst = const_cast<void*>(J.buf[(launch + 1) & 1]);
     const uint32_t sw = (uint32_t)(n + 1);
-    if (KIND == BK_JAC_F64_V2) jac_tile<double, 2>(J, src, dst, check, sw, w.tile);
-    if (KIND == BK_JAC_F32_V4) jac_tile<float, 4>(J, src, dst, check, sw, w.tile);
-    if (KIND == BK_JAC_F64_TB10) jac_tb_tile<double, 2, 10>(J, src, dst, check, sw, w.tile, ring_d);
-    if (KIND == BK_JAC_F64_TB5) jac_tb_tile<double, 2, 5>(J, src, dst, check, sw, w.tile, ring_d);
-    if (KIND == BK_JAC_F64_TB2) jac_tb_tile<double, 2, 2>(J, src, dst, check, sw, w.tile, ring_d);
-    if (KIND == BK_JAC_F32_TB5) jac_tb_tile<float, 4, 5>(J, src, dst, check, sw, w.tile, ring_f);
-    if (KIND == BK_JAC_F32_TB2) jac_tb_tile<float, 4, 2>(J, src, dst, check, sw, w.tile, ring_f);
-    if (KIND == BK_LIFE_SWAR)
+    if constexpr (VEC == 2) jac_tb_tile<double, 2, STEP, MC>(J, src, dst, mask, sw, w.tile, ring_d);
+    if constexpr (VEC == 4) jac_tb_tile<float, 4, STEP, MC>(J, src, dst, mask, sw, w.tile, ring_f);
+    const bool check = mask != 0;
+    if constexpr (KIND == BK_LIFE_SWAR)
         life_swar_tile<1, 8, true, true>(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst),
                                          J.rows, J.cols, J.pitch, J.torus, check, w.tile, J.strips,
                                          J.tile_rows, static_cast<unsigned long long*>(J.partials),
                                          nullptr);
 }
 
-// One workgroup per job: count the job's step, and on a check sweep fold the
-// job's partials in index order and evaluate its condition.
+// One workgroup per job: count the job's round, and fold and evaluate each check
+// the round holds, in sweep order (the last level's only, without mc), stopping
+// at the first that ends the loop.
 __global__ __launch_bounds__(kBatchThreads) void batch_finalize_kernel(const BatchJob* __restrict__ jobs) {
     __shared__ double lds_d[kBatchThreads / 64];
     __shared__ unsigned long long lds_u[kBatchThreads / 64];
+    __shared__ int stop;
     const BatchJob& J = jobs[blockIdx.x];
     JobState* st = J.st;
     if (st->done) return;
-    const int64_t n1 = st->n + J.step;
-    if (n1 > J.ctl.max_iter) return;
-    const bool check = is_check_sweep(n1, J.ctl);
-    double rd = 0.0;
-    unsigned long long ru = 0;
-    if (check) {
+    const int64_t n0 = st->n;
+    if (n0 + 1 > J.ctl.max_iter) return;
+    JobState s = *st;   // only thread 0's copy is updated
+    for (int lev = J.mc ? 1 : J.step; lev <= J.step; ++lev) {
+        const int64_t n = n0 + lev;
+        if (n > J.ctl.max_iter) break;
+        if (!is_check_sweep(n, J.ctl)) continue;
+        const size_t off = J.mc ? (size_t)(lev - 1) * (size_t)J.tiles : 0;
+        double rd = 0.0;
+        unsigned long long ru = 0;
         if (J.ctl.reduce == RED_SUM)
-            ru = fold_partials_u64<kBatchThreads>(static_cast<const unsigned long long*>(J.partials),
-                                                  J.ctl.nparts, lds_u);
+            ru = fold_partials_u64<kBatchThreads>(
+                static_cast<const unsigned long long*>(J.partials) + off, J.ctl.nparts, lds_u);
         else
-            rd = fold_partials<kBatchThreads>(static_cast<const double*>(J.partials), J.ctl.nparts,
-                                              J.ctl.reduce == RED_MAX_ABS, lds_d);
+            rd = fold_partials<kBatchThreads>(static_cast<const double*>(J.partials) + off,
+                                              J.ctl.nparts, J.ctl.reduce == RED_MAX_ABS, lds_d);
+        if (threadIdx.x == 0) {
+            apply_check(s, J.ctl, n, rd, ru);
+            stop = s.done;
+        }
+        __syncthreads();   // thread 0 is done with lds before the next fold
+        if (stop) break;
     }
     if (threadIdx.x != 0) return;
-    JobState s = *st;
-    s.n = n1;
-    if (check) apply_check(s, J.ctl, n1, rd, ru);
+    if (!s.done) s.n = n0 + J.step;
     publish_state(st, J.mirror, s);
 }
 
@@ -143,6 +135,7 @@ void launch_kind(const BatchJob* jobs, const WorkItem* work, int groups, hipStre
 
 void batch_geometry(BatchJob& j, int is_life, int f32) {
     j.step = 1;
+    j.mc = 0;
     if (is_life) {
         // rows are 16-byte aligned with zeroed padding to a multiple of 16 cells
         j.kind = BK_LIFE_SWAR;
@@ -153,22 +146,22 @@ void batch_geometry(BatchJob& j, int is_life, int f32) {
     }
     // rows are 16-byte aligned (the engine stages any other grid)
     const int vec = f32 ? 4 : 2;
-    int depth = 1;
+    int depth = 0;
     for (int k : f32 ? std::initializer_list<int>{5, 2} : std::initializer_list<int>{10, 5, 2})
         if (j.ctl.check_every % k == 0 && j.ctl.max_iter % k == 0) { depth = k; break; }
-    if (depth == 1) {
-        j.kind = f32 ? BK_JAC_F32_V4 : BK_JAC_F64_V2;
-        j.tile_rows = kJacTileRows;
-        j.strips = (int)((j.cols + 64 * vec - 1) / (64 * vec));
+    if (depth == 0) {
+        depth = 5;
+        j.mc = 1;
+        j.kind = f32 ? BK_JAC_F32_TB5_MC : BK_JAC_F64_TB5_MC;
     } else {
         j.kind = f32 ? (depth == 5 ? BK_JAC_F32_TB5 : BK_JAC_F32_TB2)
                      : (depth == 10 ? BK_JAC_F64_TB10 : depth == 5 ? BK_JAC_F64_TB5 : BK_JAC_F64_TB2);
-        j.step = depth;
-        j.tile_rows = depth >= 8 ? 48 : 32;
-        const int64_t ow = (64 * vec - 2 * depth) / vec * vec;
-        const int64_t need = j.cols - 1 - depth;
-        j.strips = (int)(need > 0 ? (need + ow - 1) / ow : 1);
     }
+    j.step = depth;
+    j.tile_rows = depth >= 8 ? 48 : 32;
+    const int64_t ow = (64 * vec - 2 * depth) / vec * vec;
+    const int64_t need = j.cols - 1 - depth;
+    j.strips = (int)(need > 0 ? (need + ow - 1) / ow : 1);
     j.tiles = j.strips * (int)((j.rows - 2 + j.tile_rows - 1) / j.tile_rows);
 }
 
@@ -178,13 +171,13 @@ hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int ki
     if (nwork_padded % (kWavesPerGroup * kXcds)) return hipErrorInvalidValue;
     const int groups = nwork_padded / kWavesPerGroup;
     switch (kind) {
-        case BK_JAC_F64_V2: launch_kind<BK_JAC_F64_V2>(jobs, work, groups, s); break;
-        case BK_JAC_F32_V4: launch_kind<BK_JAC_F32_V4>(jobs, work, groups, s); break;
         case BK_JAC_F64_TB10: launch_kind<BK_JAC_F64_TB10>(jobs, work, groups, s); break;
         case BK_JAC_F64_TB5: launch_kind<BK_JAC_F64_TB5>(jobs, work, groups, s); break;
         case BK_JAC_F64_TB2: launch_kind<BK_JAC_F64_TB2>(jobs, work, groups, s); break;
         case BK_JAC_F32_TB5: launch_kind<BK_JAC_F32_TB5>(jobs, work, groups, s); break;
         case BK_JAC_F32_TB2: launch_kind<BK_JAC_F32_TB2>(jobs, work, groups, s); break;
+        case BK_JAC_F64_TB5_MC: launch_kind<BK_JAC_F64_TB5_MC>(jobs, work, groups, s); break;
+        case BK_JAC_F32_TB5_MC: launch_kind<BK_JAC_F32_TB5_MC>(jobs, work, groups, s); break;
         case BK_LIFE_SWAR: launch_kind<BK_LIFE_SWAR>(jobs, work, groups, s); break;
         default: return hipErrorInvalidValue;
     }

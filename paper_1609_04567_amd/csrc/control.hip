@@ -42,15 +42,52 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(JobState* st, con
     publish_state(st, mirror, s);
 }
 
+// Finalize of a fused launch that may hold several checks (sweeps
+// n_base + j0 + 1 .. n_base + j0 + K): evaluates them in sweep order, each from
+// its own slice of tiles partials, and stops at the first that ends the loop.
+__global__ __launch_bounds__(kFinThreads) void finalize_levels_kernel(JobState* st,
+                                                                      const void* partials,
+                                                                      LoopCtl c, int j0, int K,
+                                                                      int tiles, JobState* mirror) {
+    __shared__ double lds_d[kFinThreads / 64];
+    __shared__ unsigned long long lds_u[kFinThreads / 64];
+    __shared__ int stop;
+    if (st->done) return;
+    JobState s = *st;   // only thread 0's copy is updated
+    for (int lev = 1; lev <= K; ++lev) {
+        const int64_t n = s.n_base + j0 + lev;
+        if (n > c.max_iter) break;
+        if (!is_check_sweep(n, c)) continue;
+        const size_t off = (size_t)(lev - 1) * (size_t)tiles;
+        double rd = 0.0;
+        unsigned long long ru = 0;
+        if (c.reduce == RED_SUM)
+            ru = fold_partials_u64<kFinThreads>(static_cast<const unsigned long long*>(partials) + off,
+                                                c.nparts, lds_u);
+        else
+            rd = fold_partials<kFinThreads>(static_cast<const double*>(partials) + off, c.nparts,
+                                            c.reduce == RED_MAX_ABS, lds_d);
+        if (threadIdx.x == 0) {
+            apply_check(s, c, n, rd, ru);
+            stop = s.done;
+        }
+        __syncthreads();   // thread 0 is done with lds before the next fold
+        if (stop) break;
+    }
+    if (threadIdx.x != 0) return;
+    if (!s.done && j0 + K == c.chunk) s.n_base += c.chunk;
+    publish_state(st, mirror, s);
+}
+
 __global__ __launch_bounds__(256) void init_state_kernel(JobState* st, const unsigned long long* parts,
-                                                         int nparts) {
+                                                         int nparts, int64_t n_base) {
     __shared__ unsigned long long lds[4];
     unsigned long long acc = 0;
     for (int i = threadIdx.x; i < nparts; i += 256) acc += parts[i];
     acc = block_reduce_u64<4>(acc, lds);
     if (threadIdx.x == 0) {
         JobState s;
-        s.n_base = 0;
+        s.n_base = n_base;
         s.n = 0;
         s.r = __builtin_nan("");
         s.count = acc;
@@ -113,9 +150,17 @@ hipError_t launch_count_u8(uint8_t* a, int64_t rows, int64_t cols, int64_t pitch
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(JobState* st, const void* count_parts, int nparts, hipStream_t s) {
+hipError_t launch_init_state(JobState* st, const void* count_parts, int nparts, hipStream_t s,
+                             int64_t n_base) {
     hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(256), 0, s, st,
-                       static_cast<const unsigned long long*>(count_parts), nparts);
+                       static_cast<const unsigned long long*>(count_parts), nparts, n_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_levels(JobState* st, const void* partials, const LoopCtl& c, int j0,
+                                  int K, int tiles, JobState* mirror, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_levels_kernel, dim3(1), dim3(kFinThreads), 0, s, st, partials, c,
+                       j0, K, tiles, mirror);
     return hipGetLastError();
 }
 

@@ -94,7 +94,18 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     c.nparts = d.tiles;
     const size_t esz = dtype_size(g.dtype);
     j->bytes = (size_t)g.rows * (size_t)j->xgrid.pitch * esz;
-    j->nparts_alloc = std::max(d.tiles, life ? lsr::count_u8_parts(g.rows, g.cols) : 1);
+    int nparts = d.mc ? d.tiles * d.step : d.tiles;
+    if (life) {
+        nparts = std::max(nparts, lsr::count_u8_parts(g.rows, g.cols));
+    } else {
+        // unfused geometry that replays a stop inside a round (rows are aligned:
+        // null pointers stand for the buffers, which are not allocated yet)
+        lsr::JacobiArgs ra = jacobi_args(j, nullptr, nullptr);
+        ra.g = nullptr;
+        j->replay_geom = lsr::jacobi_geom(ra, 0);
+        nparts = std::max(nparts, j->replay_geom.tiles);
+    }
+    j->nparts_alloc = nparts;
     const double per_cell = life ? 2.0 : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
     if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");
@@ -270,12 +281,15 @@ void lsr_ctx::engine_scan() {
         const lsr_grid& g = j->xgrid;
         const lsr_grid& ug = j->grid;
         const size_t esz = dtype_size(g.dtype);
-        hipError_t e = hipSuccess;
-        const int last = (int)((fin.n / j->desc.step) & 1);   // buffer holding sweep n
-        if (j->staged)
+        // a stop inside a fused round is replayed first; then the buffer holding
+        // sweep n goes back to the caller's grid
+        int last = 0;
+        hipError_t e = finish_fused(j, fin, j->desc.step, j->desc.ctl, &last) == LSR_OK
+                           ? hipSuccess : hipErrorLaunchFailure;
+        if (e == hipSuccess && j->staged)
             e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream);
-        else if (last)
+        else if (e == hipSuccess && last)
             e = hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream);
         if (e == hipSuccess) e = hipEventRecord(j->ev_end, stream);

@@ -78,11 +78,12 @@ hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, v
 
 }  // namespace
 
-SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll, int depth) {
+SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves, int unroll, int depth,
+                      int mc) {
     SweepGeom g;
     g.vec = pick_vec(a);
     if (depth > 1 && g.vec > 1 && jacobi_tb_depth_ok(depth)) {
-        jacobi_tb_geom(a, depth, tile_rows, waves, unroll, g);
+        jacobi_tb_geom(a, depth, mc, tile_rows, waves, unroll, g);
         return g;
     }
     if (g.vec == 1) {

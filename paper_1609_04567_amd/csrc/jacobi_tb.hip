@@ -15,7 +15,7 @@
 namespace lsr {
 namespace {
 
-template <typename T, bool HELM, int VEC, int NW, int K>
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC>
 __global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
@@ -23,15 +23,22 @@ __global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
     __shared__ double lds[NW];
     __shared__ __attribute__((aligned(16))) T gring[HELM ? tb_gring_elems<VEC, NW, K>() : 1];
     if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    // sweeps n1 .. n1 + K - 1; K divides the sweep cap, so all of them are due
+    // sweeps n1 .. n1 + K - 1 (sweeps past the cap are computed and never kept:
+    // the stop lands inside the launch and the driver replays up to it)
     const int64_t n1 = __hip_atomic_load(&st->n_base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + j + 1;
     if (n1 > ctl.max_iter) return;
-    const bool check = is_check_sweep(n1 + K - 1, ctl);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int lev = 1; lev <= K; ++lev) {
+        const int64_t n = n1 + lev - 1;
+        if (n <= ctl.max_iter && is_check_sweep(n, ctl)) mask |= 1u << (lev - 1);
+    }
+    if (!MC) mask &= 1u << (K - 1);   // K divides the check period and the cap
     const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
     if (t >= tiles) return;
-    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM>(a, b, g, rows, cols, pitch, rd, rd_lo,
-                                                     (uint32_t)n1, check, ctl.reduce, t, strips,
-                                                     tile_rows, partials, lds, gring);
+    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM, false, MC>(
+        a, b, g, rows, cols, pitch, rd, rd_lo, (uint32_t)n1, mask, ctl.reduce, t, strips, tiles,
+        tile_rows, partials, lds, gring);
 }
 
 // Fused depths and wavefronts per workgroup compiled for the vector (16-byte
@@ -40,10 +47,14 @@ constexpr int kDepths[] = {2, 4, 5, 8, 10};
 
 bool waves_ok(int waves) { return waves == 1 || waves == 2 || waves == 4; }
 
-template <typename T, bool HELM, int VEC, int NW, int K>
+// Fewest tiles a default fused launch aims for (bands are halved down to 2 rows
+// until it has them; 1024^2 measured best at 4-row bands, 1280 tiles).
+constexpr int64_t kMinTiles = 1024;
+
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC = false>
 hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K>), dim3(g.blocks), dim3(NW * 64), 0,
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC>), dim3(g.blocks), dim3(NW * 64), 0,
                        s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
                        T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,
@@ -54,6 +65,8 @@ hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void*
 template <typename T, bool HELM, int VEC, int K>
 hipError_t launch_shape(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                         const LoopCtl& c, int j, hipStream_t s) {
+    if (g.mc) return g.waves == 2 ? launch_t<T, HELM, VEC, 2, K, true>(a, g, st, partials, c, j, s)
+                                  : hipErrorInvalidValue;
     switch (g.waves) {
         case 1: return launch_t<T, HELM, VEC, 1, K>(a, g, st, partials, c, j, s);
         case 2: return launch_t<T, HELM, VEC, 2, K>(a, g, st, partials, c, j, s);
@@ -86,23 +99,37 @@ bool jacobi_tb_depth_ok(int depth) {
 // Depth preference measured on the MI355X at 8192^2 (GLUP/s of the whole job,
 // 1000 sweeps, L2 check every 10): FP64 K=10 1160, K=5 887 (HBM-bound), unfused
 // 254; FP32 (compensated, stochastically rounded update, ALU-heavy) K=5 685,
-// K=10 628, unfused 435.
-int jacobi_tb_auto_depth(const JacobiArgs& a, int check_every, int64_t max_iter) {
+// K=10 628, unfused 435. A depth that divides both the check period and the cap
+// puts every check on a launch's last level; otherwise the launches carry
+// per-level checks (MC) and a stop inside a launch is replayed by the driver.
+void jacobi_tb_choose(const JacobiArgs& a, int check_every, int64_t max_iter, int requested,
+                      int* depth, int* mc) {
     static constexpr int kPrefF64[] = {10, 8, 5, 4, 2};
     static constexpr int kPrefF32[] = {5, 4, 10, 8, 2};
-    for (int k : (a.f32 ? kPrefF32 : kPrefF64))
-        if (check_every % k == 0 && max_iter % k == 0) return k;
-    return 1;
+    int k = 1;
+    if (requested > 1) {
+        k = jacobi_tb_depth_ok(requested) ? requested : 1;
+    } else if (requested == 0) {
+        for (int cand : (a.f32 ? kPrefF32 : kPrefF64))
+            if (check_every % cand == 0 && max_iter % cand == 0) { k = cand; break; }
+        if (k == 1) k = 5;   // checks inside launches: 5 measured best at 256^2 and 1024^2
+    }
+    *depth = k;
+    *mc = k > 1 && !(check_every % k == 0 && max_iter % k == 0);
 }
 
-void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
+void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int waves, int unroll,
                     SweepGeom& g) {
     (void)unroll;   // rows always stream in groups of three
-    if (!waves_ok(waves)) waves = 2;
+    if (!waves_ok(waves) || mc) waves = 2;   // per-level checks: compiled for 2 waves
     g.tb = depth;
+    g.mc = mc;
     g.waves = waves;
     g.unroll = 3;
-    // deeper blocks want taller bands (the 2K halo rows are re-read per band)
+    // deeper blocks want taller bands (the 2K halo rows are re-read per band),
+    // small grids want more, shorter bands: a band is a serial stream of rows
+    // through K levels, so a launch lasts as long as its tallest band (256^2
+    // Laplace, checks every sweep: 2-row bands 11.5 ms per job, 32-row 30.4 ms)
     g.tile_rows = tile_rows > 0 ? tile_rows : (depth >= 8 ? 48 : 32);
     // windows of 64 * vec columns step by ow (a multiple of vec) and output the
     // ow columns after their first `depth`; the first window outputs from column 1
@@ -110,7 +137,11 @@ void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, in
     const int64_t need = a.cols - 1 - depth;
     const int64_t nwin = need > 0 ? (need + ow - 1) / ow : 1;
     g.strips = (int)((nwin + waves - 1) / waves);
-    g.bands = (int)((a.rows - 2 + g.tile_rows - 1) / g.tile_rows);
+    auto bands_of = [&](int tr) { return (int)((a.rows - 2 + tr - 1) / tr); };
+    if (tile_rows <= 0)
+        while (g.tile_rows > 2 && (int64_t)g.strips * bands_of(g.tile_rows) < kMinTiles)
+            g.tile_rows = g.tile_rows > 4 ? g.tile_rows / 2 : 2;
+    g.bands = bands_of(g.tile_rows);
     g.tiles = g.strips * g.bands;
     g.blocks = pad_to_xcds(g.tiles);
 }

@@ -20,6 +20,7 @@ struct SweepGeom {
     int tiles = 0;       // strips * bands (= partials per check sweep)
     int blocks = 0;      // tiles padded to a multiple of 8
     int tb = 1;          // sweeps advanced per launch (temporal blocking depth)
+    int mc = 0;          // fused launches may hold several checks (partials per level)
 };
 
 // Jacobi 5-point (Laplace / Helmholtz) -------------------------------------
@@ -37,14 +38,18 @@ struct JacobiArgs {
 // when it is a compiled depth and the grid takes the vector path; the caller
 // checks g.tb for what was chosen. With g.tb = K, launch_jacobi's j is the
 // offset of the launch's first sweep (a multiple of K) and the result lands in b.
+// mc: launches may hold several checks (see jacobi_tb_choose).
 SweepGeom jacobi_geom(const JacobiArgs& a, int tile_rows, int waves = 0, int unroll = 0,
-                      int depth = 1);
+                      int depth = 1, int mc = 0);
 hipError_t launch_jacobi(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                          const LoopCtl& c, int j, hipStream_t s);
 bool jacobi_tb_depth_ok(int depth);
-// The measured best compiled depth dividing both check_every and max_iter (1 if none).
-int jacobi_tb_auto_depth(const JacobiArgs& a, int check_every, int64_t max_iter);
-void jacobi_tb_geom(const JacobiArgs& a, int depth, int tile_rows, int waves, int unroll,
+// Fused depth for a job: `requested` (0 = automatic, 1 = unfused, else that depth
+// if compiled); *mc = 1 when some check falls inside a launch (the check period
+// or the cap is not a multiple of the depth).
+void jacobi_tb_choose(const JacobiArgs& a, int check_every, int64_t max_iter, int requested,
+                      int* depth, int* mc);
+void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int waves, int unroll,
                     SweepGeom& g);
 hipError_t launch_jacobi_tb(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                             const LoopCtl& c, int j, hipStream_t s);
@@ -89,22 +94,24 @@ hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64
 // Kernel family of one job inside a batch; every batch kernel uses 256-thread
 // workgroups (4 wavefronts).
 enum BatchKind : int32_t {
-    BK_JAC_F64_V2 = 1,     // FP64 Jacobi, one sweep per round
-    BK_JAC_F32_V4 = 2,     // FP32 Jacobi, one sweep per round
-    BK_JAC_F64_TB10 = 3,   // FP64 Jacobi, 10 fused sweeps per round
-    BK_JAC_F64_TB5 = 4,
-    BK_JAC_F64_TB2 = 5,
-    BK_JAC_F32_TB5 = 6,    // FP32 Jacobi, 5 fused sweeps per round
-    BK_JAC_F32_TB2 = 7,
-    BK_LIFE_SWAR = 8       // Life, 16 cells per lane
+    BK_JAC_F64_TB10 = 1,   // FP64 Jacobi, 10 fused sweeps per round, check on the last
+    BK_JAC_F64_TB5 = 2,
+    BK_JAC_F64_TB2 = 3,
+    BK_JAC_F32_TB5 = 4,    // FP32 Jacobi, 5 fused sweeps per round, check on the last
+    BK_JAC_F32_TB2 = 5,
+    BK_JAC_F64_TB5_MC = 6, // FP64 Jacobi, 5 fused sweeps per round, any checks inside
+    BK_JAC_F32_TB5_MC = 7,
+    BK_LIFE_SWAR = 8       // Life, 16 cells per lane, one generation per round
 };
 constexpr int kBatchKinds = 8;
 
 // Device descriptor of one job of a batch. The job's completed-sweep count n
 // lives in its JobState; a round advances it by `step` sweeps, reading
-// buf[(n / step) % 2] and writing the other buffer. Rows of both buffers (and
-// env) are 16-byte aligned; Life rows hold round_up(cols, 16) bytes with the
-// padding starting at zero.
+// buf[(n / step) % 2] and writing the other buffer (a stop inside a round leaves
+// n at the stop sweep, and the engine replays that round up to it). Rows of both
+// buffers (and env) are 16-byte aligned; Life rows hold round_up(cols, 16) bytes
+// with the padding starting at zero. With mc, a round may hold several checks:
+// level l's partials are at partials[(l - 1) * tiles + tile].
 struct BatchJob {
     const void* buf[2];
     const void* env;       // Helmholtz g, or null
@@ -114,7 +121,7 @@ struct BatchJob {
     int64_t rows, cols, pitch;
     double rd;
     LoopCtl ctl;
-    int32_t kind, helm, torus, strips, tiles, tile_rows, step, pad_;
+    int32_t kind, helm, torus, strips, tiles, tile_rows, step, mc;
 };
 
 struct WorkItem {
@@ -125,7 +132,7 @@ struct WorkItem {
 // Family, step and tile geometry a job gets inside a batch: a function of its
 // shape, dtype and loop control only (j.ctl must be set), so its reduce order is
 // the same alone and in any mix. Jacobi jobs take the deepest fused depth that
-// divides both the check period and the cap.
+// divides both the check period and the cap, else depth 5 with checks inside.
 void batch_geometry(BatchJob& j, int is_life, int f32);
 // One launch per kernel family: `work` points at that family's segment of the
 // work list (nwork_padded entries, a multiple of 32; idle entries have job -1).
@@ -139,9 +146,16 @@ hipError_t launch_batch_finalize(const BatchJob* jobs, int njobs, hipStream_t s)
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);
 
 // Loop control ---------------------------------------------------------------
-hipError_t launch_init_state(JobState* st, const void* count_parts, int nparts, hipStream_t s);
+// A fresh state (count from the count partials, if any) with n_base sweeps done.
+hipError_t launch_init_state(JobState* st, const void* count_parts, int nparts, hipStream_t s,
+                             int64_t n_base = 0);
+// After the launch whose last sweep is chunk offset j (one check, partials[tile]).
 hipError_t launch_finalize(JobState* st, const void* partials, const LoopCtl& c, int j,
                            JobState* mirror, hipStream_t s);
+// After a fused launch of K sweeps from chunk offset j0 that may hold several
+// checks (level l's partials at partials[(l - 1) * tiles + tile]).
+hipError_t launch_finalize_levels(JobState* st, const void* partials, const LoopCtl& c, int j0,
+                                  int K, int tiles, JobState* mirror, hipStream_t s);
 hipError_t launch_cancel(JobState* st, JobState* mirror, hipStream_t s);
 
 }  // namespace lsr

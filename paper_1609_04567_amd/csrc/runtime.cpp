@@ -129,6 +129,21 @@ hipEvent_t lsr_ctx::get_event() {
     return e;
 }
 
+lsr::JacobiArgs lsr_rt::jacobi_args(const Job* j, const void* src, void* dst) {
+    const lsr_grid& g = j->xgrid;
+    lsr::JacobiArgs a;
+    a.a = src;
+    a.b = dst;
+    a.g = g.env0;
+    a.rows = g.rows;
+    a.cols = g.cols;
+    a.pitch = g.pitch;
+    a.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
+    a.helm = j->stencil == LSR_ST_HELMHOLTZ5;
+    a.f32 = g.dtype == LSR_F32;
+    return a;
+}
+
 lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     // one launch advances tb sweeps (off .. off + tb - 1 of the chunk)
     const int tb = j->geom.tb;
@@ -139,20 +154,10 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     const lsr_grid& g = j->xgrid;
     switch (j->stencil) {
         case LSR_ST_LAPLACE5:
-        case LSR_ST_HELMHOLTZ5: {
-            lsr::JacobiArgs a;
-            a.a = src;
-            a.b = dst;
-            a.g = g.env0;
-            a.rows = g.rows;
-            a.cols = g.cols;
-            a.pitch = g.pitch;
-            a.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
-            a.helm = j->stencil == LSR_ST_HELMHOLTZ5;
-            a.f32 = g.dtype == LSR_F32;
-            e = lsr::launch_jacobi(a, j->geom, j->st, j->partials, j->ctl, off, s);
+        case LSR_ST_HELMHOLTZ5:
+            e = lsr::launch_jacobi(jacobi_args(j, src, dst), j->geom, j->st, j->partials, j->ctl,
+                                   off, s);
             break;
-        }
         case LSR_ST_LIFE: {
             lsr::LifeArgs a;
             a.a = static_cast<const uint8_t*>(src);
@@ -161,6 +166,7 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
             a.cols = g.cols;
             a.pitch = g.pitch;
             a.torus = g.bc == LSR_BC_TORUS;
+            a.padded = j->staged;
             e = lsr::launch_life(a, j->geom, j->st, j->partials, j->ctl, off, s);
             break;
         }
@@ -181,10 +187,42 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     }
     if (e != hipSuccess) return fail(LSR_EDEVICE, "sweep launch: %s", hipGetErrorString(e));
     const int last = off + tb - 1;
-    if (j->fin_after[last]) {
+    if (j->geom.mc) {
+        bool any = false;
+        for (int k = off; k <= last; ++k) any = any || j->fin_after[k];
+        if (any)
+            e = lsr::launch_finalize_levels(j->st, j->partials, j->ctl, off, tb, j->geom.tiles,
+                                            j->mirror_dev, s);
+    } else if (j->fin_after[last]) {
         e = lsr::launch_finalize(j->st, j->partials, j->ctl, last, j->mirror_dev, s);
-        if (e != hipSuccess) return fail(LSR_EDEVICE, "finalize launch: %s", hipGetErrorString(e));
     }
+    if (e != hipSuccess) return fail(LSR_EDEVICE, "finalize launch: %s", hipGetErrorString(e));
+    return LSR_OK;
+}
+
+// A stop inside a fused launch (possible when the launches carry several
+// checks, or at a cap that is not a multiple of the depth) leaves that launch's
+// last level in its destination. Its source still holds the state before it, so
+// the sweeps up to the stop are replayed there with the unfused kernel, under a
+// scratch loop state (the job's real final state is already in the host mirror).
+// Returns the buffer holding sweep n in *last.
+lsr_status lsr_ctx::finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::LoopCtl& ctl,
+                                 int* last) {
+    if (K == 1 || fin.n % K == 0) {
+        *last = (int)((fin.n / K) & 1);
+        return LSR_OK;
+    }
+    const int64_t L = (fin.n - 1) / K;          // the launch holding the stop
+    const int m = (int)(fin.n - L * K);         // its sweeps to keep (1 .. K-1)
+    HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream, L * K));
+    lsr::LoopCtl rc = ctl;
+    rc.max_iter = fin.n;
+    rc.check_every = 0x7fffffff;                // only sweep n is a "check" (its partials are unused)
+    for (int k = 0; k < m; ++k) {
+        HIP_TRY(lsr::launch_jacobi(jacobi_args(j, j->buf[(L + k) & 1], j->buf[(L + k + 1) & 1]),
+                                   j->replay_geom, j->st, j->partials, rc, k, stream));
+    }
+    *last = (int)((L + m) & 1);
     return LSR_OK;
 }
 
@@ -294,8 +332,9 @@ lsr_status lsr_ctx::run_job(Job* j) {
     if (status != LSR_OK) return status;
     lsr::JobState fin;
     std::memcpy(&fin, (const void*)mir, sizeof fin);
-    // the stop sweep is a multiple of tb; launch parity says which buffer holds it
-    const int last = (int)((fin.n / j->geom.tb) & 1);
+    int last = 0;
+    lsr_status rs = finish_fused(j, fin, j->geom.tb, j->ctl, &last);
+    if (rs != LSR_OK) return rs;
     if (j->staged)
         HIP_TRY(hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream));
@@ -503,11 +542,11 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
             a.pitch = j->xgrid.pitch;
             a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
             a.f32 = grid->dtype == LSR_F32;
-            // temporal blocking only where every check lands on a launch's last sweep
-            int depth = tun.tb_depth > 0 ? tun.tb_depth
-                                         : lsr::jacobi_tb_auto_depth(a, cond->check_every, max_iter);
-            if (depth > 1 && (cond->check_every % depth != 0 || max_iter % depth != 0)) depth = 1;
-            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth);
+            int depth = 1, mc = 0;
+            lsr::jacobi_tb_choose(a, cond->check_every, max_iter, tun.tb_depth, &depth, &mc);
+            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth, mc);
+            // unfused sweeps that replay a stop inside a fused launch
+            j->replay_geom = lsr::jacobi_geom(a, 0);
             break;
         }
         case LSR_ST_LIFE: {
@@ -530,6 +569,8 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
         }
     }
     int nparts = j->geom.tiles;
+    if (j->geom.mc) nparts = j->geom.tiles * j->geom.tb;   // one slice per level
+    if (j->geom.tb > 1) nparts = std::max(nparts, j->replay_geom.tiles);
     if (stencil_id == LSR_ST_LIFE) nparts = std::max(nparts, lsr::count_u8_parts(grid->rows, grid->cols));
     st = ctx->pool.alloc((size_t)std::max(nparts, 1) * 8, &j->partials);
     if (st == LSR_OK) st = ctx->pool.alloc(sizeof(lsr::JobState), (void**)&j->st);

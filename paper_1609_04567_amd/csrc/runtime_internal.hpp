@@ -171,6 +171,7 @@ struct Job {
     int64_t max_iter = 0;
     lsr::LoopCtl ctl{};
     lsr::SweepGeom geom{};
+    lsr::SweepGeom replay_geom{};       // unfused Jacobi geometry (replay after a mid-launch stop)
     lsr_grid xgrid{};                   // the grid the kernels sweep (staged copy or the caller's)
     void* buf[2] = {nullptr, nullptr};  // buf[0] = exec grid, buf[1] = partner
     // A Jacobi grid whose rows are not 16-byte aligned (pitch or base), or a Life
@@ -226,6 +227,9 @@ inline double ms_between(Clock::time_point a, Clock::time_point b) {
 // Argument validation shared by lsr_run and lsr_check_args.
 lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* c, int64_t max_iter);
 
+// Kernel arguments of a Jacobi job's sweep from src to dst (its exec grid).
+lsr::JacobiArgs jacobi_args(const Job* j, const void* src, void* dst);
+
 }  // namespace lsr_rt
 
 
@@ -253,6 +257,8 @@ struct lsr_ctx {
     lsr_status run_job(lsr_rt::Job* j);
     lsr_status launch_sweep(lsr_rt::Job* j, int off, hipStream_t s);
     lsr_status enqueue_chunk_plain(lsr_rt::Job* j, hipStream_t s);
+    lsr_status finish_fused(lsr_rt::Job* j, const lsr::JobState& fin, int step,
+                            const lsr::LoopCtl& ctl, int* last);
     hipEvent_t get_event();
     void put_event(hipEvent_t e) { event_pool.push_back(e); }
 

@@ -264,17 +264,23 @@ constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 // WT as for jacobi5_tile: the calling wavefront alone owns tile t (NW = 1); its
 // g ring is still the slot of its own wavefront in the workgroup (gring holds
 // one ring per wavefront of the workgroup).
-template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false>
+// check_mask: bit j-1 set when level j's sweep (sweep0 + j - 1) is a check sweep.
+// Without MC only bit K-1 may be set and the tile's partial goes to partials[t];
+// with MC (several checks per launch) level j's partial goes to
+// partials[(j-1) * tiles + t], its delta taken against level j-1.
+template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false,
+          bool MC = false>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
-                                                uint32_t sweep0, bool check, int red, int t,
-                                                int strips, int tile_rows,
+                                                uint32_t sweep0, uint32_t check_mask, int red,
+                                                int t, int strips, int tiles, int tile_rows,
                                                 double* __restrict__ partials, double* lds,
                                                 T* gring) {
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
+    const bool check = (check_mask >> (K - 1)) & 1u;
     const int band = t / strips, strip = t - band * strips;
     const int lane = threadIdx.x & 63, hw_wave = threadIdx.x >> 6;
     const int wave = WT ? 0 : hw_wave;
@@ -315,6 +321,9 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
         for (int s2 = 0; s2 < K; ++s2) ring[s2 * 64] = z;
     }
     double acc = 0.0;
+    double accs[MC ? K : 1];   // per-level deltas (MC)
+#pragma unroll
+    for (int k = 0; k < (MC ? K : 1); ++k) accs[k] = 0.0;
     int slot = 0;   // ring slot of g row (i - 1) at step i
 
     auto load = [&](auto fast_tag, const T* __restrict__ base, int64_t row, T (&v)[VEC], bool nt) {
@@ -393,6 +402,15 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) nv[e] = src[PC][e];
             }
+            if (MC && j < K && ((check_mask >> (j - 1)) & 1u) && row >= r0 && row < r1) {
+                // a check inside the launch: delta of level j over this tile's cells
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int64_t col = c + e;
+                    if (store_vec || (col >= olo && col < ohi))
+                        accs[j - 1] = jacobi_accum(red, accs[j - 1], (double)nv[e] - (double)src[PC][e]);
+                }
+            }
             if (j < K) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) W[j][P][e] = nv[e];
@@ -440,14 +458,23 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     if (fast) stream(std::true_type{});
     else stream(std::false_type{});
 
-    if (check) {
+    auto reduce_out = [&](double v, int slot_index) {
         if (WT) {
-            const double v = red == RED_MAX_ABS ? wave_max(acc) : wave_sum(acc);
-            if (lane == 0) partials[t] = v;
+            v = red == RED_MAX_ABS ? wave_max(v) : wave_sum(v);
+            if (lane == 0) partials[slot_index] = v;
         } else {
-            const double v = block_reduce<NW>(acc, red == RED_MAX_ABS, lds);
-            if (threadIdx.x == 0) partials[t] = v;
+            v = block_reduce<NW>(v, red == RED_MAX_ABS, lds);
+            if (threadIdx.x == 0) partials[slot_index] = v;
+            if (NW > 1) __syncthreads();   // lds is reused by the next reduce
         }
+    };
+    if (MC) {
+        accs[K - 1] = acc;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if ((check_mask >> k) & 1u) reduce_out(accs[k], k * tiles + t);
+    } else if (check) {
+        reduce_out(acc, t);
     }
 }
 

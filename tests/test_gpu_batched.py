@@ -185,3 +185,37 @@ def test_restoration_rejected_on_batched_context(bctx):
         bctx.submit(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA, L.make_cond(L.LSR_COND_BELOW, 0.1),
                     10, L.LSR_BC_BOTTOM, env0=m, param=(100.0, 0.0))
     assert ei.value.status == L.LSR_EINVAL
+
+
+def test_stops_inside_rounds_are_replayed(bctx):
+    """Jobs whose checks fall inside a fused round (check every sweep, a cap that is
+    not a multiple of the depth) stop at exactly the oracle's sweep, alone and mixed."""
+    import torch
+    say("batched stops inside rounds")
+    a = I.laplace_input(96, 100, seed=21)
+    h = I.helmholtz_input(131)
+    cases = []
+    for thr in (3e-3, 2.44e-3, 1.98e-3):      # stop at sweeps 81, 97, 117 (check every sweep)
+        t = torch.from_numpy(a).to("cuda:0")
+        kw = dict(stencil_id=L.LSR_ST_LAPLACE5, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, thr, 1), max_iter=3000, bc=L.LSR_BC_RING)
+        cases.append((t, kw, lambda thr=thr: O.jacobi_run(a, thr=thr, max_iter=3000), None))
+    for cap in (123, 7):
+        t = torch.from_numpy(h.u0).to("cuda:0")
+        g = torch.from_numpy(h.g).to("cuda:0")
+        kw = dict(stencil_id=L.LSR_ST_HELMHOLTZ5, reduce_op=L.LSR_RED_L2_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, 1e-12, 10), max_iter=cap, bc=L.LSR_BC_RING,
+                  env0=g, param=(h.alpha, h.h))
+        ora = lambda cap=cap: O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                                           reduce_op=O.RED_L2_DELTA, thr=1e-12, check_every=10,
+                                           max_iter=cap)
+        cases.append((t, kw, ora, g))
+    ids = [_submit(bctx, t, kw) for (t, kw, _, _) in cases]
+    for (t, kw, ora, _), jid in zip(cases, ids):
+        r = bctx.result(jid)
+        torch.cuda.synchronize()
+        o, ro = ora()
+        assert r.status == L.LSR_OK and r.iterations == ro.n, (r.iterations, ro.n)
+        assert bool(r.converged) == ro.converged
+        assert np.array_equal(t.cpu().numpy(), o)
+        assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r

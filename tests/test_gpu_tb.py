@@ -66,15 +66,73 @@ def test_fused_chunking_and_graphs(ctx, depth, chunk, graph):
 
 
 @pytest.mark.parametrize("depth,view", [(4, {}), (5, dict(pitch=1031, offset=1)), (3, {})])
-def test_depth_that_cannot_be_used_falls_back(ctx, depth, view):
-    """A depth that does not divide check_every, an unaligned view and a depth that
-    is not compiled all run unfused, with the same result."""
-    say(f"tb fallback depth={depth} view={view}")
+def test_other_depths_and_views(ctx, depth, view):
+    """A depth that does not divide check_every (checks inside launches), an
+    unaligned view (staged) and a depth that is not compiled (unfused) all give
+    the oracle's result."""
+    say(f"tb depth={depth} view={view}")
     a = I.laplace_input(70, 1030, seed=6)
     o, ro = O.jacobi_run(a, thr=1e-6, check_every=10, max_iter=150)
     x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=1e-6, check_every=10, max_iter=150, **view),
                   tb_depth=depth)
     assert r.iterations == ro.n and np.array_equal(x, o)
+
+
+@pytest.mark.parametrize("depth", [10, 5, 4, 2])
+@pytest.mark.parametrize("ce", [1, 3])
+@pytest.mark.parametrize("thr", [3e-3, 2.44e-3, 1.98e-3])
+def test_checks_inside_launches_stop_exactly(ctx, depth, ce, thr):
+    """check_every smaller than (or not a multiple of) the depth: every check inside a
+    launch is evaluated, and a stop inside a launch is replayed to the exact sweep
+    (with check_every 1 these thresholds stop at sweeps 81, 97 and 117)."""
+    say(f"tb multi-check depth={depth} ce={ce} thr={thr}")
+    a = I.laplace_input(96, 100, seed=21)
+    o, ro = O.jacobi_run(a, thr=thr, check_every=ce, max_iter=3000)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=thr, check_every=ce, max_iter=3000),
+                  tb_depth=depth)
+    assert r.sweeps_per_launch == depth
+    assert ro.converged and r.iterations == ro.n and bool(r.converged)
+    assert np.array_equal(x, o)
+    assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r and r.checks == ro.n // ce
+
+
+@pytest.mark.parametrize("depth", [10, 4])
+def test_harmonic_start_stops_after_one_sweep_when_fused(ctx, depth):
+    say(f"tb harmonic depth={depth}")
+    a = I.harmonic_input(64, 66, "xy")
+    o, ro = O.jacobi_run(a, thr=1e-9, max_iter=500)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, a, thr=1e-9, max_iter=500), tb_depth=depth)
+    assert ro.n == 1 and r.iterations == 1 and r.converged and np.array_equal(x, o)
+
+
+@pytest.mark.parametrize("cap", [123, 7, 1])
+def test_cap_inside_a_launch(ctx, cap):
+    say(f"tb cap {cap}")
+    h = I.helmholtz_input(130)
+    o, ro = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=1.0, h=h.h, reduce_op=O.RED_L2_DELTA,
+                         thr=1e-12, check_every=10, max_iter=cap)
+    x, r = _tuned(ctx, lambda: run_jacobi(ctx, h.u0, helm=True, g=h.g, alpha=1.0, h=h.h,
+                                          reduce_op=L.LSR_RED_L2_DELTA, thr=1e-12, check_every=10,
+                                          max_iter=cap), tb_depth=10)
+    assert r.iterations == cap and np.array_equal(x, o)
+    assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
+
+
+@pytest.mark.parametrize("helm", [False, True])
+def test_f32_multi_check_equals_unfused(ctx, helm):
+    say(f"tb f32 multi-check helm={helm}")
+    if helm:
+        h = I.helmholtz_input(132)
+        a, g, alpha, hh = h.u0, h.g, h.alpha, h.h
+    else:
+        a, g, alpha, hh = I.laplace_input(100, 132, seed=2), None, 0.0, 1.0
+    kw = dict(helm=helm, g=g, alpha=alpha, h=hh, f32=True, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+              thr=1e-4, check_every=1, max_iter=777)
+    x1, r1 = _tuned(ctx, lambda: run_jacobi(ctx, a, **kw), tb_depth=1)
+    xk, rk = _tuned(ctx, lambda: run_jacobi(ctx, a, **kw), tb_depth=0)
+    assert rk.sweeps_per_launch > 1
+    assert rk.iterations == r1.iterations and np.array_equal(xk, x1)
+    assert rk.last_reduce == r1.last_reduce   # max is exact
 
 
 @pytest.mark.parametrize("helm", [False, True])
