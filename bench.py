@@ -49,7 +49,7 @@ def kernel_source_hash(files=("jacobi.hip", "jacobi_tb.hip", "tile_jacobi.hpp", 
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str):
+def measured_traffic(name: str, files=None):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None when the
     kernel source changed since they were taken."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -57,7 +57,8 @@ def measured_traffic(name: str):
     with open(TRAFFIC_FILE) as fh:
         d = json.load(fh)
     e = d.get(name)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    h = kernel_source_hash(files) if files else kernel_source_hash()
+    if not e or e.get("source_hash") != h:
         return None
     return e.get("bytes_per_launch")
 
@@ -202,6 +203,7 @@ def run_life(args, L, I, torch):
     grids = [torch.from_numpy(s).to("cuda:0") for _ in range(args.steps + args.warmup)]
     ctx = L.Context(0)
     ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph)
+    copy_gbs = copy_probe(L, ctx, torch, "cuda:0")
     cond = L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10)
     step = lambda t: ctx.run(t, L.LSR_ST_LIFE, L.LSR_RED_SUM, cond, gens, L.LSR_BC_TORUS)
     for k in range(args.warmup):
@@ -218,7 +220,10 @@ def run_life(args, L, I, torch):
                     {"workload": f"life-b3s23 {n}x{n} u8 torus, live count every generation, "
                                  f"stop when unchanged for 10 or {gens}", "rows": n, "cols": n,
                      "generations": gens})
-    out["roofline"] = roofline(2.0 * n * n, per_launch_s, None)
+    out["roofline"] = roofline(2.0 * n * n, per_launch_s,
+                               measured_traffic(f"life_swar_{n}", ("life.hip", "tile_life.hpp",
+                                                                   "common.hpp", "kernels.hpp")))
+    out["copy_probe_gbs"] = copy_gbs
     out["result"] = {"iterations": int(results[-1].iterations), "count": int(results[-1].last_count)}
     if not args.no_cpu:
         import oracle as O
