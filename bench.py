@@ -98,6 +98,13 @@ def run_helmholtz(args, L, I, torch):
     ctx.tune(tile_rows=args.tile_rows, tb_depth=args.tb, chunk=args.chunk, use_graph=args.graph,
              waves=args.waves, unroll=args.unroll)
     copy_gbs = copy_probe(L, ctx, torch, dev)
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        b = ctx.autotune(L.LSR_ST_HELMHOLTZ5, L.LSR_F64, n, n, 10, sweeps)
+        tuned = {"tile_rows": b.tile_rows, "tb_depth": b.tb_depth, "waves": b.waves,
+                 "unroll": b.unroll, "tuning_s": round(time.perf_counter() - t0, 2)}
+        print(f"autotune: {tuned}", file=sys.stderr, flush=True)
 
     def step(t):
         return ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, sweeps, L.LSR_BC_RING,
@@ -136,6 +143,8 @@ def run_helmholtz(args, L, I, torch):
     kname = f"jacobi5_helmholtz_f64_{n}" if spl == 1 else f"jacobi5_tb{spl}_helmholtz_f64_{n}"
     out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
     out["copy_probe_gbs"] = copy_gbs
+    if tuned:
+        out["autotuned"] = tuned
     # bytes an unfused sweep would move per update, at the achieved update rate
     out["effective_gbs"] = round(value * 24.0, 1)
     out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
@@ -424,6 +433,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--tb", type=int, default=0, help="Jacobi sweeps fused per launch (0 = auto)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure launch settings for the job before timing it (helmholtz)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "

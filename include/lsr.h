@@ -177,6 +177,35 @@ lsr_status lsr_destroy(lsr_ctx *ctx);
 lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
 
 /*
+ * Autotuner (the launch heuristics of Sect. 3.3, measured instead of guessed). Runs short
+ * jobs of this description (zero-filled scratch grids of rows x cols, check_every, at most
+ * max_iter sweeps; max_iter <= 0 means no cap) with each candidate launch setting (fused
+ * depth, wavefronts per workgroup, band rows, load unroll) on the context's device, and keeps
+ * the fastest in the context's table under the key (stencil_id, dtype, bit lengths of rows
+ * and cols, check_every). Later lsr_run calls whose overrides leave the launch shape
+ * automatic (tile_rows, tb_depth, waves and unroll all 0) take the table's entry for their
+ * key, so a job's settings depend only on its key. The winner is copied to best_out when it
+ * is not NULL. Blocks until done (a few hundred short jobs; about a second at 8192^2).
+ * Plain contexts only (EINVAL on a batched one, or for RESTORE); ENOMEM/EDEVICE as lsr_run.
+ * The caller owns nothing new; scratch returns to the context's pool.
+ */
+lsr_status lsr_autotune(lsr_ctx *ctx, int32_t stencil_id, int32_t dtype, int64_t rows,
+                        int64_t cols, int32_t check_every, int64_t max_iter,
+                        lsr_tuning *best_out);
+
+/*
+ * The autotuner's table as JSON text, tagged with the device architecture:
+ *   {"arch": "gfx950", "entries": [{"stencil": 2, "dtype": 8, "rows_log2": 14, ...}, ...]}
+ * Writes at most cap bytes (NUL included) to buf; *len_out receives the size needed. With
+ * buf NULL only the size is reported; a buffer that is too small gives EINVAL.
+ */
+lsr_status lsr_tune_export(lsr_ctx *ctx, char *buf, uint64_t cap, uint64_t *len_out);
+
+/* Merges a table written by lsr_tune_export into the context's (EINVAL if it was measured on
+ * another architecture or is malformed; the context's table is then unchanged). */
+lsr_status lsr_tune_import(lsr_ctx *ctx, const char *json);
+
+/*
  * Starts one loop-of-stencil-reduce job (asynchronous). Supported combinations:
  *   LAPLACE5   F64|F32  RING            env0 NULL        MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
  *   HELMHOLTZ5 F64|F32  RING            env0 g (dtype)   MAX_ABS|L2|MEAN_ABS  BELOW|NEVER

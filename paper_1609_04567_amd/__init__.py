@@ -13,9 +13,9 @@ from ._native import (  # noqa: F401
     LSR_ENOTFOUND, LSR_ENUMERIC, LSR_F32, LSR_F64, LSR_OK, LSR_RED_L2_DELTA,
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
-    lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error, lsr_probe_copy,
-    lsr_result, lsr_run,
-    lsr_set_tuning, lsr_version, make_cond, make_grid,
+    lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
+    lsr_probe_copy, lsr_result, lsr_run, lsr_set_tuning, lsr_tune_export, lsr_tune_import,
+    lsr_version, make_cond, make_grid,
 )
 
 
@@ -62,6 +62,18 @@ class Context:
 
     def tune(self, tile_rows=0, tb_depth=0, chunk=0, use_graph=0, waves=0, unroll=0):
         lsr_set_tuning(self.handle, tile_rows, tb_depth, chunk, use_graph, waves, unroll)
+
+    def autotune(self, stencil_id, dtype, rows, cols, check_every, max_iter=0):
+        """Measures launch settings for this job description (see lsr_autotune)."""
+        return lsr_autotune(self.handle, stencil_id, dtype, rows, cols, check_every, max_iter)
+
+    def save_tuning(self, path):
+        with open(path, "w") as fh:
+            fh.write(lsr_tune_export(self.handle))
+
+    def load_tuning(self, path):
+        with open(path) as fh:
+            lsr_tune_import(self.handle, fh.read())
 
     def submit(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
         g = grid_from_tensor(grid_t, bc, env0, param)

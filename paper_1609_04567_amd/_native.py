@@ -68,6 +68,10 @@ _SIGS = {
     "lsr_create": (C.c_int, [C.POINTER(lsr_config), C.POINTER(C.c_void_p)]),
     "lsr_destroy": (C.c_int, [C.c_void_p]),
     "lsr_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(lsr_tuning)]),
+    "lsr_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int64, C.c_int32,
+                               C.c_int64, C.POINTER(lsr_tuning)]),
+    "lsr_tune_export": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "lsr_tune_import": (C.c_int, [C.c_void_p, C.c_char_p]),
     "lsr_run": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_int32, C.c_int32,
                           C.POINTER(lsr_cond), C.c_int64, C.POINTER(C.c_int64)]),
     "lsr_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(lsr_job_result)]),
@@ -162,6 +166,26 @@ def lsr_check_args(grid: lsr_grid, stencil_id: int, reduce_op: int, cond: lsr_co
                    max_iter: int) -> int:
     """Returns the status lsr_run would give for these arguments (no device needed)."""
     return lib().lsr_check_args(C.byref(grid), stencil_id, reduce_op, C.byref(cond), max_iter)
+
+
+def lsr_autotune(ctx: int, stencil_id: int, dtype: int, rows: int, cols: int, check_every: int,
+                 max_iter: int = 0) -> lsr_tuning:
+    best = lsr_tuning()
+    _check(lib().lsr_autotune(ctx, stencil_id, dtype, rows, cols, check_every, max_iter,
+                              C.byref(best)))
+    return best
+
+
+def lsr_tune_export(ctx: int) -> str:
+    need = C.c_uint64(0)
+    _check(lib().lsr_tune_export(ctx, None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib().lsr_tune_export(ctx, buf, need.value, C.byref(need)))
+    return buf.value.decode()
+
+
+def lsr_tune_import(ctx: int, text: str) -> None:
+    _check(lib().lsr_tune_import(ctx, text.encode()))
 
 
 def lsr_probe_copy(ctx: int, dst_ptr: int, src_ptr: int, nbytes: int, iters: int) -> float:

@@ -1,0 +1,268 @@
+// Autotuner: measures candidate launch settings for a job description on the
+// device and keeps the fastest per key (stencil, dtype, size class, check
+// period). lsr_run consults the table whenever the context's overrides leave
+// the launch shape automatic, so a job's settings are a pure function of its key
+// (and of the table), the same whatever else runs. The table round-trips as JSON
+// text tagged with the device's architecture name.
+#include "runtime_internal.hpp"
+
+using namespace lsr_rt;
+
+namespace lsr_rt {
+
+namespace {
+
+int bit_length(int64_t v) {
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+bool automatic_shape(const lsr_tuning& t) {
+    return t.tile_rows == 0 && t.tb_depth == 0 && t.waves == 0 && t.unroll == 0;
+}
+
+// Candidate settings for one job description.
+std::vector<lsr_tuning> candidates(int stencil) {
+    std::vector<lsr_tuning> out;
+    auto add = [&](int tile_rows, int depth, int waves, int unroll) {
+        lsr_tuning t{};
+        t.tile_rows = tile_rows;
+        t.tb_depth = depth;
+        t.waves = waves;
+        t.unroll = unroll;
+        out.push_back(t);
+    };
+    if (stencil == LSR_ST_LIFE) {
+        for (int tr : {8, 16, 32, 64, 128}) add(tr, 1, 0, 0);
+        return out;
+    }
+    static constexpr int kUnfused[][2] = {{1, 8}, {2, 8}, {4, 4}, {4, 8}, {4, 16}};
+    for (const auto& s : kUnfused)
+        for (int tr : {8, 16, 32}) add(tr, 1, s[0], s[1]);
+    for (int depth : {2, 4, 5, 8, 10})
+        for (int waves : {1, 2, 4})
+            for (int tr : {0, 4, 8, 16, 32, 48, 64}) add(tr, depth, waves, 0);
+    return out;
+}
+
+const char* arch_name(int device) {
+    static thread_local char name[64];
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    std::snprintf(name, sizeof name, "%s", p.gcnArchName);
+    // keep the base name (gfx950), not the feature suffixes
+    for (char* c = name; *c; ++c)
+        if (*c == ':') *c = 0;
+    return name;
+}
+
+}  // namespace
+
+TuneKey tune_key(int stencil, int dtype, int64_t rows, int64_t cols, int check_every) {
+    return TuneKey{stencil, dtype, bit_length(rows), bit_length(cols), check_every};
+}
+
+}  // namespace lsr_rt
+
+lsr_tuning lsr_ctx::tuned_for(const lsr_grid& g, int stencil, int check_every) const {
+    lsr_tuning t = tuning;
+    if (!automatic_shape(t)) return t;
+    auto it = tune_table.find(tune_key(stencil, g.dtype, g.rows, g.cols, check_every));
+    if (it == tune_table.end()) return t;
+    const lsr_tuning& w = it->second.tuning;
+    t.tile_rows = w.tile_rows;
+    t.tb_depth = w.tb_depth;
+    t.waves = w.waves;
+    t.unroll = w.unroll;
+    return t;
+}
+
+extern "C" {
+
+lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t rows, int64_t cols,
+                        int32_t check_every, int64_t max_iter, lsr_tuning* best_out) {
+    if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
+    if (ctx->batched) return fail(LSR_EINVAL, "the autotuner measures the plain path (non-batched context)");
+    if (stencil_id == LSR_ST_RESTORE) return fail(LSR_EINVAL, "restoration has no launch shapes to tune");
+    if (rows < 1 || cols < 1 || rows > (1 << 20) || cols > (1 << 20))
+        return fail(LSR_EINVAL, "rows and cols must be in [1, 2^20]");
+    const size_t esz = dtype_size(dtype);
+    const int64_t pitch = (cols * (int64_t)esz + 255) / 256 * 256 / (int64_t)esz;
+    const size_t bytes = (size_t)rows * (size_t)pitch * esz;
+    const bool helm = stencil_id == LSR_ST_HELMHOLTZ5;
+    lsr_grid g{};
+    g.rows = rows;
+    g.cols = cols;
+    g.pitch = pitch;
+    g.dtype = dtype;
+    g.bc = stencil_id == LSR_ST_LIFE ? LSR_BC_TORUS : LSR_BC_RING;
+    g.param[0] = 1.0;
+    g.param[1] = 1.0 / (double)std::max<int64_t>(rows - 1, 1);
+    lsr_cond cond{};
+    cond.kind = LSR_COND_NEVER;
+    cond.check_every = check_every;
+    cond.stable_window = 1;
+    cond.threshold = 0.0;
+    // a short run of the same loop: enough sweeps for several launches at every depth
+    const double cells = (double)rows * (double)cols;
+    int64_t sweeps = (int64_t)std::min(400.0, std::max(40.0, 2.0e9 / std::max(cells, 1.0)));
+    sweeps = (sweeps + 39) / 40 * 40;
+    if (max_iter > 0) sweeps = std::min<int64_t>(sweeps, max_iter);
+    const int reduce = stencil_id == LSR_ST_LIFE ? LSR_RED_SUM : LSR_RED_MAX_ABS_DELTA;
+    g.data = reinterpret_cast<void*>(16);   // validation only checks for NULL
+    g.env0 = helm ? g.data : nullptr;
+    lsr_status v = validate(&g, stencil_id, reduce, &cond, sweeps);
+    if (v != LSR_OK) return v;
+
+    HIP_TRY(hipSetDevice(ctx->device));
+    void* grid_buf = nullptr;
+    void* env_buf = nullptr;
+    lsr_status st = ctx->pool.alloc(bytes, &grid_buf);
+    if (st == LSR_OK && helm) st = ctx->pool.alloc(bytes, &env_buf);
+    if (st != LSR_OK) {
+        ctx->pool.release(grid_buf);
+        return st;
+    }
+    g.data = grid_buf;
+    g.env0 = env_buf;
+    hipError_t e = hipMemsetAsync(grid_buf, 0, bytes, ctx->user_stream);
+    if (e == hipSuccess && env_buf) e = hipMemsetAsync(env_buf, 0, bytes, ctx->user_stream);
+    if (e != hipSuccess) {
+        ctx->pool.release(grid_buf);
+        ctx->pool.release(env_buf);
+        return fail(LSR_EDEVICE, "autotune scratch: %s", hipGetErrorString(e));
+    }
+
+    lsr_tuning base;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        base = ctx->tuning;
+    }
+    lsr_tuning best{};
+    double best_ms = 1e300;
+    for (const lsr_tuning& cand : candidates(stencil_id)) {
+        lsr_tuning t = base;
+        t.tile_rows = cand.tile_rows;
+        t.tb_depth = cand.tb_depth;
+        t.waves = cand.waves;
+        t.unroll = cand.unroll;
+        double ms = 1e300;
+        for (int rep = 0; rep < 2 && st == LSR_OK; ++rep) {   // the first run also warms up
+            std::unique_ptr<Job> j(new Job());
+            j->grid = g;
+            j->xgrid = g;
+            j->stencil = stencil_id;
+            j->cond = cond;
+            j->max_iter = sweeps;
+            lsr_job id = 0;
+            st = submit_plain(ctx, std::move(j), &g, stencil_id, reduce, &cond, sweeps, t, &id);
+            if (st != LSR_OK) break;
+            lsr_job_result r{};
+            st = lsr_result(ctx, id, 1, &r);
+            if (st == LSR_OK) ms = std::min(ms, r.device_ms);
+        }
+        if (st != LSR_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipStreamSynchronize(ctx->user_stream);
+    ctx->pool.release(grid_buf);
+    ctx->pool.release(env_buf);
+    if (st != LSR_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        TuneEntry& en = ctx->tune_table[tune_key(stencil_id, dtype, rows, cols, check_every)];
+        en.tuning = best;
+        en.us_per_sweep = best_ms * 1e3 / (double)sweeps;
+    }
+    if (best_out) *best_out = best;
+    return LSR_OK;
+}
+
+lsr_status lsr_tune_export(lsr_ctx* ctx, char* buf, uint64_t cap, uint64_t* len_out) {
+    if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
+    std::string s = "{\"arch\": \"";
+    s += arch_name(ctx->device);
+    s += "\", \"entries\": [";
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        bool first = true;
+        for (const auto& kv : ctx->tune_table) {
+            const TuneKey& k = kv.first;
+            const lsr_tuning& t = kv.second.tuning;
+            char line[512];
+            std::snprintf(line, sizeof line,
+                          "%s\n  {\"stencil\": %d, \"dtype\": %d, \"rows_log2\": %d, \"cols_log2\": %d, "
+                          "\"check_every\": %d, \"tile_rows\": %d, \"tb_depth\": %d, \"waves\": %d, "
+                          "\"unroll\": %d, \"us_per_sweep\": %.6g}",
+                          first ? "" : ",", k.stencil, k.dtype, k.rows_log2, k.cols_log2,
+                          k.check_every, t.tile_rows, t.tb_depth, t.waves, t.unroll,
+                          kv.second.us_per_sweep);
+            s += line;
+            first = false;
+        }
+    }
+    s += "\n]}\n";
+    if (len_out) *len_out = s.size() + 1;
+    if (!buf || cap < s.size() + 1) {
+        if (buf) return fail(LSR_EINVAL, "buffer too small: %llu bytes needed", (unsigned long long)(s.size() + 1));
+        return LSR_OK;
+    }
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return LSR_OK;
+}
+
+lsr_status lsr_tune_import(lsr_ctx* ctx, const char* json) {
+    if (!ctx || !json) return fail(LSR_EINVAL, "ctx and json must not be NULL");
+    const std::string s(json);
+    // "arch": "<name>" must match this device
+    const std::string want = std::string("\"arch\": \"") + arch_name(ctx->device) + "\"";
+    if (s.find(want) == std::string::npos)
+        return fail(LSR_EINVAL, "tuning table is for another architecture (expected %s)", want.c_str());
+    auto field = [](const std::string& obj, const char* name, double* v) {
+        const std::string key = std::string("\"") + name + "\":";
+        const size_t p = obj.find(key);
+        if (p == std::string::npos) return false;
+        char* end = nullptr;
+        *v = std::strtod(obj.c_str() + p + key.size(), &end);
+        return end != obj.c_str() + p + key.size();
+    };
+    std::map<TuneKey, TuneEntry> parsed;
+    size_t pos = s.find('[');
+    if (pos == std::string::npos) return fail(LSR_EINVAL, "no entries list");
+    while (true) {
+        const size_t a = s.find('{', pos);
+        if (a == std::string::npos) break;
+        const size_t b = s.find('}', a);
+        if (b == std::string::npos) return fail(LSR_EINVAL, "unterminated entry");
+        const std::string obj = s.substr(a, b - a + 1);
+        const char* names[] = {"stencil", "dtype", "rows_log2", "cols_log2", "check_every",
+                               "tile_rows", "tb_depth", "waves", "unroll", "us_per_sweep"};
+        double v[10];
+        for (int i = 0; i < 10; ++i)
+            if (!field(obj, names[i], &v[i])) return fail(LSR_EINVAL, "entry lacks \"%s\"", names[i]);
+        TuneKey k{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4]};
+        TuneEntry en{};
+        en.tuning.tile_rows = (int)v[5];
+        en.tuning.tb_depth = (int)v[6];
+        en.tuning.waves = (int)v[7];
+        en.tuning.unroll = (int)v[8];
+        en.us_per_sweep = v[9];
+        if (k.check_every < 1 || en.tuning.tile_rows < 0 || en.tuning.tb_depth < 0 ||
+            en.tuning.waves < 0 || en.tuning.unroll < 0)
+            return fail(LSR_EINVAL, "entry has an out-of-range field");
+        parsed[k] = en;
+        pos = b + 1;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const auto& kv : parsed) ctx->tune_table[kv.first] = kv.second;
+    return LSR_OK;
+}
+
+}  // extern "C"

@@ -497,7 +497,19 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     lsr_tuning tun;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        tun = ctx->tuning;
+        tun = ctx->tuned_for(*grid, stencil_id, cond->check_every);
+    }
+    return submit_plain(ctx, std::move(j), grid, stencil_id, reduce_op, cond, max_iter, tun, job_out);
+}
+
+}  // extern "C"
+
+// The plain (one job at a time) path of lsr_run with the launch settings resolved.
+lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
+                                int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
+                                int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out) {
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
         if (ctx->free_slots.empty()) return fail(LSR_EBUSY, "too many jobs in flight");
         j->slot = ctx->free_slots.back();
         ctx->free_slots.pop_back();
@@ -621,6 +633,8 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     *job_out = raw->id;
     return LSR_OK;
 }
+
+extern "C" {
 
 lsr_status lsr_result(lsr_ctx* ctx, lsr_job job, int32_t wait, lsr_job_result* out) {
     if (!ctx || !out) return fail(LSR_EINVAL, "ctx and out must not be NULL");

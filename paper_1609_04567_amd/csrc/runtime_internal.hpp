@@ -230,6 +230,24 @@ lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* 
 // Kernel arguments of a Jacobi job's sweep from src to dst (its exec grid).
 lsr::JacobiArgs jacobi_args(const Job* j, const void* src, void* dst);
 
+// Key of the autotuner's table: a job's stencil, dtype, size class (bit lengths
+// of rows and cols) and check period. A choice is a pure function of this key.
+struct TuneKey {
+    int stencil, dtype, rows_log2, cols_log2, check_every;
+    bool operator<(const TuneKey& o) const {
+        if (stencil != o.stencil) return stencil < o.stencil;
+        if (dtype != o.dtype) return dtype < o.dtype;
+        if (rows_log2 != o.rows_log2) return rows_log2 < o.rows_log2;
+        if (cols_log2 != o.cols_log2) return cols_log2 < o.cols_log2;
+        return check_every < o.check_every;
+    }
+};
+TuneKey tune_key(int stencil, int dtype, int64_t rows, int64_t cols, int check_every);
+struct TuneEntry {
+    lsr_tuning tuning;
+    double us_per_sweep;   // measured device time per sweep of the winner
+};
+
 }  // namespace lsr_rt
 
 
@@ -240,6 +258,10 @@ struct lsr_ctx {
     hipStream_t capture = nullptr;   // stream used only for graph capture
     lsr_rt::Pool pool;
     lsr_tuning tuning{};
+    std::map<lsr_rt::TuneKey, lsr_rt::TuneEntry> tune_table;   // autotuner's choices (under mu)
+    // Launch settings for a job: the context's overrides, or, when those leave the
+    // launch shape automatic, the autotuner's entry for the job's key (caller holds mu).
+    lsr_tuning tuned_for(const lsr_grid& g, int stencil, int check_every) const;
     lsr::JobState* mirrors_host = nullptr;
     lsr::JobState* mirrors_dev = nullptr;
     std::vector<int> free_slots;
@@ -288,3 +310,10 @@ struct lsr_ctx {
     lsr_status engine_setup();
     void engine_teardown();
 };
+
+namespace lsr_rt {
+lsr_status submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
+                        int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
+                        int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out);
+}  // namespace lsr_rt
+

@@ -1,0 +1,76 @@
+"""The autotuner through the C ABI: it measures candidates on the device, later
+automatic jobs of the same key take its winner (results still match the oracle
+exactly), and its table round-trips through JSON."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1609_04567_amd as L
+from paper_1609_04567_amd import inputs as I
+from gpu_helpers import run_jacobi, run_life, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def tctx():
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def test_helmholtz_tuned_job_matches_oracle(tctx):
+    say("autotune helmholtz 300^2 fp64")
+    best = tctx.autotune(L.LSR_ST_HELMHOLTZ5, L.LSR_F64, 300, 300, 10, 160)
+    say(f"  winner tile_rows={best.tile_rows} depth={best.tb_depth} waves={best.waves} "
+        f"unroll={best.unroll}")
+    table = json.loads(L.lsr_tune_export(tctx.handle))
+    assert table["arch"].startswith("gfx")
+    (e,) = table["entries"]
+    assert (e["stencil"], e["dtype"], e["rows_log2"], e["cols_log2"], e["check_every"]) == \
+        (L.LSR_ST_HELMHOLTZ5, L.LSR_F64, 9, 9, 10)
+    assert (e["tile_rows"], e["tb_depth"], e["waves"], e["unroll"]) == \
+        (best.tile_rows, best.tb_depth, best.waves, best.unroll) and e["us_per_sweep"] > 0
+    h = I.helmholtz_input(300)
+    o, ro = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=1.0, h=h.h, reduce_op=O.RED_L2_DELTA,
+                         thr=1e-9, check_every=10, max_iter=160)
+    x, r = run_jacobi(tctx, h.u0, helm=True, g=h.g, alpha=1.0, h=h.h, reduce_op=L.LSR_RED_L2_DELTA,
+                      thr=1e-9, check_every=10, max_iter=160)
+    assert r.iterations == 160 and np.array_equal(x, o)
+    assert r.sweeps_per_launch == max(best.tb_depth, 1)
+
+
+def test_life_tuned_job_matches_oracle(tctx):
+    say("autotune life 200x208")
+    tctx.autotune(L.LSR_ST_LIFE, L.LSR_U8, 200, 208, 1, 300)
+    a = I.life_input(200, 208, seed=3)
+    o, ro = O.life_run(a, bc=O.BC_TORUS, stable_window=10, max_iter=300)
+    x, r = run_life(tctx, a, window=10, max_iter=300)
+    assert r.iterations == ro.n and np.array_equal(x, o)
+
+
+def test_table_round_trips_and_rejects_other_arch(tctx):
+    say("autotune table round trip")
+    tctx.autotune(L.LSR_ST_LAPLACE5, L.LSR_F32, 130, 100, 1, 200)
+    text = L.lsr_tune_export(tctx.handle)
+    other = L.Context(0)
+    try:
+        L.lsr_tune_import(other.handle, text)
+        assert L.lsr_tune_export(other.handle) == text
+        bad = text.replace(json.loads(text)["arch"], "gfx000")
+        with pytest.raises(L.LsrError):
+            L.lsr_tune_import(other.handle, bad)
+        assert L.lsr_tune_export(other.handle) == text
+    finally:
+        other.close()
+
+
+def test_batched_context_is_rejected():
+    c = L.Context(0, batched=True)
+    try:
+        with pytest.raises(L.LsrError):
+            c.autotune(L.LSR_ST_LAPLACE5, L.LSR_F64, 64, 64, 1)
+    finally:
+        c.close()
