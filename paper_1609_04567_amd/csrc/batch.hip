@@ -88,6 +88,152 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
                                          nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Whole-grid-in-LDS execution of a small job (both buffers fit in the 160 KiB of
+// one CU's LDS): one 1024-thread workgroup loads the grid once, runs the whole
+// loop in LDS (sweep, reduce, condition, as in the -d/-s procedures of
+// Sect. 3.1, with the same per-cell update and stopping rule as the tiled
+// path), then writes the stop iterate to buf[n % 2] and publishes the state.
+// Cells are dealt to threads in row-major order; the reduce is the fixed
+// workgroup tree. A small job therefore finishes within one round; a cancel
+// posted while it runs takes effect only if it arrives before that round.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallWaves = kSmallThreads / 64;
+
+template <typename T, bool HELM>
+__device__ void small_jacobi(const BatchJob& J, T* A, T* B, double* red_lds, int* flag) {
+    const int tid = threadIdx.x;
+    const int64_t rows = J.rows, cols = J.cols, cells = rows * cols;
+    JobState s = *J.st;
+    const T* src = static_cast<const T*>(J.buf[s.n & 1]);
+    for (int64_t k = tid; k < cells; k += kSmallThreads) {
+        const int64_t i = k / cols, jj = k - i * cols;
+        A[k] = B[k] = src[i * J.pitch + jj];   // B keeps the fixed ring too
+    }
+    __syncthreads();
+    const T* g = static_cast<const T*>(J.env);
+    const T rd = (T)J.rd, rd_lo = (T)(0.25 - J.rd);
+    const int64_t icols = cols - 2, inner = (rows - 2) * icols;
+    int64_t n = s.n;
+    while (n < J.ctl.max_iter) {
+        const int64_t n1 = n + 1;
+        const bool check = is_check_sweep(n1, J.ctl);
+        double acc = 0.0;
+        for (int64_t k = tid; k < inner; k += kSmallThreads) {
+            const int64_t i = 1 + k / icols, jj = 1 + (k - (i - 1) * icols);
+            const int64_t c = i * cols + jj;
+            const T v = jacobi_update<T, HELM>(A[c - cols], A[c + cols], A[c - 1], A[c + 1],
+                                               HELM ? g[i * J.pitch + jj] : T(0), rd, rd_lo, i, jj,
+                                               (uint32_t)n1);
+            if (check) acc = jacobi_accum(J.ctl.reduce, acc, (double)v - (double)A[c]);
+            B[c] = v;
+        }
+        __syncthreads();
+        T* t = A;
+        A = B;
+        B = t;
+        n = n1;
+        if (check) {
+            const double r = block_reduce<kSmallWaves>(acc, J.ctl.reduce == RED_MAX_ABS, red_lds);
+            if (tid == 0) {
+                apply_check(s, J.ctl, n1, r, 0);
+                *flag = s.done;
+            }
+            __syncthreads();
+            if (*flag) break;
+        }
+    }
+    T* dst = static_cast<T*>(const_cast<void*>(J.buf[n & 1]));
+    for (int64_t k = tid; k < cells; k += kSmallThreads) {
+        const int64_t i = k / cols, jj = k - i * cols;
+        dst[i * J.pitch + jj] = A[k];
+    }
+    if (tid == 0) publish_state(J.st, J.mirror, s);
+}
+
+__device__ void small_life(const BatchJob& J, uint8_t* A, uint8_t* B, unsigned long long* red_lds,
+                           int* flag) {
+    const int tid = threadIdx.x;
+    const int64_t rows = J.rows, cols = J.cols, cells = rows * cols;
+    JobState s = *J.st;
+    const uint8_t* src = static_cast<const uint8_t*>(J.buf[s.n & 1]);
+    for (int64_t k = tid; k < cells; k += kSmallThreads) {
+        const int64_t i = k / cols, jj = k - i * cols;
+        A[k] = src[i * J.pitch + jj];   // 0/1 after the job's initial count pass
+    }
+    __syncthreads();
+    int64_t n = s.n;
+    while (n < J.ctl.max_iter) {
+        const int64_t n1 = n + 1;
+        const bool check = is_check_sweep(n1, J.ctl);
+        unsigned long long cnt = 0;
+        for (int64_t k = tid; k < cells; k += kSmallThreads) {
+            const int64_t i = k / cols, jj = k - i * cols;
+            int nb = 0;
+#pragma unroll
+            for (int di = -1; di <= 1; ++di)
+#pragma unroll
+                for (int dj = -1; dj <= 1; ++dj) {
+                    if (di == 0 && dj == 0) continue;
+                    int64_t r = i + di, c = jj + dj;
+                    if (J.torus) {
+                        r = r < 0 ? r + rows : r >= rows ? r - rows : r;
+                        c = c < 0 ? c + cols : c >= cols ? c - cols : c;
+                    } else if (r < 0 || r >= rows || c < 0 || c >= cols) {
+                        continue;
+                    }
+                    nb += A[r * cols + c];
+                }
+            const uint8_t v = (nb == 3 || (A[k] && nb == 2)) ? 1 : 0;
+            B[k] = v;
+            cnt += v;
+        }
+        __syncthreads();
+        uint8_t* t = A;
+        A = B;
+        B = t;
+        n = n1;
+        if (check) {
+            const unsigned long long total = block_reduce_u64<kSmallWaves>(cnt, red_lds);
+            if (tid == 0) {
+                apply_check(s, J.ctl, n1, 0.0, total);
+                *flag = s.done;
+            }
+            __syncthreads();
+            if (*flag) break;
+        }
+    }
+    uint8_t* dst = static_cast<uint8_t*>(const_cast<void*>(J.buf[n & 1]));
+    for (int64_t k = tid; k < cells; k += kSmallThreads) {
+        const int64_t i = k / cols, jj = k - i * cols;
+        dst[i * J.pitch + jj] = A[k];
+    }
+    if (tid == 0) publish_state(J.st, J.mirror, s);
+}
+
+// The job's descriptor travels by value: the engine rebuilds its device job table
+// while a small job may still be running on its own stream.
+template <int KIND>
+__global__ __launch_bounds__(kSmallThreads) void batch_small_kernel(const BatchJob J) {
+    __shared__ __attribute__((aligned(16))) unsigned char grid_lds[kSmallLdsBytes];
+    __shared__ double red_d[kSmallWaves];
+    __shared__ unsigned long long red_u[kSmallWaves];
+    __shared__ int flag;
+    if (J.st->done || J.st->n >= J.ctl.max_iter) return;
+    const int64_t cells = J.rows * J.cols;
+    if (KIND == BK_SMALL_F64) {
+        double* A = reinterpret_cast<double*>(grid_lds);
+        if (J.helm) small_jacobi<double, true>(J, A, A + cells, red_d, &flag);
+        else small_jacobi<double, false>(J, A, A + cells, red_d, &flag);
+    } else if (KIND == BK_SMALL_F32) {
+        float* A = reinterpret_cast<float*>(grid_lds);
+        if (J.helm) small_jacobi<float, true>(J, A, A + cells, red_d, &flag);
+        else small_jacobi<float, false>(J, A, A + cells, red_d, &flag);
+    } else {
+        small_life(J, grid_lds, grid_lds + cells, red_u, &flag);
+    }
+}
+
 // One workgroup per job: count the job's round, and fold and evaluate each check
 // the round holds, in sweep order (the last level's only, without mc), stopping
 // at the first that ends the loop.
@@ -136,6 +282,13 @@ void launch_kind(const BatchJob* jobs, const WorkItem* work, int groups, hipStre
 void batch_geometry(BatchJob& j, int is_life, int f32) {
     j.step = 1;
     j.mc = 0;
+    if (batch_small_fits(j.rows, j.cols, is_life ? 1 : f32 ? 4 : 8)) {
+        j.kind = is_life ? BK_SMALL_LIFE : f32 ? BK_SMALL_F32 : BK_SMALL_F64;
+        j.tile_rows = (int)j.rows;
+        j.strips = 1;
+        j.tiles = 1;   // one work item = the whole job; no partials
+        return;
+    }
     if (is_life) {
         // rows are 16-byte aligned with zeroed padding to a multiple of 16 cells
         j.kind = BK_LIFE_SWAR;
@@ -179,6 +332,17 @@ hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int ki
         case BK_JAC_F64_TB5_MC: launch_kind<BK_JAC_F64_TB5_MC>(jobs, work, groups, s); break;
         case BK_JAC_F32_TB5_MC: launch_kind<BK_JAC_F32_TB5_MC>(jobs, work, groups, s); break;
         case BK_LIFE_SWAR: launch_kind<BK_LIFE_SWAR>(jobs, work, groups, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_small(const BatchJob& j, hipStream_t s) {
+    const dim3 g(1), b(kSmallThreads);
+    switch (j.kind) {
+        case BK_SMALL_F64: hipLaunchKernelGGL(batch_small_kernel<BK_SMALL_F64>, g, b, 0, s, j); break;
+        case BK_SMALL_F32: hipLaunchKernelGGL(batch_small_kernel<BK_SMALL_F32>, g, b, 0, s, j); break;
+        case BK_SMALL_LIFE: hipLaunchKernelGGL(batch_small_kernel<BK_SMALL_LIFE>, g, b, 0, s, j); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -38,6 +38,7 @@ constexpr int kWindowsInFlight = 2;
 }  // namespace
 
 lsr_status lsr_ctx::engine_setup() {
+    HIP_TRY(hipStreamCreateWithFlags(&small_stream, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&d_jobs, sizeof(lsr::BatchJob) * kMaxBatch));
     HIP_TRY(hipMalloc(&d_work, sizeof(lsr::WorkItem) * (kMaxWork + kPad)));
     for (int i = 0; i < 2; ++i) {
@@ -52,6 +53,11 @@ lsr_status lsr_ctx::engine_setup() {
 
 void lsr_ctx::engine_teardown() {
     (void)hipStreamSynchronize(stream);
+    if (small_stream) {
+        (void)hipStreamSynchronize(small_stream);
+        (void)hipStreamDestroy(small_stream);
+        small_stream = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
         if (h_jobs[i]) (void)hipHostFree(h_jobs[i]);
@@ -68,7 +74,9 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     const bool life = j->stencil == LSR_ST_LIFE;
     const bool f32 = g.dtype == LSR_F32;
     j->xgrid = g;
-    j->staged = needs_staging(g, j->stencil);
+    // small grids are swept in LDS from any pitch or alignment: never staged
+    j->staged = !lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
+                needs_staging(g, j->stencil);
     if (j->staged) j->xgrid.pitch = stage_pitch(g);   // buffers assigned at admission
     lsr::BatchJob& d = j->desc;
     d = lsr::BatchJob{};
@@ -222,6 +230,18 @@ lsr_status lsr_ctx::engine_admit() {
                                      g.rows, hipMemcpyDeviceToDevice, stream));
             HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream));
         }
+        if (lsr::batch_is_small(j->desc)) {
+            // the whole loop in one workgroup on the second stream, after the init
+            hipEvent_t ready = get_event();
+            if (!ready) return fail(LSR_EDEVICE, "event pool");
+            HIP_TRY(hipEventRecord(ready, stream));
+            HIP_TRY(hipStreamWaitEvent(small_stream, ready, 0));
+            put_event(ready);
+            HIP_TRY(lsr::launch_batch_small(j->desc, small_stream));
+            j->ev_small = get_event();
+            if (!j->ev_small) return fail(LSR_EDEVICE, "event pool");
+            HIP_TRY(hipEventRecord(j->ev_small, small_stream));
+        }
         j->t_admit = Clock::now();
         tables_dirty = true;
     }
@@ -232,8 +252,10 @@ lsr_status lsr_ctx::engine_upload() {
     HIP_TRY(hipEventSynchronize(stage_ev[s]));
     lsr::BatchJob* hj = h_jobs[s];
     lsr::WorkItem* hw = h_work[s];
-    const int n = (int)active.size();
-    for (int i = 0; i < n; ++i) hj[i] = active[i]->desc;
+    int n = 0;
+    for (Job* j : active)
+        if (!lsr::batch_is_small(j->desc)) hj[n++] = j->desc;
+    n_table = n;
     int64_t pos = 0;
     for (int k = 1; k <= lsr::kBatchKinds; ++k) {
         seg_off[k] = (int)pos;
@@ -253,10 +275,12 @@ lsr_status lsr_ctx::engine_upload() {
 }
 
 lsr_status lsr_ctx::engine_window() {
+    if (n_table == 0) return LSR_OK;   // only small jobs, each on the second stream
     double round_us = kRoundOverheadUs;
-    for (Job* j : active) round_us += j->est_us;
+    for (Job* j : active)
+        if (!lsr::batch_is_small(j->desc)) round_us += j->est_us;
     const int rounds = (int)std::min<double>(kMaxRounds, std::max(1.0, std::floor(kWindowUs / round_us)));
-    const int n = (int)active.size();
+    const int n = n_table;
     for (int r = 0; r < rounds; ++r) {
         for (int k = 1; k <= lsr::kBatchKinds; ++k) {
             if (seg_len[k] == 0) continue;
@@ -272,9 +296,17 @@ void lsr_ctx::engine_scan() {
     keep.reserve(active.size());
     for (Job* j : active) {
         volatile lsr::JobState* m = j->mirror_host;
-        if (!m->done) {
+        const bool small = lsr::batch_is_small(j->desc);
+        // a small job is over when its launch is (its writes are then all visible)
+        const bool over = small ? hipEventQuery(j->ev_small) == hipSuccess : (bool)m->done;
+        if (!over) {
             keep.push_back(j);
             continue;
+        }
+        if (small) {
+            (void)hipStreamWaitEvent(stream, j->ev_small, 0);
+            put_event(j->ev_small);
+            j->ev_small = nullptr;
         }
         lsr::JobState fin;
         std::memcpy(&fin, (const void*)m, sizeof fin);
@@ -366,15 +398,28 @@ void lsr_ctx::serve() {
             }
         }
         if (s == LSR_OK && tables_dirty) s = engine_upload();
-        if (s == LSR_OK && !active.empty()) {
+        if (s == LSR_OK && n_table > 0) {
             s = engine_window();
             if (s == LSR_OK) {
                 hipEvent_t ev = get_event();
                 if (!ev || hipEventRecord(ev, stream) != hipSuccess) s = fail(LSR_EDEVICE, "event record failed");
                 else inflight.push_back(ev);
             }
+        } else if (s == LSR_OK && !active.empty() && inflight.empty()) {
+            // only small jobs (each a single launch on the second stream): poll them
+            const size_t before = active.size();
+            engine_scan();
+            bool waiting;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                waiting = pending.empty();
+            }
+            if (active.size() == before && waiting)
+                std::this_thread::sleep_for(std::chrono::microseconds(50));
         }
-        if (s == LSR_OK && (inflight.size() >= (size_t)kWindowsInFlight || (active.empty() && !inflight.empty()))) {
+        // drain the oldest window when two are queued, or when no further window
+        // will be enqueued (no table jobs left: only small jobs, or none, remain)
+        if (s == LSR_OK && (inflight.size() >= (size_t)kWindowsInFlight || (n_table == 0 && !inflight.empty()))) {
             hipEvent_t ev = inflight.front();
             inflight.pop_front();
             hipError_t e = hipEventSynchronize(ev);

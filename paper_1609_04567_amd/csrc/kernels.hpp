@@ -101,9 +101,18 @@ enum BatchKind : int32_t {
     BK_JAC_F32_TB2 = 5,
     BK_JAC_F64_TB5_MC = 6, // FP64 Jacobi, 5 fused sweeps per round, any checks inside
     BK_JAC_F32_TB5_MC = 7,
-    BK_LIFE_SWAR = 8       // Life, 16 cells per lane, one generation per round
+    BK_LIFE_SWAR = 8,      // Life, 16 cells per lane, one generation per round
+    BK_SMALL_F64 = 9,      // whole job in LDS, one launch on the engine's second stream: FP64 Jacobi
+    BK_SMALL_F32 = 10,     //   FP32 Jacobi
+    BK_SMALL_LIFE = 11     //   Life
 };
-constexpr int kBatchKinds = 8;
+constexpr int kBatchKinds = 11;
+// A grid runs whole-grid-in-LDS when both of its buffers fit in this many bytes
+// (rows * cols * element size * 2; one 1024-thread workgroup per job).
+constexpr int64_t kSmallLdsBytes = 160 * 1024 - 1024;
+inline bool batch_small_fits(int64_t rows, int64_t cols, int esz) {
+    return rows * cols * (int64_t)esz * 2 <= kSmallLdsBytes;
+}
 
 // Device descriptor of one job of a batch. The job's completed-sweep count n
 // lives in its JobState; a round advances it by `step` sweeps, reading
@@ -131,7 +140,8 @@ struct WorkItem {
 
 // Family, step and tile geometry a job gets inside a batch: a function of its
 // shape, dtype and loop control only (j.ctl must be set), so its reduce order is
-// the same alone and in any mix. Jacobi jobs take the deepest fused depth that
+// the same alone and in any mix. Small grids (batch_small_fits) run their whole
+// loop in LDS in one round; other Jacobi jobs take the deepest fused depth that
 // divides both the check period and the cap, else depth 5 with checks inside.
 void batch_geometry(BatchJob& j, int is_life, int f32);
 // One launch per kernel family: `work` points at that family's segment of the
@@ -141,6 +151,11 @@ constexpr int kBatchWorkQuantum = 32;
 hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
                               int nwork_padded, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchJob* jobs, int njobs, hipStream_t s);
+inline bool batch_is_small(const BatchJob& j) {
+    return j.kind == BK_SMALL_F64 || j.kind == BK_SMALL_F32 || j.kind == BK_SMALL_LIFE;
+}
+// Runs a small job's whole loop in one workgroup (its state must be initialised).
+hipError_t launch_batch_small(const BatchJob& j, hipStream_t s);
 
 // HBM copy probe: bytes must be a multiple of 16, buffers 16-byte aligned.
 hipError_t launch_copy16(const void* src, void* dst, int64_t bytes, hipStream_t s);

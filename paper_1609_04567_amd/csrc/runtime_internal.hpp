@@ -202,6 +202,7 @@ struct Job {
     int nparts_alloc = 0;               // partials allocated (tiles, or the initial count's)
     double est_us = 0.0;                // estimated device time of one sweep
     bool cancel_posted = false;         // a cancel kernel has been enqueued
+    hipEvent_t ev_small = nullptr;      // end of a small job's launch on the second stream
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
 
     // Returns the job's scratch (partner, staged copies, partials, state) to the pool.
@@ -255,6 +256,7 @@ struct lsr_ctx {
     int device = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;    // internal execution stream
+    hipStream_t small_stream = nullptr;  // batched engine: whole-grid-in-LDS jobs
     hipStream_t capture = nullptr;   // stream used only for graph capture
     lsr_rt::Pool pool;
     lsr_tuning tuning{};
@@ -298,6 +300,7 @@ struct lsr_ctx {
     int seg_off[lsr::kBatchKinds + 1] = {};
     int seg_len[lsr::kBatchKinds + 1] = {};
     int64_t work_items = 0;
+    int n_table = 0;                    // jobs in the device table (small jobs are not)
     bool tables_dirty = false;
     void serve();
     lsr_status engine_submit(lsr_rt::Job* j);

@@ -68,7 +68,10 @@ def _submit(ctx, t, kw):
 MIX = [("laplace", 128, 1, False, 600), ("laplace", 200, 2, True, 600),
        ("helmholtz", 129, 0, False, 700), ("helmholtz", 257, 0, True, 500),
        ("life", 128, 3, False, 2000), ("life", 160, 4, False, 900), ("life", 130, 5, False, 500),
-       ("laplace", 333, 6, False, 300), ("laplace", 67, 7, True, 400)]
+       ("laplace", 333, 6, False, 300), ("laplace", 67, 7, True, 400),
+       # grids whose two buffers fit in LDS run whole in one workgroup
+       ("helmholtz", 97, 0, False, 700), ("helmholtz", 140, 0, True, 500),
+       ("laplace", 60, 8, False, 900)]
 
 
 def test_mixed_batch_matches_oracle(bctx):
