@@ -255,7 +255,8 @@ def test_model_flags_the_unguarded_west_halo():
 # schedule on the CPU (zeros outside the grid and before the stream start, a
 # zero west neighbour at lane 0 and east neighbour at lane 63, boundary cells
 # carried unchanged) and checks that the stored cells cover the interior
-# exactly once and equal K plain sweeps.
+# exactly once and equal K plain sweeps, and that the kernel's load guard only
+# lets in-grid rows be read.
 # ---------------------------------------------------------------------------
 
 def _tb_geometry(rows, cols, vec, nw, k, tile_rows):
@@ -286,13 +287,19 @@ def _tb_model(u, k, vec, nw, tile_rows):
             ohi = min(cw + k + ow, cols - 1)
             if vec > 1 and cw % vec:
                 loads_ok = False         # windows must start 16-byte aligned
-            # rows stream in groups of three; the unguarded (fast) path must only
-            # touch rows and columns inside the grid
+            # rows stream in groups of three (level-0 row i and g row i - 1 at
+            # step i); the kernel's load guard, as written: the fast path reads
+            # unguarded, the other path only rows in [0, rows)
             i_beg = r0 - k
             i_end = i_beg + (r1 + k - i_beg + 2) // 3 * 3
             edge = cw == 0 or cw + width > cols - 1
             fast = not edge and r0 - 2 * k >= 1 and i_end <= rows
-            if fast and not (i_beg - 1 >= 0 and i_end <= rows and cw + width <= cols):
+            for i in range(i_beg, i_end):
+                for row in (i, i - 1):
+                    read = fast or 0 <= row < rows
+                    if read and not 0 <= row < rows:
+                        loads_ok = False
+            if fast and cw + width > cols:
                 loads_ok = False
             level = {}
             for i in range(r0 - k, r1 + k):
