@@ -425,7 +425,7 @@ def main():
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--sweeps", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=200)
-    ap.add_argument("--cpu-sweeps", type=int, default=600)
+    ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
