@@ -43,38 +43,49 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(JobState* st, con
 }
 
 // Finalize of a fused launch that may hold several checks (sweeps
-// n_base + j0 + 1 .. n_base + j0 + K): evaluates them in sweep order, each from
-// its own slice of tiles partials, and stops at the first that ends the loop.
+// n_base + j0 + 1 .. n_base + j0 + K): wavefront l - 1 folds level l's slice of
+// tiles partials (lane-strided, then the fixed butterfly), all checked levels at
+// once; thread 0 then evaluates the checks in sweep order and stops at the first
+// that ends the loop.
 __global__ __launch_bounds__(kFinThreads) void finalize_levels_kernel(JobState* st,
                                                                       const void* partials,
                                                                       LoopCtl c, int j0, int K,
                                                                       int tiles, JobState* mirror) {
-    __shared__ double lds_d[kFinThreads / 64];
-    __shared__ unsigned long long lds_u[kFinThreads / 64];
-    __shared__ int stop;
+    __shared__ double rd_l[kFinThreads / 64];
+    __shared__ unsigned long long ru_l[kFinThreads / 64];
     if (st->done) return;
-    JobState s = *st;   // only thread 0's copy is updated
+    const int64_t nb = st->n_base;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave < K) {
+        const int64_t n = nb + j0 + wave + 1;
+        if (n <= c.max_iter && is_check_sweep(n, c)) {
+            const size_t off = (size_t)wave * (size_t)tiles;
+            if (c.reduce == RED_SUM) {
+                const unsigned long long* p = static_cast<const unsigned long long*>(partials) + off;
+                unsigned long long acc = 0;
+                for (int i = lane; i < c.nparts; i += 64) acc += p[i];
+                acc = wave_sum_u64(acc);
+                if (lane == 0) ru_l[wave] = acc;
+            } else {
+                const double* p = static_cast<const double*>(partials) + off;
+                const bool is_max = c.reduce == RED_MAX_ABS;
+                double acc = 0.0;
+                for (int i = lane; i < c.nparts; i += 64) acc = is_max ? max_nan(acc, p[i]) : acc + p[i];
+                acc = is_max ? wave_max(acc) : wave_sum(acc);
+                if (lane == 0) rd_l[wave] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    JobState s = *st;
     for (int lev = 1; lev <= K; ++lev) {
-        const int64_t n = s.n_base + j0 + lev;
+        const int64_t n = nb + j0 + lev;
         if (n > c.max_iter) break;
         if (!is_check_sweep(n, c)) continue;
-        const size_t off = (size_t)(lev - 1) * (size_t)tiles;
-        double rd = 0.0;
-        unsigned long long ru = 0;
-        if (c.reduce == RED_SUM)
-            ru = fold_partials_u64<kFinThreads>(static_cast<const unsigned long long*>(partials) + off,
-                                                c.nparts, lds_u);
-        else
-            rd = fold_partials<kFinThreads>(static_cast<const double*>(partials) + off, c.nparts,
-                                            c.reduce == RED_MAX_ABS, lds_d);
-        if (threadIdx.x == 0) {
-            apply_check(s, c, n, rd, ru);
-            stop = s.done;
-        }
-        __syncthreads();   // thread 0 is done with lds before the next fold
-        if (stop) break;
+        apply_check(s, c, n, rd_l[lev - 1], ru_l[lev - 1]);
+        if (s.done) break;
     }
-    if (threadIdx.x != 0) return;
     if (!s.done && j0 + K == c.chunk) s.n_base += c.chunk;
     publish_state(st, mirror, s);
 }
