@@ -13,7 +13,8 @@ host API overhead included). roofline: the sweep kernel's algorithmic traffic
 (24 B per cell update: read u, read g, write u') per launch, divided by its mean
 launch time measured with HIP events on the library's own stream (the job's
 device time over its sweep launches, so it also carries the small finalize
-kernels and launch gaps), against 8 TB/s.
+kernels and launch gaps), against 8 TB/s. plain_sweep: the same job run with one
+sweep per launch, outside the timed region, and its own fraction of 8 TB/s.
 
 Other workloads (--workload): laplace (256^2 FP64, 2000 sweeps), life (16384^2
 u8 torus, 2000 generations), restore (4096^2 two-phase restoration, FP64 and
@@ -40,8 +41,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash(files=("jacobi.hip", "jacobi_tb.hip", "tile_jacobi.hpp", "common.hpp",
-                              "kernels.hpp")) -> str:
+def kernel_source_hash(files=("jacobi.hip", "jacobi_tb.hip", "tile_jacobi.hpp",
+                              "common.hpp")) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_1609_04567_amd", "csrc", f), "rb") as fh:
@@ -149,6 +150,21 @@ def run_helmholtz(args, L, I, torch):
     out["effective_gbs"] = round(value * 24.0, 1)
     out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
                        "last_l2_update": results[-1].last_reduce}
+    if spl > 1 and not args.no_plain:
+        # the same job with one sweep per launch (outside the timed region): the plain
+        # sweep's own fraction of HBM bandwidth, 24 bytes per update
+        pctx = L.Context(0)
+        pctx.tune(tb_depth=1)
+        ps = 500
+        grids[0].zero_()
+        rp = pctx.run(grids[0], L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, ps, L.LSR_BC_RING,
+                      env0=g, param=(h.alpha, h.h))
+        assert rp.status == L.LSR_OK and rp.iterations == ps and rp.sweeps_per_launch == 1
+        sweep_s = rp.device_ms * 1e-3 / ps
+        out["plain_sweep"] = {"glups": round((n - 2) ** 2 / sweep_s / 1e9, 1), "sweeps": ps,
+                              "roofline": roofline(24.0 * (n - 2) ** 2, sweep_s,
+                                                   measured_traffic(f"jacobi5_helmholtz_f64_{n}"))}
+        pctx.close()
     if not args.no_cpu:
         import oracle as O
         t0 = time.perf_counter()
@@ -427,6 +443,8 @@ def main():
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the one-sweep-per-launch measurement beside a fused run")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
