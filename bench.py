@@ -227,7 +227,7 @@ def run_life(args, L, I, torch):
     s = I.life_input(n, seed=3)
     grids = [torch.from_numpy(s).to("cuda:0") for _ in range(args.steps + args.warmup)]
     ctx = L.Context(0)
-    ctx.tune(tile_rows=args.tile_rows, chunk=args.chunk, use_graph=args.graph)
+    ctx.tune(tile_rows=args.tile_rows, tb_depth=args.tb, chunk=args.chunk, use_graph=args.graph)
     copy_gbs = copy_probe(L, ctx, torch, "cuda:0")
     cond = L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10)
     step = lambda t: ctx.run(t, L.LSR_ST_LIFE, L.LSR_RED_SUM, cond, gens, L.LSR_BC_TORUS)
@@ -239,16 +239,24 @@ def run_life(args, L, I, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lups = sum(n * n * r.iterations for r in results)
-    per_launch_s = sum(r.device_ms for r in results) * 1e-3 / sum(r.iterations for r in results)
-    out = base_line("GLUP/s", round(lups / wall / 1e9, 2), "GLUP/s", args.steps, args.warmup,
+    spl = int(results[-1].sweeps_per_launch)   # generations fused per launch
+    launches = sum(-(-r.iterations // spl) for r in results)
+    per_launch_s = sum(r.device_ms for r in results) * 1e-3 / launches
+    value = lups / wall / 1e9
+    out = base_line("GLUP/s", round(value, 2), "GLUP/s", args.steps, args.warmup,
                     round(wall / args.steps * 1e3, 3), "u8",
                     {"workload": f"life-b3s23 {n}x{n} u8 torus, live count every generation, "
                                  f"stop when unchanged for 10 or {gens}", "rows": n, "cols": n,
-                     "generations": gens})
-    out["roofline"] = roofline(2.0 * n * n, per_launch_s,
-                               measured_traffic(f"life_swar_{n}", ("life.hip", "tile_life.hpp",
-                                                                   "common.hpp", "kernels.hpp")))
+                     "generations": gens, "generations_per_launch": spl})
+    # a launch reads and writes every cell once, whatever number of generations it fuses
+    if spl == 1:
+        kname, files = f"life_swar_{n}", ("life.hip", "tile_life.hpp", "common.hpp")
+    else:
+        kname, files = f"life_tb{spl}_{n}", ("life_tb.hip", "common.hpp")
+    out["roofline"] = roofline(2.0 * n * n, per_launch_s, measured_traffic(kname, files))
     out["copy_probe_gbs"] = copy_gbs
+    # bytes an unfused generation would move per cell, at the achieved update rate
+    out["effective_gbs"] = round(value * 2.0, 1)
     out["result"] = {"iterations": int(results[-1].iterations), "count": int(results[-1].last_count)}
     if not args.no_cpu:
         import oracle as O

@@ -153,13 +153,16 @@ typedef struct {
 /* Tuning overrides; 0 in a field means "choose automatically". */
 typedef struct {
     int32_t tile_rows;      /* rows each workgroup streams through per sweep */
-    int32_t tb_depth;       /* Jacobi sweeps fused per launch (temporal blocking); 1 = off,
-                               0 = the measured best compiled depth (2, 4, 5, 8, 10) that divides
-                               both check_every and max_iter. A depth is used only where it
-                               divides both and the grid is 16-byte aligned (pitch and
-                               buffers), else the job runs unfused. Fields are bit for bit
-                               those of unfused sweeps; the reduce value differs at most in
-                               the order of its partial sums. */
+    int32_t tb_depth;       /* sweeps (generations) fused per launch (temporal blocking); 1 = off.
+                               Jacobi: 2, 4, 5, 8 or 10; 0 = the measured best depth that
+                               divides both check_every and max_iter, else 5 with checks
+                               inside launches. Life: 2, 3, 4, 6 or 8; 0 = 4. A stop or cap
+                               inside a launch is replayed exactly from the launch's source.
+                               Fusion needs 16-byte aligned grids (pitch and buffers; Life
+                               also rows of a multiple of 16 cells), else the job runs
+                               unfused. Fields and counts are bit for bit those of unfused
+                               sweeps; a float reduce value differs at most in the order of
+                               its partial sums. Restoration is never fused. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
     int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblsr.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["control.hip", "jacobi.hip", "jacobi_tb.hip", "life.hip", "restore.hip", "probe.hip",
+SOURCES = ["control.hip", "jacobi.hip", "jacobi_tb.hip", "life.hip", "life_tb.hip", "restore.hip", "probe.hip",
            "batch.hip", "runtime.cpp", "engine.cpp", "autotune.cpp"]
 ARCH = os.environ.get("LSR_OFFLOAD_ARCH", "gfx950")
 

@@ -38,6 +38,8 @@ std::vector<lsr_tuning> candidates(int stencil) {
     };
     if (stencil == LSR_ST_LIFE) {
         for (int tr : {8, 16, 32, 64, 128}) add(tr, 1, 0, 0);
+        for (int depth : {2, 3, 4, 6, 8})
+            for (int tr : {16, 32, 64, 128}) add(tr, depth, 0, 0);
         return out;
     }
     static constexpr int kUnfused[][2] = {{1, 8}, {2, 8}, {4, 4}, {4, 8}, {4, 16}};

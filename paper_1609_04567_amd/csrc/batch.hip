@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
     constexpr bool MC = KindInfo<KIND>::mc;
     __shared__ __attribute__((aligned(16))) double ring_d[VEC == 2 ? tb_gring_elems<2, kWavesPerGroup, STEP>() : 1];
     __shared__ __attribute__((aligned(16))) float ring_f[VEC == 4 ? tb_gring_elems<4, kWavesPerGroup, STEP>() : 1];
-    const int wave = threadIdx.x >> 6;
+    // the wavefront index is wave-uniform: the work item and its job load as scalars
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const WorkItem w = work[xcd_logical_tile(blockIdx.x, gridDim.x) * kWavesPerGroup + wave];
     if (w.job < 0) return;
     const BatchJob& J = jobs[w.job];

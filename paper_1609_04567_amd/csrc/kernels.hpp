@@ -68,6 +68,16 @@ bool life_rows_ok(const LifeArgs& a);
 SweepGeom life_geom(const LifeArgs& a, int tile_rows);
 hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
                        const LoopCtl& c, int j, hipStream_t s);
+// Temporally blocked Life (life_tb.hip): g.tb generations per launch, the count of
+// each checked generation in its own slice of partials (g.mc). Rows must be
+// 16-byte aligned multiples of 16 cells, unpadded (life_tb_ok).
+bool life_tb_ok(const LifeArgs& a);
+// Generations per launch for a job: `requested` (0 = automatic, 1 = unfused, or
+// a compiled depth), 1 when the rows do not qualify.
+int life_tb_choose(const LifeArgs& a, int requested);
+SweepGeom life_tb_geom(const LifeArgs& a, int depth, int tile_rows);
+hipError_t launch_life_tb(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                          const LoopCtl& c, int j, hipStream_t s);
 // Live-cell count of a u8 grid into partials (one per block), normalising bytes
 // above 1 to 1 in place; returns the partial count.
 hipError_t launch_count_u8(uint8_t* a, int64_t rows, int64_t cols, int64_t pitch,

@@ -53,6 +53,7 @@ SweepGeom life_geom(const LifeArgs& a, int tile_rows) {
 
 hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
                        const LoopCtl& c, int j, hipStream_t s) {
+    if (g.tb > 1) return launch_life_tb(a, g, st, partials, c, j, s);
     if (!life_rows_ok(a)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((life_swar_kernel<kWaves, kUnroll, true>), dim3(g.blocks), dim3(kWaves * 64),
                        0, s, a.a, a.b, a.rows, a.cols, a.pitch, a.torus, st,

@@ -144,6 +144,19 @@ lsr::JacobiArgs lsr_rt::jacobi_args(const Job* j, const void* src, void* dst) {
     return a;
 }
 
+lsr::LifeArgs lsr_rt::life_args(const Job* j, const void* src, void* dst) {
+    const lsr_grid& g = j->xgrid;
+    lsr::LifeArgs a;
+    a.a = static_cast<const uint8_t*>(src);
+    a.b = static_cast<uint8_t*>(dst);
+    a.rows = g.rows;
+    a.cols = g.cols;
+    a.pitch = g.pitch;
+    a.torus = g.bc == LSR_BC_TORUS;
+    a.padded = j->staged;
+    return a;
+}
+
 lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     // one launch advances tb sweeps (off .. off + tb - 1 of the chunk)
     const int tb = j->geom.tb;
@@ -158,18 +171,9 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
             e = lsr::launch_jacobi(jacobi_args(j, src, dst), j->geom, j->st, j->partials, j->ctl,
                                    off, s);
             break;
-        case LSR_ST_LIFE: {
-            lsr::LifeArgs a;
-            a.a = static_cast<const uint8_t*>(src);
-            a.b = static_cast<uint8_t*>(dst);
-            a.rows = g.rows;
-            a.cols = g.cols;
-            a.pitch = g.pitch;
-            a.torus = g.bc == LSR_BC_TORUS;
-            a.padded = j->staged;
-            e = lsr::launch_life(a, j->geom, j->st, j->partials, j->ctl, off, s);
+        case LSR_ST_LIFE:
+            e = lsr::launch_life(life_args(j, src, dst), j->geom, j->st, j->partials, j->ctl, off, s);
             break;
-        }
         case LSR_ST_RESTORE: {
             lsr::RestoreArgs a;
             a.a = src;
@@ -219,8 +223,15 @@ lsr_status lsr_ctx::finish_fused(Job* j, const lsr::JobState& fin, int K, const 
     rc.max_iter = fin.n;
     rc.check_every = 0x7fffffff;                // only sweep n is a "check" (its partials are unused)
     for (int k = 0; k < m; ++k) {
-        HIP_TRY(lsr::launch_jacobi(jacobi_args(j, j->buf[(L + k) & 1], j->buf[(L + k + 1) & 1]),
-                                   j->replay_geom, j->st, j->partials, rc, k, stream));
+        void* src = j->buf[(L + k) & 1];
+        void* dst = j->buf[(L + k + 1) & 1];
+        if (j->stencil == LSR_ST_LIFE) {
+            lsr::LifeArgs a = life_args(j, src, dst);
+            HIP_TRY(lsr::launch_life(a, j->replay_geom, j->st, j->partials, rc, k, stream));
+        } else {
+            HIP_TRY(lsr::launch_jacobi(jacobi_args(j, src, dst), j->replay_geom, j->st, j->partials,
+                                       rc, k, stream));
+        }
     }
     *last = (int)((L + m) & 1);
     return LSR_OK;
@@ -570,7 +581,11 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
             a.pitch = j->xgrid.pitch;
             a.torus = grid->bc == LSR_BC_TORUS;
             a.padded = j->staged;
-            j->geom = lsr::life_geom(a, tun.tile_rows);
+            const int depth = lsr::life_tb_choose(a, tun.tb_depth);
+            j->geom = depth > 1 ? lsr::life_tb_geom(a, depth, tun.tile_rows)
+                                : lsr::life_geom(a, tun.tile_rows);
+            // single generations that replay a stop inside a fused launch
+            j->replay_geom = lsr::life_geom(a, 0);
             break;
         }
         default: {

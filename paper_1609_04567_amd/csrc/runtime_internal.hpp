@@ -230,6 +230,8 @@ lsr_status validate(const lsr_grid* g, int stencil, int reduce, const lsr_cond* 
 
 // Kernel arguments of a Jacobi job's sweep from src to dst (its exec grid).
 lsr::JacobiArgs jacobi_args(const Job* j, const void* src, void* dst);
+// The same for a Life job.
+lsr::LifeArgs life_args(const Job* j, const void* src, void* dst);
 
 // Key of the autotuner's table: a job's stencil, dtype, size class (bit lengths
 // of rows and cols) and check period. A choice is a pure function of this key.

@@ -362,3 +362,157 @@ def test_tb_stores_stay_in_interior_at_full_size(rows, cols, vec, k):
     live = olo < ohi
     # consecutive output ranges abut: no column is skipped or written twice
     assert (olo[live][1:] == ohi[live][:-1]).all() and ohi[live][-1] == cols - 1
+
+
+# ---------------------------------------------------------------------------
+# Temporally blocked Life kernel (life_tb_kernel): a launch advances K
+# generations. Wavefront tile wt = t * NW + w covers band wt // strips and the
+# 992-column window strip = wt % strips; lane l loads the 16 cells at column
+# strip * 992 - 16 + 16 l (wrapped on a torus, zero outside a dead border) and
+# lanes 1..62 store and count. Rows r0 - K .. r1 + K - 1 stream through K levels.
+# The model replays that schedule word by word on the CPU (DPP lane shifts give
+# zero at lanes 0 and 63) and checks every load and store address, that the
+# stores cover the grid exactly once, and that the result and the per-level
+# counts equal the oracle's K generations.
+# ---------------------------------------------------------------------------
+LIFE_TB_WIN = 992
+
+
+def _c_rem(x, m):
+    """C's % (truncating toward zero) followed by the kernel's wrap into [0, m)."""
+    r = np.fmod(x, m)
+    return np.where(r < 0, r + m, r)
+
+
+def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=None):
+    lead = k if lead is None else lead   # rows streamed before and after the band
+    words = buf.view(np.uint32)
+    out = np.zeros_like(buf)
+    writes = np.zeros((rows, cols), np.int32)
+    bad = []
+    strips = -(-cols // LIFE_TB_WIN)
+    bands = -(-rows // tile_rows)
+    wave_tiles = strips * bands
+    tiles = -(-wave_tiles // nw)
+    counts = [0] * k
+    lanes = np.arange(64)
+    zero = np.zeros((64, 4), np.uint32)
+    for t in range(tiles):
+        for w in range(nw):
+            wt = t * nw + w
+            if wt >= wave_tiles:
+                continue
+            band, strip = divmod(wt, strips)
+            col_raw = strip * LIFE_TB_WIN - 16 + lanes * 16
+            in_cols = (col_raw >= 0) & (col_raw < cols)
+            col = np.where(torus & ~in_cols, _c_rem(col_raw, cols), col_raw)
+            loads = in_cols | bool(torus)
+            own = (lanes >= 1) & (lanes <= 62) & (col_raw < cols)
+            live = np.where(loads, np.uint32(0xFFFFFFFF), np.uint32(0))[:, None]
+            r0, r1 = band * tile_rows, min(band * tile_rows + tile_rows, rows)
+
+            def load(r):
+                if r < 0 or r >= rows:
+                    if not torus:
+                        return zero.copy()
+                    r = int(_c_rem(r, rows))
+                W = np.zeros((64, 4), np.uint32)
+                for ln in np.nonzero(loads)[0]:
+                    c = int(col[ln])
+                    if not (0 <= r < rows and 0 <= c and c + 16 <= cols and c % 16 == 0):
+                        bad.append(("load", t, w, ln, r, c))
+                        continue
+                    W[ln] = words[r, c // 4:c // 4 + 4]
+                return W
+
+            up = [zero.copy() for _ in range(k)]
+            mid = [zero.copy() for _ in range(k)]
+            for i in range(r0 - lead, r1 + lead):
+                cur = load(i)
+                for lv in range(1, k + 1):
+                    row = i - lv
+                    V = (up[lv - 1] + mid[lv - 1] + cur).astype(np.uint32)
+                    wv = np.concatenate([[0], V[:-1, 3]]).astype(np.uint32) >> np.uint32(24)
+                    ev = np.concatenate([V[1:, 0], [0]]).astype(np.uint32) & np.uint32(0xFF)
+                    o = np.zeros((64, 4), np.uint32)
+                    for m in range(4):
+                        prev = (V[:, m - 1] >> np.uint32(24)) if m > 0 else wv
+                        nxt = (V[:, m + 1] & np.uint32(0xFF)) if m < 3 else ev
+                        T = (((V[:, m] << np.uint32(8)) | prev) + V[:, m]
+                             + ((V[:, m] >> np.uint32(8)) | (nxt << np.uint32(24)))).astype(np.uint32)
+                        c = mid[lv - 1][:, m]
+                        o[:, m] = _zero_bytes_hi(((T - c) | c) ^ np.uint32(0x03030303)) >> np.uint32(7)
+                    in_rows = 0 <= row < rows
+                    o &= live if (torus or in_rows) else np.uint32(0)
+                    if (check_mask >> (lv - 1)) & 1 and r0 <= row < r1:
+                        counts[lv - 1] += int(np.unpackbits(o[own].view(np.uint8)).sum())
+                    up[lv - 1] = mid[lv - 1]
+                    mid[lv - 1] = cur
+                    cur = o
+                row = i - k
+                if r0 <= row < r1:
+                    for ln in np.nonzero(own)[0]:
+                        c = int(col_raw[ln])
+                        if not (0 <= c and c + 16 <= cols):
+                            bad.append(("store", t, w, ln, row, c))
+                            continue
+                        out[row, c:c + 16] = cur[ln].view(np.uint8)
+                        writes[row, c:c + 16] += 1
+    return out, counts, writes, bad
+
+
+@pytest.mark.parametrize("rows,cols,k,tile_rows", [
+    (1, 16, 2, 64), (2, 32, 3, 8), (3, 48, 4, 4), (9, 64, 8, 4), (40, 1008, 4, 16),
+    (37, 2000, 3, 8), (20, 992, 6, 64), (13, 1024, 2, 5)])
+@pytest.mark.parametrize("torus", [True, False])
+def test_life_tb_model_matches_oracle(rows, cols, k, tile_rows, torus):
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    a = I.life_input(rows, cols, seed=rows * 7 + cols + k)
+    out, counts, writes, bad = _life_tb_launch(a.copy(), rows, cols, torus, k, tile_rows, 4,
+                                               (1 << k) - 1)
+    assert bad == []
+    assert (writes == 1).all()
+    bc = O.BC_TORUS if torus else O.BC_BOTTOM
+    o, _ = O.life_run(a, bc=bc, cond=O.COND_NEVER, max_iter=k)
+    assert np.array_equal(out, o)
+    for lv in range(1, k + 1):
+        _, ro = O.life_run(a, bc=bc, cond=O.COND_NEVER, max_iter=lv)
+        assert counts[lv - 1] == ro.count, lv
+
+
+def test_life_tb_model_catches_a_short_halo():
+    """A mistake planted in the model (one row less streamed before and after each
+    band) must fail the comparison with the oracle, so the check is not vacuous."""
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    rows, cols, k = 24, 48, 3
+    a = I.life_input(rows, cols, seed=5)
+    o, _ = O.life_run(a, bc=O.BC_TORUS, cond=O.COND_NEVER, max_iter=k)
+    good, _, _, _ = _life_tb_launch(a.copy(), rows, cols, True, k, 8, 4, 0)
+    assert np.array_equal(good, o)
+    short, _, writes, _ = _life_tb_launch(a.copy(), rows, cols, True, k, 8, 4, 0, lead=k - 1)
+    assert not np.array_equal(short, o)
+
+
+@pytest.mark.parametrize("rows,cols,tile_rows", [(16384, 16384, 64), (4096, 4096, 64),
+                                                 (1000, 160, 64), (8192, 992 * 3, 32)])
+def test_life_tb_stores_tile_the_grid_at_full_size(rows, cols, tile_rows):
+    """Owned windows x bands cover every cell exactly once; loaded columns stay in
+    [0, cols - 16] after the wrap."""
+    strips = -(-cols // LIFE_TB_WIN)
+    bands = -(-rows // tile_rows)
+    cover = np.zeros(cols, np.int32)
+    lanes = np.arange(64)
+    for strip in range(strips):
+        col_raw = strip * LIFE_TB_WIN - 16 + lanes * 16
+        own = (lanes >= 1) & (lanes <= 62) & (col_raw < cols)
+        for c in col_raw[own]:
+            cover[c:c + 16] += 1
+        col = np.where((col_raw < 0) | (col_raw >= cols), _c_rem(col_raw, cols), col_raw)
+        assert (col >= 0).all() and (col + 16 <= cols).all()
+    assert (cover == 1).all()
+    row_cover = np.zeros(rows, np.int32)
+    for band in range(bands):
+        row_cover[band * tile_rows:min(rows, band * tile_rows + tile_rows)] += 1
+    assert (row_cover == 1).all()
