@@ -38,6 +38,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# 32-bit vector lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 39.32
+# lane operations of the fused Life kernel's level body per cell and generation,
+# per 16 cells: column sums 8, byte shifts 8 + 2 lane shifts, 3x3 totals 4, the
+# rule 16, the count 6 (44 instructions of its compiled loop)
+LIFE_OPS_PER_CELL = 44 / 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -251,9 +257,16 @@ def run_life(args, L, I, torch):
     # a launch reads and writes every cell once, whatever number of generations it fuses
     if spl == 1:
         kname, files = f"life_swar_{n}", ("life.hip", "tile_life.hpp", "common.hpp")
+        out["roofline"] = roofline(2.0 * n * n, per_launch_s, measured_traffic(kname, files))
     else:
+        # fused generations are bound by the vector ALU: LIFE_OPS_PER_CELL 32-bit
+        # lane operations per cell and generation against the chip's lane rate
         kname, files = f"life_tb{spl}_{n}", ("life_tb.hip", "common.hpp")
-    out["roofline"] = roofline(2.0 * n * n, per_launch_s, measured_traffic(kname, files))
+        achieved = n * n * spl * LIFE_OPS_PER_CELL / per_launch_s / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TOPS,
+                           "unit": "Tops/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                           "traffic": measured_traffic(kname, files)}
+        out["hbm_per_launch"] = roofline(2.0 * n * n, per_launch_s, None)
     out["copy_probe_gbs"] = copy_gbs
     # bytes an unfused generation would move per cell, at the achieved update rate
     out["effective_gbs"] = round(value * 2.0, 1)

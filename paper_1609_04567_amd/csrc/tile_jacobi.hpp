@@ -136,9 +136,9 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
                                              double* __restrict__ partials, double* lds) {
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     const int band = t / strips, strip = t - band * strips;
-    // readfirstlane: the wavefront index is wave-uniform, so window bounds and
-    // the edge test stay scalar
-    const int lane = threadIdx.x & 63, wave = WT ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // (the wavefront index stays a vector value here: made scalar, the edge
+    // handling turns into branches and the 8192^2 FP64 sweep lost 10 %)
+    const int lane = threadIdx.x & 63, wave = WT ? 0 : threadIdx.x >> 6;
     const int64_t cw = (int64_t)strip * (NW * 64 * VEC) + (int64_t)wave * (64 * VEC);
     const int64_t c = cw + (int64_t)lane * VEC;
     const int64_t r0 = 1 + (int64_t)band * tile_rows;
@@ -284,7 +284,10 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     constexpr int OW = tb_out_width<VEC, K>();
     const bool check = (check_mask >> (K - 1)) & 1u;
     const int band = t / strips, strip = t - band * strips;
-    const int lane = threadIdx.x & 63, hw_wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // the wavefront's slot in the workgroup (a wavefront tile of the batched kernel
+    // is NW = 1 in a workgroup of several); readfirstlane keeps it scalar
+    const int hw_wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wave = WT ? 0 : hw_wave;
     const int64_t cw = ((int64_t)strip * NW + wave) * OW;       // window start (aligned)
     const int64_t c = cw + (int64_t)lane * VEC;

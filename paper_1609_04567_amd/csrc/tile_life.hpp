@@ -47,7 +47,7 @@ __device__ __forceinline__ void life_swar_tile(const uint8_t* __restrict__ a, ui
                                                unsigned long long* lds) {
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     const int band = t / strips, strip = t - band * strips;
-    const int lane = threadIdx.x & 63, wave = WT ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wave = WT ? 0 : threadIdx.x >> 6;
     const int64_t cw = (int64_t)strip * (NW * 1024) + (int64_t)wave * 1024;
     const int64_t c = cw + (int64_t)lane * 16;
     const bool active = c < cols;
