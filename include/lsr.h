@@ -71,7 +71,9 @@ typedef enum {
 typedef enum {
     LSR_ST_LAPLACE5 = 1,    /* b = 0.25*((N+S)+(W+E)) on interior cells (Helmholtz with alpha=0, f=0) */
     LSR_ST_HELMHOLTZ5 = 2,  /* b = (((N+S)+(W+E)) + g) * rd, rd = 1/(4 + alpha*h*h), g = h^2 f in env0
-                               (the Jacobi solver of Sect. 4.1); param[0] = alpha, param[1] = h */
+                               (the Jacobi solver of Sect. 4.1); param[0] = alpha, param[1] = h.
+                               F32 storage needs alpha*h*h in [-4/3, 4] (EINVAL otherwise): its
+                               stochastically rounded update relies on |0.25 - rd| <= 1/8 */
     LSR_ST_LIFE = 3,        /* B3/S23 on u8 cells (Fig. 1); non-zero bytes are alive; output is 0/1 */
     LSR_ST_RESTORE = 4      /* flagged pixels (env0 = u8 mask) take argmin_t sum phi(t - u_m) over
                                their in-range 8-neighbourhood (phase 2 of Sect. 4.3);

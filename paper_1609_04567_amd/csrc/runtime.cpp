@@ -56,6 +56,11 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
             if (stencil == LSR_ST_HELMHOLTZ5) {
                 const double rd = 1.0 / (4.0 + g->param[0] * (g->param[1] * g->param[1]));
                 if (!std::isfinite(rd)) return fail(LSR_EINVAL, "1/(4 + alpha h^2) is not finite");
+                // the FP32 update rounds 0.25 t + (0.25 e - (0.25 - rd) t) with an add
+                // that needs |0.25 - rd| <= 1/8
+                if (g->dtype == LSR_F32 && !(rd >= 0.125 && rd <= 0.375))
+                    return fail(LSR_EINVAL, "FP32 Helmholtz needs 1/(4 + alpha h^2) in [1/8, 3/8] "
+                                            "(alpha h^2 in [-4/3, 4])");
             }
             if (reduce != LSR_RED_MAX_ABS_DELTA && reduce != LSR_RED_L2_DELTA && reduce != LSR_RED_MEAN_ABS_DELTA)
                 return fail(LSR_EINVAL, "Jacobi reduces are MAX_ABS_DELTA, L2_DELTA, MEAN_ABS_DELTA");

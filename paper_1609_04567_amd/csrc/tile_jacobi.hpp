@@ -85,14 +85,15 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// fl(p + c) rounded stochastically by the exact remainder (TwoSum): one ulp
-// towards p + c with probability |remainder| / ulp, using 24 bits of `bits`.
-__device__ __forceinline__ float add_round_stochastic(float p, float c, uint32_t bits) {
+// fl(p + c) rounded stochastically by its exact remainder: one ulp towards
+// p + c with probability |remainder| / ulp, resolved to 1/256 ulp by the byte
+// `bits8` (u = (bits8 + 1/2) / 256). Needs |c| <= |p|, where Fast2Sum's
+// remainder c - (fl(p + c) - p) is exact (Dekker, 1971).
+__device__ __forceinline__ float add_round_stochastic(float p, float c, uint32_t bits8) {
     const float hi = p + c;
-    const float bb = hi - p;
-    const float rem = (p - (hi - bb)) + (c - bb);
+    const float rem = c - (hi - p);
     const float ulp = __uint_as_float(__float_as_uint(hi) & 0x7f800000u) * 1.1920928955078125e-7f;
-    const float u = (float)(bits >> 8) * 5.9604644775390625e-8f;  // [0, 1)
+    const float u = ((float)bits8 + 0.5f) * 3.90625e-3f;
     return (fabsf(rem) > u * ulp) ? hi + copysignf(ulp, rem) : hi;
 }
 
@@ -107,9 +108,15 @@ __device__ __forceinline__ T jacobi_update(T N, T S, T W, T E, T gv, T rd, T rd_
         const T sn = (N + S) + (W + E);
         const T tt = sn + gv, bb = tt - sn;
         const T te = (sn - (tt - bb)) + (gv - bb);  // exact: sn + gv = tt + te
-        const uint32_t key = (uint32_t)row * 0x9e3779b1u ^ (uint32_t)col * 0x85ebca77u ^
+        // one hash per (row, group of four columns, sweep), one byte of it per
+        // column: a lane's four cells share the hash (the integer multiplies are
+        // quarter-rate instructions)
+        const uint32_t key = (uint32_t)row * 0x9e3779b1u ^ (uint32_t)(col >> 2) * 0x85ebca77u ^
                              sweep * 0xc2b2ae3du;
-        return add_round_stochastic(T(0.25) * tt, T(0.25) * te - rd_lo * tt, hash32(key));
+        const uint32_t bits8 = (hash32(key) >> (8 * (uint32_t)(col & 3))) & 0xFFu;
+        // |rd_lo| <= 1/8 (checked at submission) keeps |0.25 te - rd_lo tt| below
+        // |0.25 tt|, as the rounding add requires
+        return add_round_stochastic(T(0.25) * tt, T(0.25) * te - rd_lo * tt, bits8);
     } else {
         return T(0.25) * ((N + S) + (W + E));
     }

@@ -65,6 +65,12 @@ VALID = [
     (_g(), L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA, _c()),
     (_g(dtype=L.LSR_F32), L.LSR_ST_LAPLACE5, L.LSR_RED_L2_DELTA, _c(L.LSR_COND_NEVER)),
     (_g(env0=FAKE), L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, _c(every=10)),
+    (_g(dtype=L.LSR_F32, env0=FAKE), L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, _c(every=10)),
+    # alpha h^2 = 4 and -4/3: the ends of the FP32 form's range; FP64 takes any finite 1/(4 + alpha h^2)
+    (_g(dtype=L.LSR_F32, env0=FAKE, param=(4.0, 1.0)), L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, _c()),
+    (_g(dtype=L.LSR_F32, env0=FAKE, param=(-4.0 / 3.0, 1.0)), L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+     _c()),
+    (_g(env0=FAKE, param=(100.0, 1.0)), L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, _c()),
     (_g(dtype=L.LSR_U8, bc=L.LSR_BC_TORUS), L.LSR_ST_LIFE, L.LSR_RED_SUM, _c(L.LSR_COND_STABLE_FOR)),
     (_g(1, 1, dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_LIFE, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER)),
     (_g(dtype=L.LSR_F32, bc=L.LSR_BC_BOTTOM, env0=FAKE, param=(100.0,)), L.LSR_ST_RESTORE,
@@ -86,6 +92,10 @@ INVALID = [
     ("u8 jacobi", _g(dtype=L.LSR_U8), L.LSR_ST_LAPLACE5, 1, _c(), 10),
     ("torus jacobi", _g(bc=L.LSR_BC_TORUS), L.LSR_ST_LAPLACE5, 1, _c(), 10),
     ("helmholtz no env", _g(), L.LSR_ST_HELMHOLTZ5, 2, _c(), 10),
+    ("f32 helmholtz alpha h^2 > 4", _g(dtype=L.LSR_F32, env0=FAKE, param=(4.5, 1.0)),
+     L.LSR_ST_HELMHOLTZ5, 2, _c(), 10),
+    ("f32 helmholtz alpha h^2 < -4/3", _g(dtype=L.LSR_F32, env0=FAKE, param=(-1.5, 1.0)),
+     L.LSR_ST_HELMHOLTZ5, 2, _c(), 10),
     ("laplace with env", _g(env0=FAKE), L.LSR_ST_LAPLACE5, 1, _c(), 10),
     ("jacobi sum reduce", _g(), L.LSR_ST_LAPLACE5, L.LSR_RED_SUM, _c(), 10),
     ("jacobi stable cond", _g(), L.LSR_ST_LAPLACE5, 1, _c(L.LSR_COND_STABLE_FOR), 10),
