@@ -164,7 +164,9 @@ typedef struct {
                                also rows of a multiple of 16 cells), else the job runs
                                unfused. Fields and counts are bit for bit those of unfused
                                sweeps; a float reduce value differs at most in the order of
-                               its partial sums. Restoration is never fused. */
+                               its partial sums. Restoration is never fused. A batched context
+                               takes the depth (FP64 10, 5 or 2; FP32 5 or 2) and tile_rows
+                               from the same overrides or tuning table. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
     int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */

@@ -280,7 +280,7 @@ void launch_kind(const BatchJob* jobs, const WorkItem* work, int groups, hipStre
 
 }  // namespace
 
-void batch_geometry(BatchJob& j, int is_life, int f32) {
+void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_tile_rows) {
     j.step = 1;
     j.mc = 0;
     if (batch_small_fits(j.rows, j.cols, is_life ? 1 : f32 ? 4 : 8)) {
@@ -301,8 +301,12 @@ void batch_geometry(BatchJob& j, int is_life, int f32) {
     // rows are 16-byte aligned (the engine stages any other grid)
     const int vec = f32 ? 4 : 2;
     int depth = 0;
-    for (int k : f32 ? std::initializer_list<int>{5, 2} : std::initializer_list<int>{10, 5, 2})
-        if (j.ctl.check_every % k == 0 && j.ctl.max_iter % k == 0) { depth = k; break; }
+    const auto depths = f32 ? std::initializer_list<int>{5, 2} : std::initializer_list<int>{10, 5, 2};
+    for (int k : depths)   // a requested depth the families hold, if it divides both
+        if (k == want_depth && j.ctl.check_every % k == 0 && j.ctl.max_iter % k == 0) depth = k;
+    if (depth == 0 && want_depth != 5)
+        for (int k : depths)
+            if (j.ctl.check_every % k == 0 && j.ctl.max_iter % k == 0) { depth = k; break; }
     if (depth == 0) {
         depth = 5;
         j.mc = 1;
@@ -312,7 +316,7 @@ void batch_geometry(BatchJob& j, int is_life, int f32) {
                      : (depth == 10 ? BK_JAC_F64_TB10 : depth == 5 ? BK_JAC_F64_TB5 : BK_JAC_F64_TB2);
     }
     j.step = depth;
-    j.tile_rows = depth >= 8 ? 48 : 32;
+    j.tile_rows = want_tile_rows > 0 ? want_tile_rows : depth >= 8 ? 48 : 32;
     const int64_t ow = (64 * vec - 2 * depth) / vec * vec;
     const int64_t need = j.cols - 1 - depth;
     j.strips = (int)(need > 0 ? (need + ow - 1) / ow : 1);

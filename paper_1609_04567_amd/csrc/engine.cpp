@@ -97,8 +97,15 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     c.stable_window = j->cond.stable_window;
     c.threshold = j->cond.threshold;
     c.mean_div = (double)g.rows * (double)g.cols;
-    // rows are aligned (or staged into aligned copies, 256-byte aligned pool blocks)
-    lsr::batch_geometry(d, life, f32);
+    // rows are aligned (or staged into aligned copies, 256-byte aligned pool blocks);
+    // fused depth and band height from the tuning table or overrides, as on the
+    // plain path
+    lsr_tuning tu;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        tu = tuned_for(g, j->stencil, j->cond.check_every);
+    }
+    lsr::batch_geometry(d, life, f32, tu.tb_depth, tu.tile_rows);
     c.nparts = d.tiles;
     const size_t esz = dtype_size(g.dtype);
     j->bytes = (size_t)g.rows * (size_t)j->xgrid.pitch * esz;

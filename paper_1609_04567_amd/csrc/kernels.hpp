@@ -151,9 +151,13 @@ struct WorkItem {
 // Family, step and tile geometry a job gets inside a batch: a function of its
 // shape, dtype and loop control only (j.ctl must be set), so its reduce order is
 // the same alone and in any mix. Small grids (batch_small_fits) run their whole
-// loop in LDS in one round; other Jacobi jobs take the deepest fused depth that
-// divides both the check period and the cap, else depth 5 with checks inside.
-void batch_geometry(BatchJob& j, int is_life, int f32);
+// loop in LDS in one round; other Jacobi jobs take want_depth when a family holds
+// it (FP64 10, 5, 2; FP32 5, 2) and it divides both the check period and the
+// cap, else the deepest such depth, else depth 5 with checks inside (also
+// chosen by want_depth = 5); want_tile_rows > 0 sets the band height. The
+// wanted values come from the context's tuning table, so the geometry is still
+// a function of the job's own key.
+void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth = 0, int want_tile_rows = 0);
 // One launch per kernel family: `work` points at that family's segment of the
 // work list (nwork_padded entries, a multiple of 32; idle entries have job -1).
 // A workgroup runs four consecutive entries, one per wavefront.

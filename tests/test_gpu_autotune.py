@@ -74,3 +74,38 @@ def test_batched_context_is_rejected():
             c.autotune(L.LSR_ST_LAPLACE5, L.LSR_F64, 64, 64, 1)
     finally:
         c.close()
+
+
+def test_batched_jobs_take_the_table_entry():
+    """A batched context reads the same tuning table: an imported entry for a job's
+    key sets its fused depth and band height inside the rounds, and the field is
+    bit-identical to the one the default geometry gives (every level evaluates the
+    same update with the same rounding keys)."""
+    import torch
+    say("batched job with an imported tuning entry")
+    h = I.helmholtz_input(300)
+    out = {}
+    for tuned in (False, True):
+        c = L.Context(0, batched=True)
+        try:
+            if tuned:
+                table = json.loads(L.lsr_tune_export(c.handle))
+                table["entries"] = [{"stencil": L.LSR_ST_HELMHOLTZ5, "dtype": L.LSR_F32,
+                                     "rows_log2": 9, "cols_log2": 9, "check_every": 10,
+                                     "tile_rows": 16, "tb_depth": 2, "waves": 0, "unroll": 0,
+                                     "us_per_sweep": 1.0}]
+                L.lsr_tune_import(c.handle, json.dumps(table))
+            t = torch.from_numpy(h.u0.astype(np.float32)).to("cuda:0")
+            g = torch.from_numpy(h.g.astype(np.float32)).to("cuda:0")
+            r = c.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                      L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 160, L.LSR_BC_RING, env0=g,
+                      param=(h.alpha, h.h))
+            torch.cuda.synchronize()
+            out[tuned] = (t.cpu().numpy(), r)
+        finally:
+            c.close()
+    (x0, r0), (x1, r1) = out[False], out[True]
+    assert r0.sweeps_per_launch == 5 and r1.sweeps_per_launch == 2
+    assert r0.iterations == r1.iterations == 160
+    assert np.array_equal(x0, x1)
+    assert abs(r1.last_reduce - r0.last_reduce) <= 1e-12 * abs(r0.last_reduce)
