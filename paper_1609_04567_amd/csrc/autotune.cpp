@@ -47,7 +47,7 @@ std::vector<lsr_tuning> candidates(int stencil) {
         for (int tr : {8, 16, 32}) add(tr, 1, s[0], s[1]);
     for (int depth : {2, 4, 5, 8, 10})
         for (int waves : {1, 2, 4})
-            for (int tr : {0, 4, 8, 16, 32, 48, 64}) add(tr, depth, waves, 0);
+            for (int tr : {0, 4, 8, 16, 32, 40, 48, 64}) add(tr, depth, waves, 0);
     return out;
 }
 

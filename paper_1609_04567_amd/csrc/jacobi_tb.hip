@@ -15,8 +15,11 @@
 namespace lsr {
 namespace {
 
+// FP64: at least three wavefronts per SIMD (168 VGPRs). At depth 10 the register
+// pipeline needs about 174, and the compiler fits it in 168 with a few values
+// spilled, which the third wavefront repays (8192^2 Helmholtz +10 %).
 template <typename T, bool HELM, int VEC, int NW, int K, bool MC>
-__global__ __launch_bounds__(NW * 64) void jacobi5_tb_kernel(
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
     double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles, int tile_rows) {
@@ -130,7 +133,7 @@ void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int w
     // small grids want more, shorter bands: a band is a serial stream of rows
     // through K levels, so a launch lasts as long as its tallest band (256^2
     // Laplace, checks every sweep: 2-row bands 11.5 ms per job, 32-row 30.4 ms)
-    g.tile_rows = tile_rows > 0 ? tile_rows : (depth >= 8 ? 48 : 32);
+    g.tile_rows = tile_rows > 0 ? tile_rows : (depth >= 8 ? 40 : 32);
     // windows of 64 * vec columns step by ow (a multiple of vec) and output the
     // ow columns after their first `depth`; the first window outputs from column 1
     const int64_t ow = (64 * g.vec - 2 * depth) / g.vec * g.vec;

@@ -454,13 +454,11 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
         slot = (slot + 1 == K) ? 0 : slot + 1;
     };
 
-    // rows come in groups of three. FP64: the next group's loads are issued
-    // before the current group is computed (two register buffers, alternating),
-    // so a wavefront always has a group of loads in flight while it computes
-    // (8192^2 Helmholtz, 10 levels: +2 %). FP32's update is ALU-bound and loses
-    // occupancy to the second buffer (-4 %), so it loads each group just before
-    // computing it.
-    auto stream_plain = [&](auto fast_tag) {
+    // rows come in groups of three, each group's loads issued just before it is
+    // computed. (Keeping the next group's loads in flight in a second register
+    // buffer cost 24 VGPRs, and with them the third wavefront per SIMD at depth
+    // 10: 8192^2 FP64 Helmholtz 1190 -> 1320 GLUP/s without it.)
+    auto stream = [&](auto fast_tag) {
         for (int64_t i0 = i_beg; i0 < i_end; i0 += 3) {
             T in[3][VEC], gin[3][VEC];
 #pragma unroll
@@ -472,33 +470,6 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
             step(fast_tag, std::integral_constant<int, 1>{}, i0 + 1, in[1], gin[1]);
             step(fast_tag, std::integral_constant<int, 2>{}, i0 + 2, in[2], gin[2]);
         }
-    };
-    auto stream_prefetch = [&](auto fast_tag) {
-        T inA[3][VEC], ginA[3][VEC], inB[3][VEC], ginB[3][VEC];
-        auto fetch = [&](int64_t i0, T (&in)[3][VEC], T (&gin)[3][VEC]) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                load(fast_tag, a, i0 + q, in[q], false);
-                if (HELM) load(fast_tag, g, i0 + q - 1, gin[q], NTG);
-            }
-        };
-        auto run3 = [&](int64_t i0, const T (&in)[3][VEC], const T (&gin)[3][VEC]) {
-            step(fast_tag, std::integral_constant<int, 0>{}, i0, in[0], gin[0]);
-            step(fast_tag, std::integral_constant<int, 1>{}, i0 + 1, in[1], gin[1]);
-            step(fast_tag, std::integral_constant<int, 2>{}, i0 + 2, in[2], gin[2]);
-        };
-        fetch(i_beg, inA, ginA);
-        for (int64_t i0 = i_beg; i0 < i_end; i0 += 6) {
-            if (i0 + 3 < i_end) fetch(i0 + 3, inB, ginB);
-            run3(i0, inA, ginA);
-            if (i0 + 3 >= i_end) break;
-            if (i0 + 6 < i_end) fetch(i0 + 6, inA, ginA);
-            run3(i0 + 3, inB, ginB);
-        }
-    };
-    auto stream = [&](auto fast_tag) {
-        if constexpr (sizeof(T) == 8) stream_prefetch(fast_tag);
-        else stream_plain(fast_tag);
     };
     if (fast) stream(std::true_type{});
     else stream(std::false_type{});
