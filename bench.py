@@ -5,19 +5,21 @@ Helmholtz Jacobi solver, 8192 x 8192 FP64 grid including the boundary ring,
 alpha = 1, manufactured solution sin(pi x) sin(pi y); the L2 norm of the update
 is reduced every 10 sweeps, stop below 1e-9 or at 5000 sweeps (it always reaches
 the cap: the closed form gives ||update|| ~ 3.2e-4 there). One step = one whole
-lsr_run job (5000 fused sweep+reduce launches, 500 on-device checks) from a zero
-interior that is already resident in HBM.
+lsr_run job (5000 sweeps with the reduce fused in, 10 per launch at the automatic
+depth, and 500 on-device checks) from a zero interior that is already resident in
+HBM.
 
 value = whole-job GLUP/s (interior cells x sweeps / wall time of the step,
-host API overhead included). roofline: the sweep kernel's algorithmic traffic
-(24 B per cell update: read u, read g, write u') per launch, divided by its mean
-launch time measured with HIP events on the library's own stream (the job's
-device time over its sweep launches, so it also carries the small finalize
-kernels and launch gaps), against 8 TB/s. plain_sweep: the same job run with one
-sweep per launch, outside the timed region, and its own fraction of 8 TB/s.
+host API overhead included). roofline: the fused kernel's compulsory traffic per
+launch (24 B per interior cell: read u and g, write u, once per launch whatever
+the number of sweeps it fuses), divided by its mean launch time measured with HIP
+events on the library's own stream (the job's device time over its launches, so
+it also carries the small finalize kernels and launch gaps), against 8 TB/s.
+plain_sweep: the same job run with one sweep per launch, outside the timed
+region, and its own fraction of 8 TB/s.
 
 Other workloads (--workload): laplace (256^2 FP64, 2000 sweeps), life (16384^2
-u8 torus, 2000 generations), restore (4096^2 two-phase restoration, FP64 and
+u8 torus, 2000 generations, 8 per launch; its roofline is the vector ALU's), restore (4096^2 two-phase restoration, FP64 and
 FP32), served (a prefix of the mixed job stream through the batched engine in
 FP32 storage, against the plain per-grid FP64 path on the same jobs).
 
