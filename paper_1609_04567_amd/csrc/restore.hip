@@ -167,14 +167,32 @@ __global__ __launch_bounds__(256) void restore_kernel(
     if (t >= tiles) return;
     const int band = t / strips, strip = t - band * strips;
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
-    const int64_t jx = (int64_t)strip * 64 + lx;
     const bool is_max = ctl.reduce == RED_MAX_ABS;
-    double acc = 0.0;
+    // Wavefront ly owns rows ly, ly + 4, ... of the band (TR / 4 rows of 64
+    // columns). About 40 % of pixels are flagged, so the wavefront first lists
+    // its flagged pixels (row-in-band << 6 | lane) in LDS and then solves them 64
+    // at a time with every lane busy, instead of running each row's Newton loop
+    // with the unflagged lanes idle.
+    constexpr int kPerWave = TR / 4 * 64;
+    __shared__ uint16_t list[4][kPerWave];
+    int n = 0;
     for (int rr = ly; rr < TR; rr += 4) {
         const int64_t i = (int64_t)band * TR + rr;
-        if (i >= rows || jx >= cols) continue;
+        const int64_t jx = (int64_t)strip * 64 + lx;
+        const bool flagged = i < rows && jx < cols && mask[i * pitch + jx];
+        const uint64_t ballot = __ballot(flagged);
+        const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+        if (flagged) list[ly][pos] = (uint16_t)((rr << 6) | lx);
+        n += __popcll(ballot);
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int e = lx; e < n; e += 64) {
+        const int code = list[ly][e];
+        const int64_t i = (int64_t)band * TR + (code >> 6);
+        const int64_t jx = (int64_t)strip * 64 + (code & 63);
         const int64_t p = i * pitch + jx;
-        if (!mask[p]) continue;
         T v[8];
         unsigned valid = 0;
 #pragma unroll
