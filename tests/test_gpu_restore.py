@@ -119,3 +119,22 @@ def _detect_crop(y, A0, A1, B0, B1, K):
     m, u = O.amf_detect(y[a0:a1, b0:b1], 19)
     return (np.ascontiguousarray(m[A0 - a0:A1 - a0, B0 - b0:B1 - b0]),
             np.ascontiguousarray(u[A0 - a0:A1 - a0, B0 - b0:B1 - b0]))
+
+
+@pytest.mark.parametrize("pattern", ["all", "none", "checker", "rows"])
+@pytest.mark.parametrize("shape", [(33, 70), (100, 129), (16, 64)])
+def test_restore_mask_extremes_match_oracle(ctx, pattern, shape):
+    """Every pixel flagged (a wavefront's list full), none flagged, and patterns
+    whose flagged pixels fall unevenly over the wavefronts of a tile, on shapes
+    with partial bands and partial column strips."""
+    say(f"restore mask {pattern} {shape}")
+    r = I.restore_input(*shape, seed=5, noise=0.4)
+    _, u0 = O.amf_detect(r.y, 19)
+    ii, jj = np.indices(shape)
+    m = {"all": np.ones(shape), "none": np.zeros(shape), "checker": (ii + jj) % 2,
+         "rows": (ii % 5 == 1) | (jj % 7 == 3)}[pattern].astype(np.uint8)
+    o, ro = O.restore_run(u0.astype(np.float64), m, thr=0.1, max_iter=50)
+    x, res = run_restore(ctx, u0, m, thr=0.1, max_iter=50)
+    assert res.status == L.LSR_OK
+    assert res.iterations == ro.n and bool(res.converged) == ro.converged
+    assert rel_err(x, o) <= 1e-12
