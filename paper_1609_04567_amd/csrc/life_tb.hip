@@ -22,6 +22,7 @@
 // normalises them).
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -131,52 +132,64 @@ __global__ __launch_bounds__(NW * 64) void life_tb_kernel(
             }
         };
 
-        uint32_t up[K][4], mid[K][4];   // level l's input rows i - l - 1 and i - l (index l - 1)
+        // R[l][s]: the last three rows of level l (l = 0: the loaded rows of generation
+        // n), in slots by row phase: at step i (phase P = (i - i_beg) mod 3) level l
+        // writes its row into slot P and level l + 1 reads rows i-l-2, i-l-1, i-l
+        // from slots P+1, P+2, P (mod 3). Steps go in groups of three, so slot
+        // numbers are compile-time constants and rows never move between registers.
+        uint32_t R[K][3][4];
 #pragma unroll
         for (int l = 0; l < K; ++l)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) up[l][m] = mid[l][m] = 0;
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) R[l][q][m] = 0;
 
         // the K levels of step i (input row i of generation n), then the store of row i - K
-        auto process_group = [&](int64_t i0, const uint32_t (&w)[U][4]) {
+        auto step = [&](auto phase, int64_t i, const uint32_t (&row_in)[4]) {
+            constexpr int P = decltype(phase)::value, PU = (P + 1) % 3, PM = (P + 2) % 3;
 #pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int64_t i = i0 + k;
-                if (i >= i_end) break;
-                uint32_t in[4] = {w[k][0], w[k][1], w[k][2], w[k][3]};
+            for (int m = 0; m < 4; ++m) R[0][P][m] = row_in[m];
+            uint32_t out[4];
 #pragma unroll
-                for (int l = 1; l <= K; ++l) {
-                    const int64_t row = i - l;   // row of generation n + l computed here
-                    uint32_t V[4], out[4];
+            for (int l = 1; l <= K; ++l) {
+                const int64_t row = i - l;   // row of generation n + l computed here
+                const uint32_t(&src)[3][4] = R[l - 1];
+                uint32_t V[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) V[m] = up[l - 1][m] + mid[l - 1][m] + in[m];
-                    life_rule16(V, mid[l - 1], out);
-                    if (!TORUS) {
-                        const uint32_t lv = (row >= 0 && row < rows) ? live : 0u;
+                for (int m = 0; m < 4; ++m) V[m] = src[PU][m] + src[PM][m] + src[P][m];
+                life_rule16(V, src[PM], out);
+                if (!TORUS) {
+                    const uint32_t lv = (row >= 0 && row < rows) ? live : 0u;
 #pragma unroll
-                        for (int m = 0; m < 4; ++m) out[m] &= lv;
-                    }
-                    if (((mask >> (l - 1)) & 1u) && row >= r0 && row < r1)
-                        cnt[l - 1] += (uint32_t)(__popc(out[0]) + __popc(out[1]) + __popc(out[2]) +
-                                                 __popc(out[3])) & own;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        up[l - 1][m] = mid[l - 1][m];
-                        mid[l - 1][m] = in[m];
-                        in[m] = out[m];
-                    }
+                    for (int m = 0; m < 4; ++m) out[m] &= lv;
                 }
-                const int64_t row = i - K;
-                if (row >= r0 && row < r1 && own) {
-                    typedef uint32_t W4 __attribute__((ext_vector_type(4)));
-                    W4 o;
-                    o[0] = in[0];
-                    o[1] = in[1];
-                    o[2] = in[2];
-                    o[3] = in[3];
-                    __builtin_nontemporal_store(o, reinterpret_cast<W4*>(b + row * pitch + col_raw));
+                if (((mask >> (l - 1)) & 1u) && row >= r0 && row < r1)
+                    cnt[l - 1] += (uint32_t)(__popc(out[0]) + __popc(out[1]) + __popc(out[2]) +
+                                             __popc(out[3])) & own;
+                if (l < K) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) R[l][P][m] = out[m];
                 }
             }
+            const int64_t row = i - K;
+            if (row >= r0 && row < r1 && own) {
+                typedef uint32_t W4 __attribute__((ext_vector_type(4)));
+                W4 o;
+                o[0] = out[0];
+                o[1] = out[1];
+                o[2] = out[2];
+                o[3] = out[3];
+                __builtin_nontemporal_store(o, reinterpret_cast<W4*>(b + row * pitch + col_raw));
+            }
+        };
+        static_assert(U == 3, "a load group is one rotation of the row slots");
+        auto process_group = [&](int64_t i0, const uint32_t (&w)[U][4]) {
+            step(std::integral_constant<int, 0>{}, i0, w[0]);
+            if (i0 + 1 >= i_end) return;
+            step(std::integral_constant<int, 1>{}, i0 + 1, w[1]);
+            if (i0 + 2 >= i_end) return;
+            step(std::integral_constant<int, 2>{}, i0 + 2, w[2]);
         };
 
         uint32_t ga[U][4], gb[U][4];
