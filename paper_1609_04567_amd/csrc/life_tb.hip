@@ -62,8 +62,9 @@ __device__ __forceinline__ void life_rule16(const uint32_t (&V)[4], const uint32
 }
 
 // NW wavefronts per workgroup, each its own window (wave tile wt = t * NW + w,
-// strip-major within a band); K generations; U rows per load group (two groups
-// alternate, so with U a multiple of 3 the level rotation needs no copies).
+// strip-major within a band); K generations; U = 3 rows per load group (one
+// rotation of the row slots; two groups alternate, so the next group's loads are
+// in flight while the current one is computed).
 // check_mask bit l-1: generation n1 + l - 1 is checked; its count over the
 // workgroup's windows goes to partials[(l - 1) * tiles + t].
 template <int NW, int K, int U, bool TORUS>
