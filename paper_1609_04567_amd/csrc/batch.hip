@@ -114,18 +114,21 @@ __device__ void small_jacobi(const BatchJob& J, T* A, T* B, double* red_lds, int
     __syncthreads();
     const T* g = static_cast<const T*>(J.env);
     const T rd = (T)J.rd, rd_lo = (T)(0.25 - J.rd);
-    const int64_t icols = cols - 2, inner = (rows - 2) * icols;
+    // the grid fits in LDS, so cell indices fit in 32 bits (a 64-bit division per
+    // cell cost more than the update)
+    const int cols32 = (int)cols, icols = cols32 - 2, inner = ((int)rows - 2) * icols;
     int64_t n = s.n;
     while (n < J.ctl.max_iter) {
         const int64_t n1 = n + 1;
         const bool check = is_check_sweep(n1, J.ctl);
         double acc = 0.0;
-        for (int64_t k = tid; k < inner; k += kSmallThreads) {
-            const int64_t i = 1 + k / icols, jj = 1 + (k - (i - 1) * icols);
-            const int64_t c = i * cols + jj;
-            const T v = jacobi_update<T, HELM>(A[c - cols], A[c + cols], A[c - 1], A[c + 1],
-                                               HELM ? g[i * J.pitch + jj] : T(0), rd, rd_lo, i, jj,
-                                               (uint32_t)n1);
+        for (int k = tid; k < inner; k += kSmallThreads) {
+            const int q = k / icols;
+            const int i = 1 + q, jj = 1 + (k - q * icols);
+            const int c = i * cols32 + jj;
+            const T v = jacobi_update<T, HELM>(A[c - cols32], A[c + cols32], A[c - 1], A[c + 1],
+                                               HELM ? g[(int64_t)i * J.pitch + jj] : T(0), rd, rd_lo,
+                                               (int64_t)i, (int64_t)jj, (uint32_t)n1);
             if (check) acc = jacobi_accum(J.ctl.reduce, acc, (double)v - (double)A[c]);
             B[c] = v;
         }
@@ -168,22 +171,24 @@ __device__ void small_life(const BatchJob& J, uint8_t* A, uint8_t* B, unsigned l
         const int64_t n1 = n + 1;
         const bool check = is_check_sweep(n1, J.ctl);
         unsigned long long cnt = 0;
-        for (int64_t k = tid; k < cells; k += kSmallThreads) {
-            const int64_t i = k / cols, jj = k - i * cols;
+        // 32-bit cell indices: the grid fits in LDS
+        const int rows32 = (int)rows, cols32 = (int)cols, cells32 = (int)cells;
+        for (int k = tid; k < cells32; k += kSmallThreads) {
+            const int i = k / cols32, jj = k - i * cols32;
             int nb = 0;
 #pragma unroll
             for (int di = -1; di <= 1; ++di)
 #pragma unroll
                 for (int dj = -1; dj <= 1; ++dj) {
                     if (di == 0 && dj == 0) continue;
-                    int64_t r = i + di, c = jj + dj;
+                    int r = i + di, c = jj + dj;
                     if (J.torus) {
-                        r = r < 0 ? r + rows : r >= rows ? r - rows : r;
-                        c = c < 0 ? c + cols : c >= cols ? c - cols : c;
-                    } else if (r < 0 || r >= rows || c < 0 || c >= cols) {
+                        r = r < 0 ? r + rows32 : r >= rows32 ? r - rows32 : r;
+                        c = c < 0 ? c + cols32 : c >= cols32 ? c - cols32 : c;
+                    } else if (r < 0 || r >= rows32 || c < 0 || c >= cols32) {
                         continue;
                     }
-                    nb += A[r * cols + c];
+                    nb += A[r * cols32 + c];
                 }
             const uint8_t v = (nb == 3 || (A[k] && nb == 2)) ? 1 : 0;
             B[k] = v;
