@@ -3,9 +3,9 @@
 // Phase 1, adaptive-median detection (integer, one shot). A 16x16 workgroup
 // stages its pixels plus a halo of w_max/2 in LDS. Each thread grows its window
 // w = 3, 5, ..., w_max over the in-range pixels only; for each window it finds
-// min and max in one pass and the lower median (rank (count-1)/2) by an 8-step
-// radix select: the largest v with #{x < v} <= rank, decided one bit at a time
-// from the top. The first window with min < med < max decides the flag
+// min and max in one pass and the lower median (rank (count-1)/2) by a radix
+// select: the largest v with #{x < v} <= rank, decided two bits at a time from
+// the top (four passes over the window). The first window with min < med < max decides the flag
 // !(min < y < max); otherwise the w_max window decides (y == min || y == max).
 // Output: mask (0/1) and the initial iterate (med where flagged, y elsewhere).
 //
@@ -59,13 +59,21 @@ __global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
                 hi = max(hi, v);
             }
         const int rank = (cnt - 1) / 2;
+        // two bits per pass: of the candidates med | d << bit (d = 1, 2, 3), whose
+        // counts below grow with d, keep the largest with at most `rank` below
+        // (the same choice as two one-bit steps, with half the window reads)
         med = 0;
-        for (int bit = 7; bit >= 0; --bit) {
-            const int cand = med | (1 << bit);
-            int below = 0;
+        for (int bit = 6; bit >= 0; bit -= 2) {
+            const int c1 = med | (1 << bit), c2 = med | (2 << bit), c3 = med | (3 << bit);
+            int b1 = 0, b2 = 0, b3 = 0;
             for (int a = ia; a <= ib; ++a)
-                for (int b = ja; b <= jb; ++b) below += tile[a * TW + b] < cand;
-            if (below <= rank) med = cand;
+                for (int b = ja; b <= jb; ++b) {
+                    const int v = tile[a * TW + b];
+                    b1 += v < c1;
+                    b2 += v < c2;
+                    b3 += v < c3;
+                }
+            med = b3 <= rank ? c3 : b2 <= rank ? c2 : b1 <= rank ? c1 : med;
         }
         if (lo < med && med < hi) {
             flag = !(lo < yv && yv < hi);
