@@ -38,8 +38,9 @@ std::vector<lsr_tuning> candidates(int stencil) {
     };
     if (stencil == LSR_ST_LIFE) {
         for (int tr : {8, 16, 32, 64, 128}) add(tr, 1, 0, 0);
-        for (int depth : {2, 3, 4, 6, 8})
-            for (int tr : {16, 32, 64, 128}) add(tr, depth, 0, 0);
+        // tile_rows 0: the band height the fused kernel derives from its occupancy
+        for (int depth : {2, 3, 4, 5, 6, 8})
+            for (int tr : {0, 16, 32, 64, 128}) add(tr, depth, 0, 0);
         return out;
     }
     static constexpr int kUnfused[][2] = {{1, 8}, {2, 8}, {4, 4}, {4, 8}, {4, 16}};
@@ -112,6 +113,9 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
     // a short run of the same loop: enough sweeps for several launches at every depth
     const double cells = (double)rows * (double)cols;
     int64_t sweeps = (int64_t)std::min(400.0, std::max(40.0, 2.0e9 / std::max(cells, 1.0)));
+    // a fused Life launch takes tens of microseconds: 40 generations are a few
+    // launches, too few to rank depths
+    if (stencil_id == LSR_ST_LIFE) sweeps = std::max<int64_t>(sweeps, 240);
     sweeps = (sweeps + 39) / 40 * 40;
     if (max_iter > 0) sweeps = std::min<int64_t>(sweeps, max_iter);
     const int reduce = stencil_id == LSR_ST_LIFE ? LSR_RED_SUM : LSR_RED_MAX_ABS_DELTA;
