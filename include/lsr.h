@@ -191,9 +191,11 @@ lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
  * the fastest in the context's table under the key (stencil_id, dtype, bit lengths of rows
  * and cols, check_every). Later lsr_run calls whose overrides leave the launch shape
  * automatic (tile_rows, tb_depth, waves and unroll all 0) take the table's entry for their
- * key, so a job's settings depend only on its key. The winner is copied to best_out when it
- * is not NULL. Blocks until done (a few hundred short jobs; about a second at 8192^2).
- * Plain contexts only (EINVAL on a batched one, or for RESTORE); ENOMEM/EDEVICE as lsr_run.
+ * key, so a job's settings depend only on its key (a batched context takes the entry's fused
+ * depth and band rows; give it a measured table with lsr_tune_import). The winner is copied
+ * to best_out when it is not NULL. Blocks until done (a few hundred short jobs; about a
+ * second at 8192^2). Runs on plain contexts only (EINVAL on a batched one, or for RESTORE);
+ * ENOMEM/EDEVICE as lsr_run.
  * The caller owns nothing new; scratch returns to the context's pool.
  */
 lsr_status lsr_autotune(lsr_ctx *ctx, int32_t stencil_id, int32_t dtype, int64_t rows,
