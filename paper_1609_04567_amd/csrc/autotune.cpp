@@ -65,8 +65,8 @@ const char* arch_name(int device) {
 
 }  // namespace
 
-TuneKey tune_key(int stencil, int dtype, int64_t rows, int64_t cols, int check_every) {
-    return TuneKey{stencil, dtype, bit_length(rows), bit_length(cols), check_every};
+TuneKey tune_key(int stencil, int dtype, int bc, int64_t rows, int64_t cols, int check_every) {
+    return TuneKey{stencil, dtype, bc, bit_length(rows), bit_length(cols), check_every};
 }
 
 }  // namespace lsr_rt
@@ -74,7 +74,7 @@ TuneKey tune_key(int stencil, int dtype, int64_t rows, int64_t cols, int check_e
 lsr_tuning lsr_ctx::tuned_for(const lsr_grid& g, int stencil, int check_every) const {
     lsr_tuning t = tuning;
     if (!automatic_shape(t)) return t;
-    auto it = tune_table.find(tune_key(stencil, g.dtype, g.rows, g.cols, check_every));
+    auto it = tune_table.find(tune_key(stencil, g.dtype, g.bc, g.rows, g.cols, check_every));
     if (it == tune_table.end()) return t;
     const lsr_tuning& w = it->second.tuning;
     t.tile_rows = w.tile_rows;
@@ -148,46 +148,55 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
         std::lock_guard<std::mutex> lk(ctx->mu);
         base = ctx->tuning;
     }
-    lsr_tuning best{};
-    double best_ms = 1e300;
-    for (const lsr_tuning& cand : candidates(stencil_id)) {
-        lsr_tuning t = base;
-        t.tile_rows = cand.tile_rows;
-        t.tb_depth = cand.tb_depth;
-        t.waves = cand.waves;
-        t.unroll = cand.unroll;
-        double ms = 1e300;
-        for (int rep = 0; rep < 2 && st == LSR_OK; ++rep) {   // the first run also warms up
-            std::unique_ptr<Job> j(new Job());
-            j->grid = g;
-            j->xgrid = g;
-            j->stencil = stencil_id;
-            j->cond = cond;
-            j->max_iter = sweeps;
-            lsr_job id = 0;
-            st = submit_plain(ctx, std::move(j), &g, stencil_id, reduce, &cond, sweeps, t, &id);
+    // Life jobs key on their boundary too: both boundaries are measured
+    const int bcs_life[] = {LSR_BC_TORUS, LSR_BC_BOTTOM};
+    const int bcs_jac[] = {LSR_BC_RING};
+    const int* bcs = stencil_id == LSR_ST_LIFE ? bcs_life : bcs_jac;
+    const int nbc = stencil_id == LSR_ST_LIFE ? 2 : 1;
+    lsr_tuning best_first{};
+    for (int b = 0; b < nbc && st == LSR_OK; ++b) {
+        g.bc = bcs[b];
+        lsr_tuning best{};
+        double best_ms = 1e300;
+        for (const lsr_tuning& cand : candidates(stencil_id)) {
+            lsr_tuning t = base;
+            t.tile_rows = cand.tile_rows;
+            t.tb_depth = cand.tb_depth;
+            t.waves = cand.waves;
+            t.unroll = cand.unroll;
+            double ms = 1e300;
+            for (int rep = 0; rep < 2 && st == LSR_OK; ++rep) {   // the first run also warms up
+                std::unique_ptr<Job> j(new Job());
+                j->grid = g;
+                j->xgrid = g;
+                j->stencil = stencil_id;
+                j->cond = cond;
+                j->max_iter = sweeps;
+                lsr_job id = 0;
+                st = submit_plain(ctx, std::move(j), &g, stencil_id, reduce, &cond, sweeps, t, &id);
+                if (st != LSR_OK) break;
+                lsr_job_result r{};
+                st = lsr_result(ctx, id, 1, &r);
+                if (st == LSR_OK) ms = std::min(ms, r.device_ms);
+            }
             if (st != LSR_OK) break;
-            lsr_job_result r{};
-            st = lsr_result(ctx, id, 1, &r);
-            if (st == LSR_OK) ms = std::min(ms, r.device_ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
         }
         if (st != LSR_OK) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = t;
-        }
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        TuneEntry& en = ctx->tune_table[tune_key(stencil_id, dtype, g.bc, rows, cols, check_every)];
+        en.tuning = best;
+        en.us_per_sweep = best_ms * 1e3 / (double)sweeps;
+        if (b == 0) best_first = best;
     }
     (void)hipStreamSynchronize(ctx->user_stream);
     ctx->pool.release(grid_buf);
     ctx->pool.release(env_buf);
     if (st != LSR_OK) return st;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        TuneEntry& en = ctx->tune_table[tune_key(stencil_id, dtype, rows, cols, check_every)];
-        en.tuning = best;
-        en.us_per_sweep = best_ms * 1e3 / (double)sweeps;
-    }
-    if (best_out) *best_out = best;
+    if (best_out) *best_out = best_first;
     return LSR_OK;
 }
 
@@ -204,10 +213,10 @@ lsr_status lsr_tune_export(lsr_ctx* ctx, char* buf, uint64_t cap, uint64_t* len_
             const lsr_tuning& t = kv.second.tuning;
             char line[512];
             std::snprintf(line, sizeof line,
-                          "%s\n  {\"stencil\": %d, \"dtype\": %d, \"rows_log2\": %d, \"cols_log2\": %d, "
-                          "\"check_every\": %d, \"tile_rows\": %d, \"tb_depth\": %d, \"waves\": %d, "
-                          "\"unroll\": %d, \"us_per_sweep\": %.6g}",
-                          first ? "" : ",", k.stencil, k.dtype, k.rows_log2, k.cols_log2,
+                          "%s\n  {\"stencil\": %d, \"dtype\": %d, \"bc\": %d, \"rows_log2\": %d, "
+                          "\"cols_log2\": %d, \"check_every\": %d, \"tile_rows\": %d, \"tb_depth\": %d, "
+                          "\"waves\": %d, \"unroll\": %d, \"us_per_sweep\": %.6g}",
+                          first ? "" : ",", k.stencil, k.dtype, k.bc, k.rows_log2, k.cols_log2,
                           k.check_every, t.tile_rows, t.tb_depth, t.waves, t.unroll,
                           kv.second.us_per_sweep);
             s += line;
@@ -248,21 +257,40 @@ lsr_status lsr_tune_import(lsr_ctx* ctx, const char* json) {
         const size_t b = s.find('}', a);
         if (b == std::string::npos) return fail(LSR_EINVAL, "unterminated entry");
         const std::string obj = s.substr(a, b - a + 1);
-        const char* names[] = {"stencil", "dtype", "rows_log2", "cols_log2", "check_every",
+        const char* names[] = {"stencil", "dtype", "bc", "rows_log2", "cols_log2", "check_every",
                                "tile_rows", "tb_depth", "waves", "unroll", "us_per_sweep"};
-        double v[10];
-        for (int i = 0; i < 10; ++i)
+        double v[11];
+        for (int i = 0; i < 11; ++i)
             if (!field(obj, names[i], &v[i])) return fail(LSR_EINVAL, "entry lacks \"%s\"", names[i]);
-        TuneKey k{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4]};
+        for (int i = 0; i < 10; ++i)
+            if (!(v[i] >= -1.0 && v[i] <= 2147483647.0) || v[i] != std::floor(v[i]))
+                return fail(LSR_EINVAL, "entry field \"%s\" is not an integer in range", names[i]);
+        TuneKey k{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5]};
         TuneEntry en{};
-        en.tuning.tile_rows = (int)v[5];
-        en.tuning.tb_depth = (int)v[6];
-        en.tuning.waves = (int)v[7];
-        en.tuning.unroll = (int)v[8];
-        en.us_per_sweep = v[9];
-        if (k.check_every < 1 || en.tuning.tile_rows < 0 || en.tuning.tb_depth < 0 ||
-            en.tuning.waves < 0 || en.tuning.unroll < 0)
-            return fail(LSR_EINVAL, "entry has an out-of-range field");
+        en.tuning.tile_rows = (int)v[6];
+        en.tuning.tb_depth = (int)v[7];
+        en.tuning.waves = (int)v[8];
+        en.tuning.unroll = (int)v[9];
+        en.us_per_sweep = v[10];
+        const lsr_tuning& t = en.tuning;
+        const bool jac = k.stencil == LSR_ST_LAPLACE5 || k.stencil == LSR_ST_HELMHOLTZ5;
+        const bool life = k.stencil == LSR_ST_LIFE;
+        if (!jac && !life) return fail(LSR_EINVAL, "entry for stencil %d, which has no launch shapes", k.stencil);
+        if (jac ? (k.dtype != LSR_F64 && k.dtype != LSR_F32) || k.bc != LSR_BC_RING
+                : k.dtype != LSR_U8 || (k.bc != LSR_BC_TORUS && k.bc != LSR_BC_BOTTOM))
+            return fail(LSR_EINVAL, "entry's dtype or boundary does not fit stencil %d", k.stencil);
+        if (k.rows_log2 < 1 || k.rows_log2 > 40 || k.cols_log2 < 1 || k.cols_log2 > 40 || k.check_every < 1)
+            return fail(LSR_EINVAL, "entry has an out-of-range key field");
+        const bool depth_ok = t.tb_depth == 0 || t.tb_depth == 1 ||
+                              (jac ? lsr::jacobi_tb_depth_ok(t.tb_depth) : lsr::life_tb_depth_ok(t.tb_depth));
+        if (!depth_ok) return fail(LSR_EINVAL, "entry's tb_depth %d is not a compiled depth", t.tb_depth);
+        if (t.tile_rows < 0 || t.tile_rows > 65536)
+            return fail(LSR_EINVAL, "entry's tile_rows %d is outside [0, 65536]", t.tile_rows);
+        if (jac ? !(t.waves == 0 || t.waves == 1 || t.waves == 2 || t.waves == 4) ||
+                      !(t.unroll == 0 || t.unroll == 4 || t.unroll == 8 || t.unroll == 16)
+                : t.waves != 0 || t.unroll != 0)
+            return fail(LSR_EINVAL, "entry's waves %d / unroll %d are not supported", t.waves, t.unroll);
+        if (!(en.us_per_sweep >= 0.0)) return fail(LSR_EINVAL, "entry's us_per_sweep is negative");
         parsed[k] = en;
         pos = b + 1;
     }

@@ -90,7 +90,8 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     d.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
     lsr::LoopCtl& c = d.ctl;
     c.max_iter = j->max_iter;
-    c.check_every = j->cond.check_every;
+    // a check period of at least max_iter leaves only the check at the cap
+    c.check_every = (int32_t)std::min<int64_t>(j->cond.check_every, j->max_iter);
     c.chunk = 1;
     c.reduce = j->ctl.reduce;
     c.cond = j->cond.kind;
@@ -323,7 +324,7 @@ void lsr_ctx::engine_scan() {
         // a stop inside a fused round is replayed first; then the buffer holding
         // sweep n goes back to the caller's grid
         int last = 0;
-        hipError_t e = finish_fused(j, fin, j->desc.step, j->desc.ctl, &last) == LSR_OK
+        hipError_t e = finish_fused(j, fin, j->desc.step, j->desc.ctl, &last, stream) == LSR_OK
                            ? hipSuccess : hipErrorLaunchFailure;
         if (e == hipSuccess && j->staged)
             e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,

@@ -72,6 +72,8 @@ hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void
 // each checked generation in its own slice of partials (g.mc). Rows must be
 // 16-byte aligned multiples of 16 cells, unpadded (life_tb_ok).
 bool life_tb_ok(const LifeArgs& a);
+// True for a compiled fused Life depth (2, 3, 4, 5, 6, 8).
+bool life_tb_depth_ok(int depth);
 // Generations per launch for a job: `requested` (0 = automatic, 1 = unfused, or
 // a compiled depth), 1 when the rows do not qualify.
 int life_tb_choose(const LifeArgs& a, int requested);

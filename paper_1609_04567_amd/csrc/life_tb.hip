@@ -280,6 +280,12 @@ bool life_tb_ok(const LifeArgs& a) {
     return al && a.pitch % 16 == 0 && a.cols % 16 == 0 && !a.padded;
 }
 
+bool life_tb_depth_ok(int depth) {
+    for (int k : kDepths)
+        if (k == depth) return true;
+    return false;
+}
+
 int life_tb_choose(const LifeArgs& a, int requested) {
     if (requested == 1 || !life_tb_ok(a)) return 1;
     if (requested > 1) {

@@ -99,26 +99,35 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
 
 namespace {
 
+// Longest chunk base (sweeps) the driver captures into one graph.
+constexpr int64_t kMaxChunkBase = 65536;
+
 // Sweeps per chunk: a multiple of lcm(check_every, 2 * tb) that keeps a chunk
 // near kChunkTargetUs of device time at HBM speed, so the enqueue-ahead window
 // stays a few milliseconds and the overshoot after a stop stays bounded. A
-// chunk then ends on a check sweep and holds an even number of launches, so
-// every chunk (and every replay of a captured one) starts from buffer 0.
+// chunk then holds an even number of launches, so every chunk (and every replay
+// of a captured one) starts from buffer 0, and every chunk has its check sweeps
+// at the same offsets. A check period of at least max_iter leaves only the check
+// at the cap, which falls at one fixed offset of the last chunk: the base is then
+// 2 * tb. Computed in 64 bits; 0 when the base exceeds kMaxChunkBase.
 int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int override_chunk, int tb) {
-    const int base = std::lcm(check_every, 2 * tb);
-    int chunk;
+    const int64_t base = (int64_t)check_every >= max_iter ? 2 * (int64_t)tb
+                                                           : std::lcm((int64_t)check_every, 2 * (int64_t)tb);
+    if (base > kMaxChunkBase) return 0;
+    int64_t chunk;
     if (override_chunk > 0) {
-        chunk = (override_chunk + base - 1) / base * base;
+        chunk = ((int64_t)override_chunk + base - 1) / base * base;
     } else {
         const double bytes = (double)g->rows * (double)g->cols * (double)dtype_size(g->dtype) * 3.0;
         const double est_us = std::max(4.0, bytes / 5.0e6);
-        int m = (int)std::max(1.0, std::floor(kChunkTargetUs / (est_us * base)));
+        const int64_t m = (int64_t)std::max(1.0, std::floor(kChunkTargetUs / (est_us * (double)base)));
         chunk = base * m;
         if (chunk > kMaxChunk) chunk = std::max(base, kMaxChunk / base * base);
     }
     const int64_t cap = (max_iter + base - 1) / base * base;
-    if (chunk > cap) chunk = (int)cap;
-    return chunk;
+    if (chunk > cap) chunk = cap;
+    if (chunk > kMaxChunkBase) chunk = base;
+    return (int)chunk;
 }
 
 }  // namespace
@@ -162,7 +171,7 @@ lsr::LifeArgs lsr_rt::life_args(const Job* j, const void* src, void* dst) {
     return a;
 }
 
-lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
+lsr_status lsr_rt::launch_sweep(Job* j, int off, hipStream_t s) {
     // one launch advances tb sweeps (off .. off + tb - 1 of the chunk)
     const int tb = j->geom.tb;
     const int launch = off / tb;
@@ -198,11 +207,11 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
     const int last = off + tb - 1;
     if (j->geom.mc) {
         bool any = false;
-        for (int k = off; k <= last; ++k) any = any || j->fin_after[k];
+        for (int k = off; k <= last; ++k) any = any || j->fin_at(k);
         if (any)
             e = lsr::launch_finalize_levels(j->st, j->partials, j->ctl, off, tb, j->geom.tiles,
                                             j->mirror_dev, s);
-    } else if (j->fin_after[last]) {
+    } else if (j->fin_at(last)) {
         e = lsr::launch_finalize(j->st, j->partials, j->ctl, last, j->mirror_dev, s);
     }
     if (e != hipSuccess) return fail(LSR_EDEVICE, "finalize launch: %s", hipGetErrorString(e));
@@ -215,34 +224,35 @@ lsr_status lsr_ctx::launch_sweep(Job* j, int off, hipStream_t s) {
 // the sweeps up to the stop are replayed there with the unfused kernel, under a
 // scratch loop state (the job's real final state is already in the host mirror).
 // Returns the buffer holding sweep n in *last.
-lsr_status lsr_ctx::finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::LoopCtl& ctl,
-                                 int* last) {
+lsr_status lsr_rt::finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::LoopCtl& ctl,
+                                int* last, hipStream_t s) {
     if (K == 1 || fin.n % K == 0) {
         *last = (int)((fin.n / K) & 1);
         return LSR_OK;
     }
     const int64_t L = (fin.n - 1) / K;          // the launch holding the stop
     const int m = (int)(fin.n - L * K);         // its sweeps to keep (1 .. K-1)
-    HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream, L * K));
+    HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, s, L * K));
     lsr::LoopCtl rc = ctl;
     rc.max_iter = fin.n;
     rc.check_every = 0x7fffffff;                // only sweep n is a "check" (its partials are unused)
+    rc.chunk = 0x7fffffff;
     for (int k = 0; k < m; ++k) {
         void* src = j->buf[(L + k) & 1];
         void* dst = j->buf[(L + k + 1) & 1];
         if (j->stencil == LSR_ST_LIFE) {
             lsr::LifeArgs a = life_args(j, src, dst);
-            HIP_TRY(lsr::launch_life(a, j->replay_geom, j->st, j->partials, rc, k, stream));
+            HIP_TRY(lsr::launch_life(a, j->replay_geom, j->st, j->partials, rc, k, s));
         } else {
             HIP_TRY(lsr::launch_jacobi(jacobi_args(j, src, dst), j->replay_geom, j->st, j->partials,
-                                       rc, k, stream));
+                                       rc, k, s));
         }
     }
     *last = (int)((L + m) & 1);
     return LSR_OK;
 }
 
-lsr_status lsr_ctx::enqueue_chunk_plain(Job* j, hipStream_t s) {
+lsr_status lsr_rt::enqueue_chunk(Job* j, hipStream_t s) {
     for (int off = 0; off < j->ctl.chunk; off += j->geom.tb) {
         lsr_status st = launch_sweep(j, off, s);
         if (st != LSR_OK) return st;
@@ -282,7 +292,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
     }
     if (j->use_graph) {
         HIP_TRY(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
-        lsr_status st = enqueue_chunk_plain(j, capture);
+        lsr_status st = enqueue_chunk(j, capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(capture, &graph);
         if (st != LSR_OK) {
@@ -311,7 +321,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
                 hipError_t e = hipGraphLaunch(j->exec, stream);
                 if (e != hipSuccess) { status = fail(LSR_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e)); break; }
             } else {
-                status = enqueue_chunk_plain(j, stream);
+                status = enqueue_chunk(j, stream);
                 if (status != LSR_OK) break;
             }
             hipEvent_t ev = get_event();
@@ -349,7 +359,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
     lsr::JobState fin;
     std::memcpy(&fin, (const void*)mir, sizeof fin);
     int last = 0;
-    lsr_status rs = finish_fused(j, fin, j->geom.tb, j->ctl, &last);
+    lsr_status rs = finish_fused(j, fin, j->geom.tb, j->ctl, &last, stream);
     if (rs != LSR_OK) return rs;
     if (j->staged)
         HIP_TRY(hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
@@ -521,6 +531,84 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
 }  // extern "C"
 
 // The plain (one job at a time) path of lsr_run with the launch settings resolved.
+lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int* nparts_out) {
+    const lsr_grid& g = j->xgrid;
+    const int stencil_id = j->stencil;
+    // a check period of at least max_iter leaves only the check at the cap: the
+    // same loop as a period of exactly max_iter
+    const int check_every = (int)std::min<int64_t>(j->cond.check_every, j->max_iter);
+    auto plan = [&](int want_depth) {
+        switch (stencil_id) {
+            case LSR_ST_LAPLACE5:
+            case LSR_ST_HELMHOLTZ5: {
+                lsr::JacobiArgs a{};
+                a.a = j->buf[0];
+                a.b = j->buf[1];
+                a.g = g.env0;
+                a.rows = g.rows;
+                a.cols = g.cols;
+                a.pitch = g.pitch;
+                a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
+                a.f32 = g.dtype == LSR_F32;
+                int depth = 1, mc = 0;
+                lsr::jacobi_tb_choose(a, check_every, j->max_iter, want_depth, &depth, &mc);
+                j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth, mc);
+                // unfused sweeps that replay a stop inside a fused launch
+                j->replay_geom = lsr::jacobi_geom(a, 0);
+                break;
+            }
+            case LSR_ST_LIFE: {
+                lsr::LifeArgs a{};
+                a.a = static_cast<const uint8_t*>(j->buf[0]);
+                a.b = static_cast<uint8_t*>(j->buf[1]);
+                a.rows = g.rows;
+                a.cols = g.cols;
+                a.pitch = g.pitch;
+                a.torus = g.bc == LSR_BC_TORUS;
+                a.padded = j->staged;
+                const int depth = lsr::life_tb_choose(a, want_depth);
+                j->geom = depth > 1 ? lsr::life_tb_geom(a, depth, tun.tile_rows)
+                                    : lsr::life_geom(a, tun.tile_rows);
+                // single generations that replay a stop inside a fused launch
+                j->replay_geom = lsr::life_geom(a, 0);
+                break;
+            }
+            default: {
+                lsr::RestoreArgs a{};
+                a.rows = g.rows;
+                a.cols = g.cols;
+                j->geom = lsr::restore_geom(a, tun.tile_rows);
+            }
+        }
+        return pick_chunk(&g, check_every, j->max_iter, tun.chunk, j->geom.tb);
+    };
+    int chunk = plan(tun.tb_depth);
+    // a check period whose lcm with two fused launches is too long to capture:
+    // unfused sweeps need only lcm(check_every, 2)
+    if (chunk == 0 && j->geom.tb > 1) chunk = plan(1);
+    if (chunk == 0)
+        return fail(LSR_EINVAL, "check_every %d: a chunk of lcm(check_every, 2) sweeps exceeds %lld; "
+                                "use a check period of at most %lld or at least max_iter",
+                    j->cond.check_every, (long long)kMaxChunkBase, (long long)(kMaxChunkBase / 2));
+    int nparts = j->geom.tiles;
+    if (j->geom.mc) nparts = j->geom.tiles * j->geom.tb;   // one slice per level
+    if (j->geom.tb > 1) nparts = std::max(nparts, j->replay_geom.tiles);
+    if (stencil_id == LSR_ST_LIFE) nparts = std::max(nparts, lsr::count_u8_parts(g.rows, g.cols));
+    *nparts_out = nparts;
+    lsr::LoopCtl& c = j->ctl;
+    c.max_iter = j->max_iter;
+    c.check_every = check_every;
+    c.chunk = chunk;
+    c.reduce = reduce_op;
+    c.cond = j->cond.kind;
+    c.stable_window = j->cond.stable_window;
+    c.nparts = j->geom.tiles;
+    c.threshold = j->cond.threshold;
+    c.mean_div = (double)g.rows * (double)g.cols;
+    return LSR_OK;
+}
+
+// The plain (one job at a time) path of lsr_run with the launch settings resolved.
 lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
                                 int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
                                 int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out) {
@@ -558,73 +646,15 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
         give_back();
         return st;
     }
-    switch (stencil_id) {
-        case LSR_ST_LAPLACE5:
-        case LSR_ST_HELMHOLTZ5: {
-            lsr::JacobiArgs a{};
-            a.a = j->buf[0];
-            a.b = j->buf[1];
-            a.g = j->xgrid.env0;
-            a.rows = grid->rows;
-            a.cols = grid->cols;
-            a.pitch = j->xgrid.pitch;
-            a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
-            a.f32 = grid->dtype == LSR_F32;
-            int depth = 1, mc = 0;
-            lsr::jacobi_tb_choose(a, cond->check_every, max_iter, tun.tb_depth, &depth, &mc);
-            j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth, mc);
-            // unfused sweeps that replay a stop inside a fused launch
-            j->replay_geom = lsr::jacobi_geom(a, 0);
-            break;
-        }
-        case LSR_ST_LIFE: {
-            lsr::LifeArgs a{};
-            a.a = static_cast<const uint8_t*>(j->buf[0]);
-            a.b = static_cast<uint8_t*>(j->buf[1]);
-            a.rows = grid->rows;
-            a.cols = grid->cols;
-            a.pitch = j->xgrid.pitch;
-            a.torus = grid->bc == LSR_BC_TORUS;
-            a.padded = j->staged;
-            const int depth = lsr::life_tb_choose(a, tun.tb_depth);
-            j->geom = depth > 1 ? lsr::life_tb_geom(a, depth, tun.tile_rows)
-                                : lsr::life_geom(a, tun.tile_rows);
-            // single generations that replay a stop inside a fused launch
-            j->replay_geom = lsr::life_geom(a, 0);
-            break;
-        }
-        default: {
-            lsr::RestoreArgs a{};
-            a.rows = grid->rows;
-            a.cols = grid->cols;
-            j->geom = lsr::restore_geom(a, tun.tile_rows);
-        }
-    }
-    int nparts = j->geom.tiles;
-    if (j->geom.mc) nparts = j->geom.tiles * j->geom.tb;   // one slice per level
-    if (j->geom.tb > 1) nparts = std::max(nparts, j->replay_geom.tiles);
-    if (stencil_id == LSR_ST_LIFE) nparts = std::max(nparts, lsr::count_u8_parts(grid->rows, grid->cols));
-    st = ctx->pool.alloc((size_t)std::max(nparts, 1) * 8, &j->partials);
+    int nparts = 0;
+    st = plan_plain(j.get(), reduce_op, tun, &nparts);
+    if (st == LSR_OK) st = ctx->pool.alloc((size_t)std::max(nparts, 1) * 8, &j->partials);
     if (st == LSR_OK) st = ctx->pool.alloc(sizeof(lsr::JobState), (void**)&j->st);
     if (st != LSR_OK) {
         j->release_scratch(ctx->pool);
         give_back();
         return st;
     }
-    lsr::LoopCtl& c = j->ctl;
-    c.max_iter = max_iter;
-    c.check_every = cond->check_every;
-    c.chunk = pick_chunk(grid, cond->check_every, max_iter, tun.chunk, j->geom.tb);
-    c.reduce = reduce_op;
-    c.cond = cond->kind;
-    c.stable_window = cond->stable_window;
-    c.nparts = j->geom.tiles;
-    c.threshold = cond->threshold;
-    c.mean_div = (double)grid->rows * (double)grid->cols;
-    j->fin_after.assign(c.chunk, 0);
-    const int jmax = (int)((max_iter - 1) % c.chunk);
-    for (int off = 0; off < c.chunk; ++off)
-        j->fin_after[off] = ((off + 1) % c.check_every == 0) || off == jmax;
     j->use_graph = tun.use_graph >= 0;
     j->mirror_host = ctx->mirrors_host + j->slot;
     j->mirror_dev = ctx->mirrors_dev + j->slot;

@@ -186,7 +186,6 @@ struct Job {
     int slot = -1;
     lsr::JobState* mirror_host = nullptr;
     lsr::JobState* mirror_dev = nullptr;
-    std::vector<char> fin_after;        // finalize after chunk offset j
     hipEvent_t ev_user = nullptr, ev_begin = nullptr, ev_end = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -204,6 +203,14 @@ struct Job {
     bool cancel_posted = false;         // a cancel kernel has been enqueued
     hipEvent_t ev_small = nullptr;      // end of a small job's launch on the second stream
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+
+    // True when a finalize launch follows the sweep at chunk offset off: a check
+    // offset (a multiple of the check period), the offset of the cap sweep, and the
+    // chunk's last sweep (where the state's chunk base advances).
+    bool fin_at(int off) const {
+        const int jmax = (int)((max_iter - 1) % ctl.chunk);
+        return ((off + 1) % ctl.check_every) == 0 || off == jmax || off == ctl.chunk - 1;
+    }
 
     // Returns the job's scratch (partner, staged copies, partials, state) to the pool.
     void release_scratch(Pool& pool) {
@@ -233,19 +240,21 @@ lsr::JacobiArgs jacobi_args(const Job* j, const void* src, void* dst);
 // The same for a Life job.
 lsr::LifeArgs life_args(const Job* j, const void* src, void* dst);
 
-// Key of the autotuner's table: a job's stencil, dtype, size class (bit lengths
-// of rows and cols) and check period. A choice is a pure function of this key.
+// Key of the autotuner's table: a job's stencil, dtype, boundary, size class
+// (bit lengths of rows and cols) and check period. A choice is a pure function of
+// this key.
 struct TuneKey {
-    int stencil, dtype, rows_log2, cols_log2, check_every;
+    int stencil, dtype, bc, rows_log2, cols_log2, check_every;
     bool operator<(const TuneKey& o) const {
         if (stencil != o.stencil) return stencil < o.stencil;
         if (dtype != o.dtype) return dtype < o.dtype;
+        if (bc != o.bc) return bc < o.bc;
         if (rows_log2 != o.rows_log2) return rows_log2 < o.rows_log2;
         if (cols_log2 != o.cols_log2) return cols_log2 < o.cols_log2;
         return check_every < o.check_every;
     }
 };
-TuneKey tune_key(int stencil, int dtype, int64_t rows, int64_t cols, int check_every);
+TuneKey tune_key(int stencil, int dtype, int bc, int64_t rows, int64_t cols, int check_every);
 struct TuneEntry {
     lsr_tuning tuning;
     double us_per_sweep;   // measured device time per sweep of the winner
@@ -281,10 +290,6 @@ struct lsr_ctx {
 
     void drive();
     lsr_status run_job(lsr_rt::Job* j);
-    lsr_status launch_sweep(lsr_rt::Job* j, int off, hipStream_t s);
-    lsr_status enqueue_chunk_plain(lsr_rt::Job* j, hipStream_t s);
-    lsr_status finish_fused(lsr_rt::Job* j, const lsr::JobState& fin, int step,
-                            const lsr::LoopCtl& ctl, int* last);
     hipEvent_t get_event();
     void put_event(hipEvent_t e) { event_pool.push_back(e); }
 
@@ -317,6 +322,20 @@ struct lsr_ctx {
 };
 
 namespace lsr_rt {
+// Plans a plain-path job whose exec grid (xgrid) and buffer roles are set:
+// sweep geometry (fused depth from the tuning), the unfused replay geometry, the
+// loop control with its chunk, and the partial count to allocate. EINVAL when the
+// check period makes a chunk too long to capture.
+lsr_status plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int* nparts_out);
+// Enqueues the sweep launch that starts at chunk offset off (and the finalize
+// that follows it, if any) on stream s.
+lsr_status launch_sweep(Job* j, int off, hipStream_t s);
+// Enqueues one whole chunk of sweep and finalize launches on s.
+lsr_status enqueue_chunk(Job* j, hipStream_t s);
+// After a stop: replays a stop inside a fused launch with unfused sweeps (on s)
+// and returns in *last the buffer that holds sweep fin.n.
+lsr_status finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::LoopCtl& ctl,
+                        int* last, hipStream_t s);
 lsr_status submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
                         int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
                         int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out);

@@ -29,8 +29,8 @@ def test_helmholtz_tuned_job_matches_oracle(tctx):
     table = json.loads(L.lsr_tune_export(tctx.handle))
     assert table["arch"].startswith("gfx")
     (e,) = table["entries"]
-    assert (e["stencil"], e["dtype"], e["rows_log2"], e["cols_log2"], e["check_every"]) == \
-        (L.LSR_ST_HELMHOLTZ5, L.LSR_F64, 9, 9, 10)
+    assert (e["stencil"], e["dtype"], e["bc"], e["rows_log2"], e["cols_log2"], e["check_every"]) == \
+        (L.LSR_ST_HELMHOLTZ5, L.LSR_F64, L.LSR_BC_RING, 9, 9, 10)
     assert (e["tile_rows"], e["tb_depth"], e["waves"], e["unroll"]) == \
         (best.tile_rows, best.tb_depth, best.waves, best.unroll) and e["us_per_sweep"] > 0
     h = I.helmholtz_input(300)
@@ -45,10 +45,35 @@ def test_helmholtz_tuned_job_matches_oracle(tctx):
 def test_life_tuned_job_matches_oracle(tctx):
     say("autotune life 200x208")
     tctx.autotune(L.LSR_ST_LIFE, L.LSR_U8, 200, 208, 1, 300)
+    # both boundaries are measured and keyed separately
+    keys = sorted(e["bc"] for e in json.loads(L.lsr_tune_export(tctx.handle))["entries"])
+    assert keys == [L.LSR_BC_TORUS, L.LSR_BC_BOTTOM]
     a = I.life_input(200, 208, seed=3)
-    o, ro = O.life_run(a, bc=O.BC_TORUS, stable_window=10, max_iter=300)
-    x, r = run_life(tctx, a, window=10, max_iter=300)
-    assert r.iterations == ro.n and np.array_equal(x, o)
+    for torus, bc in ((True, O.BC_TORUS), (False, O.BC_BOTTOM)):
+        o, ro = O.life_run(a, bc=bc, stable_window=10, max_iter=300)
+        x, r = run_life(tctx, a, torus=torus, window=10, max_iter=300)
+        assert r.iterations == ro.n and np.array_equal(x, o)
+
+
+_ENTRY = {"stencil": 3, "dtype": 1, "bc": 1, "rows_log2": 8, "cols_log2": 8, "check_every": 1,
+          "tile_rows": 0, "tb_depth": 8, "waves": 0, "unroll": 0, "us_per_sweep": 1.0}
+
+
+@pytest.mark.parametrize("bad", [{"stencil": 4}, {"stencil": 9}, {"tb_depth": 7}, {"tb_depth": 3, "stencil": 2,
+                                  "dtype": 8, "bc": 0}, {"bc": 0}, {"dtype": 8}, {"tile_rows": -2},
+                                 {"tile_rows": 100000}, {"waves": 2}, {"check_every": 0},
+                                 {"tb_depth": 2.5}])
+def test_import_rejects_entries_the_library_cannot_run(tctx, bad):
+    say(f"tune import rejects {bad}")
+    base = {"arch": json.loads(L.lsr_tune_export(tctx.handle))["arch"], "entries": [dict(_ENTRY)]}
+    L.lsr_tune_import(tctx.handle, json.dumps(base))       # the valid entry is taken
+    good = L.lsr_tune_export(tctx.handle)
+    e = dict(_ENTRY)
+    e.update(bad)
+    with pytest.raises(L.LsrError) as ei:
+        L.lsr_tune_import(tctx.handle, json.dumps({"arch": base["arch"], "entries": [e]}))
+    assert ei.value.status == L.LSR_EINVAL
+    assert L.lsr_tune_export(tctx.handle) == good         # the table is unchanged
 
 
 def test_table_round_trips_and_rejects_other_arch(tctx):
@@ -91,7 +116,7 @@ def test_batched_jobs_take_the_table_entry():
             if tuned:
                 table = json.loads(L.lsr_tune_export(c.handle))
                 table["entries"] = [{"stencil": L.LSR_ST_HELMHOLTZ5, "dtype": L.LSR_F32,
-                                     "rows_log2": 9, "cols_log2": 9, "check_every": 10,
+                                     "bc": L.LSR_BC_RING, "rows_log2": 9, "cols_log2": 9, "check_every": 10,
                                      "tile_rows": 16, "tb_depth": 2, "waves": 0, "unroll": 0,
                                      "us_per_sweep": 1.0}]
                 L.lsr_tune_import(c.handle, json.dumps(table))

@@ -167,16 +167,24 @@ def test_cancel_pending_and_running(bctx):
     import torch
     say("batched cancel")
     h = I.helmholtz_input(1024)
-    t = torch.zeros((1024, 1024), dtype=torch.float64, device="cuda:0")
-    g = torch.from_numpy(h.g).to("cuda:0")
-    j1 = bctx.submit(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
-                     L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 5000, L.LSR_BC_RING, env0=g,
-                     param=(h.alpha, h.h))
+    mk = lambda: (torch.zeros((1024, 1024), dtype=torch.float64, device="cuda:0"),
+                  torch.from_numpy(h.g).to("cuda:0"))
+    cond = L.make_cond(L.LSR_COND_BELOW, 1e-9, 10)
+    # two million sweeps of 1024^2 take seconds: both jobs are still running or
+    # queued when the cancels arrive
+    (t1, g1), (t2, g2) = mk(), mk()
+    j1 = bctx.submit(t1, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, 2_000_000, L.LSR_BC_RING,
+                     env0=g1, param=(h.alpha, h.h))
+    j2 = bctx.submit(t2, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, 2_000_000, L.LSR_BC_RING,
+                     env0=g2, param=(h.alpha, h.h))
+    out = L._native.lsr_job_result()
+    assert L._native.lib().lsr_result(bctx.handle, j1, 0, L._native.C.byref(out)) == L.LSR_EBUSY
+    bctx.cancel(j2)
     bctx.cancel(j1)
-    r1 = bctx.result(j1)
-    assert r1.status in (L.LSR_ECANCELED, L.LSR_OK)
-    if r1.status == L.LSR_ECANCELED:
-        assert r1.iterations < 5000
+    for j in (j1, j2):
+        r = bctx.result(j)
+        assert r.status == L.LSR_ECANCELED
+        assert 0 <= r.iterations < 2_000_000 and not r.converged
 
 
 def test_restoration_rejected_on_batched_context(bctx):

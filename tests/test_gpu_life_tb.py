@@ -15,7 +15,7 @@ from gpu_helpers import run_life, say
 
 pytestmark = pytest.mark.gpu
 
-DEPTHS = [2, 3, 4, 6, 8]
+DEPTHS = [2, 3, 4, 5, 6, 8]
 
 
 def _tuned(ctx, fn, **tune):

@@ -463,7 +463,7 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
 
 @pytest.mark.parametrize("rows,cols,k,tile_rows", [
     (1, 16, 2, 64), (2, 32, 3, 8), (3, 48, 4, 4), (9, 64, 8, 4), (40, 1008, 4, 16),
-    (37, 2000, 3, 8), (20, 992, 6, 64), (13, 1024, 2, 5)])
+    (37, 2000, 3, 8), (20, 992, 6, 64), (13, 1024, 2, 5), (29, 1040, 5, 7), (6, 16, 5, 2)])
 @pytest.mark.parametrize("torus", [True, False])
 def test_life_tb_model_matches_oracle(rows, cols, k, tile_rows, torus):
     import oracle as O
