@@ -137,23 +137,33 @@ int orc_jacobi_run(int helmholtz, double *a, const double *g, int64_t rows, int6
  * Game of Life (Fig. 1): count live neighbours of the 3x3 window, then
  * alive' = (count == 3) || (alive && count == 2).
  * ------------------------------------------------------------------------- */
+/* Index of the neighbour at offset d in {-1, 0, 1} of position x on an axis of
+ * length n: wrapped on a torus, -1 (absent) past a dead border. */
+static int64_t neighbour_index(int bc, int64_t x, int d, int64_t n) {
+    int64_t y = x + d;
+    if (y >= 0 && y < n) return y;
+    if (bc != ORC_BC_TORUS) return -1;
+    return y < 0 ? y + n : y - n;
+}
+
 static void life_sweep(int bc, const uint8_t *a, uint8_t *b, int64_t rows, int64_t cols) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < rows; ++i) {
+        /* the rows above, at and below i (NULL: out of range, all dead) */
+        const uint8_t *nb_row[3];
+        for (int di = -1; di <= 1; ++di) {
+            int64_t ii = neighbour_index(bc, i, di, rows);
+            nb_row[di + 1] = ii < 0 ? NULL : a + ii * cols;
+        }
         for (int64_t j = 0; j < cols; ++j) {
+            int64_t jl = neighbour_index(bc, j, -1, cols), jr = neighbour_index(bc, j, 1, cols);
             int count = 0;
-            for (int di = -1; di <= 1; ++di) {
-                for (int dj = -1; dj <= 1; ++dj) {
-                    if (di == 0 && dj == 0) continue;
-                    int64_t ii = i + di, jj = j + dj;
-                    if (bc == ORC_BC_TORUS) {
-                        ii = (ii + rows) % rows;
-                        jj = (jj + cols) % cols;
-                    } else if (ii < 0 || jj < 0 || ii >= rows || jj >= cols) {
-                        continue; /* out of range is dead */
-                    }
-                    count += a[ii * cols + jj] != 0;
-                }
+            for (int r = 0; r < 3; ++r) {
+                const uint8_t *row = nb_row[r];
+                if (!row) continue;
+                if (jl >= 0) count += row[jl] != 0;
+                if (r != 1) count += row[j] != 0; /* the cell itself is not its neighbour */
+                if (jr >= 0) count += row[jr] != 0;
             }
             int alive = a[i * cols + j] != 0;
             b[i * cols + j] = (uint8_t)(count == 3 || (alive && count == 2));
