@@ -23,9 +23,10 @@
  * Conventions
  *  - Every call returns lsr_status; nothing throws or aborts across the ABI.
  *    lsr_last_error() gives a thread-local message for the last failure.
- *  - All grid/env pointers are DEVICE pointers (e.g. torch tensors' data_ptr())
- *    on the context's device. Grids are row-major with a row pitch counted in
- *    elements (pitch >= cols); env arrays use the same pitch as the grid.
+ *  - Grid/env pointers are DEVICE pointers (e.g. torch tensors' data_ptr()) on
+ *    the context's device, except for lsr_run_host, which takes host buffers.
+ *    Grids are row-major with a row pitch counted in elements (pitch >= cols);
+ *    env arrays use the same pitch as the grid.
  *  - The caller owns grid->data and the env arrays. The library owns its scratch
  *    (the ping-pong partner grid, per-block partials, the 64-byte job state) and
  *    draws it from a pool bounded by lsr_config.hbm_budget_bytes.
@@ -225,6 +226,30 @@ lsr_status lsr_tune_import(lsr_ctx *ctx, const char *json);
  */
 lsr_status lsr_run(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id, int32_t reduce_op,
                    const lsr_cond *cond, int64_t max_iter, lsr_job *job_out);
+
+/*
+ * Starts one job whose grid lives in HOST memory: the ingest of a stream item as
+ * the paper's runtime does it (Sect. 3.3: when a task is scheduled, device
+ * buffers are allocated and filled by H2D copies; Fig. 2: read(output) copies the
+ * result back by D2H). Same arguments, checks and supported combinations as
+ * lsr_run, except that grid->data and grid->env0 are host pointers (rows x pitch
+ * elements each) and RESTORE is EINVAL (its mask stays a device buffer).
+ *  - Memory: the context allocates the job's device grid, env and scratch from
+ *    its pool, so all of the job's device memory counts against
+ *    hbm_budget_bytes. Plain context: allocated at this call (ENOMEM/EBUSY as
+ *    lsr_run). Batched context: allocated at admission, which waits in arrival
+ *    order until the budget can hold them; the H2D copies run on the engine's
+ *    copy stream and the job joins the sweep rounds once they have completed.
+ *  - Ownership: the caller keeps both host buffers alive, and does not write
+ *    them, until lsr_result reports a terminal status; grid->data then holds the
+ *    last iterate (its contents are unspecified after EDEVICE). The device copies
+ *    are freed at retirement.
+ *  - Pinned host memory (hipHostMalloc, a torch pin_memory tensor) lets the copies
+ *    run asynchronously; with pageable memory each copy blocks the thread that
+ *    issues it.
+ */
+lsr_status lsr_run_host(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id, int32_t reduce_op,
+                        const lsr_cond *cond, int64_t max_iter, lsr_job *job_out);
 
 /*
  * Result of a job. wait != 0 blocks until the job ends; wait == 0 returns EBUSY while it

@@ -14,7 +14,7 @@ from ._native import (  # noqa: F401
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
-    lsr_probe_copy, lsr_result, lsr_run, lsr_set_tuning, lsr_tune_export, lsr_tune_import,
+    lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_set_tuning, lsr_tune_export, lsr_tune_import,
     lsr_version, make_cond, make_grid,
 )
 
@@ -33,6 +33,27 @@ def grid_from_tensor(t, bc: int, env0=None, param=()):
         raise ValueError("grid must be a 2-D device tensor with unit column stride")
     if env0 is not None and (env0.shape != t.shape or env0.stride(0) != t.stride(0)):
         raise ValueError("env0 must have the grid's shape and pitch")
+    return make_grid(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), _dtype_code(t), bc,
+                     env0.data_ptr() if env0 is not None else None, tuple(param))
+
+
+def grid_from_host(t, bc: int, env0=None, param=()):
+    """lsr_grid over a 2-D host array (a CPU torch tensor, pinned for asynchronous
+    copies, or a numpy array) with unit column stride."""
+    import numpy as np
+    import torch
+
+    def desc(a):
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(a)
+        if a.dim() != 2 or a.stride(1) != 1 or a.is_cuda:
+            raise ValueError("host grid must be a 2-D CPU array with unit column stride")
+        return a
+    t = desc(t)
+    if env0 is not None:
+        env0 = desc(env0)
+        if env0.shape != t.shape or env0.stride(0) != t.stride(0):
+            raise ValueError("env0 must have the grid's shape and pitch")
     return make_grid(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), _dtype_code(t), bc,
                      env0.data_ptr() if env0 is not None else None, tuple(param))
 
@@ -79,6 +100,13 @@ class Context:
         g = grid_from_tensor(grid_t, bc, env0, param)
         job = lsr_run(self.handle, g, stencil_id, reduce_op, cond, max_iter)
         self._keep[job] = (grid_t, env0)  # the caller's buffers stay alive until the result
+        return job
+
+    def submit_host(self, grid, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+        """Starts a job on host buffers (lsr_run_host); grid receives the result."""
+        g = grid_from_host(grid, bc, env0, param)
+        job = lsr_run_host(self.handle, g, stencil_id, reduce_op, cond, max_iter)
+        self._keep[job] = (grid, env0)
         return job
 
     def result(self, job, wait=True):

@@ -74,6 +74,8 @@ _SIGS = {
     "lsr_tune_import": (C.c_int, [C.c_void_p, C.c_char_p]),
     "lsr_run": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_int32, C.c_int32,
                           C.POINTER(lsr_cond), C.c_int64, C.POINTER(C.c_int64)]),
+    "lsr_run_host": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_int32, C.c_int32,
+                               C.POINTER(lsr_cond), C.c_int64, C.POINTER(C.c_int64)]),
     "lsr_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(lsr_job_result)]),
     "lsr_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "lsr_amf_detect": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_void_p, C.c_void_p,
@@ -141,6 +143,15 @@ def lsr_run(ctx: int, grid: lsr_grid, stencil_id: int, reduce_op: int, cond: lsr
     job = C.c_int64()
     _check(lib().lsr_run(ctx, C.byref(grid), stencil_id, reduce_op, C.byref(cond), max_iter,
                          C.byref(job)))
+    return job.value
+
+
+def lsr_run_host(ctx: int, grid: lsr_grid, stencil_id: int, reduce_op: int, cond: lsr_cond,
+                 max_iter: int) -> int:
+    """lsr_run with grid->data and grid->env0 in host memory."""
+    job = C.c_int64()
+    _check(lib().lsr_run_host(ctx, C.byref(grid), stencil_id, reduce_op, C.byref(cond), max_iter,
+                              C.byref(job)))
     return job.value
 
 

@@ -39,6 +39,7 @@ constexpr int kWindowsInFlight = 2;
 
 lsr_status lsr_ctx::engine_setup() {
     HIP_TRY(hipStreamCreateWithFlags(&small_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&d_jobs, sizeof(lsr::BatchJob) * kMaxBatch));
     HIP_TRY(hipMalloc(&d_work, sizeof(lsr::WorkItem) * (kMaxWork + kPad)));
     for (int i = 0; i < 2; ++i) {
@@ -58,6 +59,11 @@ void lsr_ctx::engine_teardown() {
         (void)hipStreamDestroy(small_stream);
         small_stream = nullptr;
     }
+    if (copy_stream) {
+        (void)hipStreamSynchronize(copy_stream);
+        (void)hipStreamDestroy(copy_stream);
+        copy_stream = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
         if (h_jobs[i]) (void)hipHostFree(h_jobs[i]);
@@ -74,9 +80,10 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     const bool life = j->stencil == LSR_ST_LIFE;
     const bool f32 = g.dtype == LSR_F32;
     j->xgrid = g;
-    // small grids are swept in LDS from any pitch or alignment: never staged
-    j->staged = !lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
-                needs_staging(g, j->stencil);
+    // small grids are swept in LDS from any pitch or alignment: staged only when
+    // they live in host memory
+    j->staged = j->host || (!lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
+                            needs_staging(g, j->stencil));
     if (j->staged) j->xgrid.pitch = stage_pitch(g);   // buffers assigned at admission
     lsr::BatchJob& d = j->desc;
     d = lsr::BatchJob{};
@@ -138,12 +145,21 @@ void lsr_ctx::engine_finish(Job* j, lsr_status st) {
     cv_done.notify_all();
 }
 
+// Admission in arrival order while the pool can hold a job's device memory: the
+// partner, partials and state, plus the staged copies of its grid and env (a
+// host job's grids therefore count against the budget like its scratch). A device
+// job is activated at once; a host job first has its H2D copies enqueued on the
+// copy stream, behind everything already enqueued on the execution stream (its
+// blocks may have been released by jobs retired while earlier windows still ran),
+// and is activated by engine_poll_ingest once they have completed.
 lsr_status lsr_ctx::engine_admit() {
     while (true) {
         Job* j = nullptr;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (pending.empty() || (int)active.size() >= kMaxBatch || free_slots.empty()) return LSR_OK;
+            if (pending.empty() || (int)(active.size() + ingesting.size()) >= kMaxBatch ||
+                free_slots.empty())
+                return LSR_OK;
             j = pending.front();
         }
         if (j->cancel.load()) {
@@ -172,7 +188,8 @@ lsr_status lsr_ctx::engine_admit() {
             pool.release(st);
             pool.release(s0);
             pool.release(senv);
-            if (!active.empty() || !retiring.empty()) return LSR_OK;  // wait for memory
+            if (!active.empty() || !retiring.empty() || !ingesting.empty())
+                return LSR_OK;  // wait for memory
             {
                 std::lock_guard<std::mutex> lk(mu);
                 pending.pop_front();
@@ -189,7 +206,6 @@ lsr_status lsr_ctx::engine_admit() {
             free_slots.pop_back();
             j->phase = Phase::Running;
         }
-        active.push_back(j);  // from here on a device failure also finishes this job
         work_items += j->desc.tiles;
         j->buf[1] = partner;
         j->partials = parts;
@@ -212,47 +228,120 @@ lsr_status lsr_ctx::engine_admit() {
         d.st = j->st;
         d.partials = parts;
         d.mirror = j->mirror_dev;
+        if (!j->host) {
+            active.push_back(j);  // from here on a device failure also finishes this job
+            HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
+            HIP_TRY(hipEventRecord(j->ev_begin, stream));
+            lsr_status a = engine_activate(j);
+            if (a != LSR_OK) return a;
+            continue;
+        }
+        ingesting.push_back(j);
         const lsr_grid& g = j->xgrid;
         const lsr_grid& ug = j->grid;
         const size_t esz = dtype_size(g.dtype);
-        HIP_TRY(hipStreamWaitEvent(stream, j->ev_user, 0));
-        HIP_TRY(hipEventRecord(j->ev_begin, stream));
-        if (j->staged) {
-            if (j->stencil == LSR_ST_LIFE) {   // padding cells start (and stay) 0/1
-                HIP_TRY(hipMemsetAsync(s0, 0, (size_t)g.rows * g.pitch * esz, stream));
-                HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, stream));
-            }
-            HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
-                                     g.rows, hipMemcpyDeviceToDevice, stream));
-            if (senv)
-                HIP_TRY(hipMemcpy2DAsync(senv, g.pitch * esz, ug.env0, ug.pitch * esz, g.cols * esz,
-                                         g.rows, hipMemcpyDeviceToDevice, stream));
+        hipEvent_t behind = get_event();
+        if (!behind) return fail(LSR_EDEVICE, "event pool");
+        HIP_TRY(hipEventRecord(behind, stream));
+        HIP_TRY(hipStreamWaitEvent(copy_stream, behind, 0));
+        put_event(behind);
+        HIP_TRY(hipStreamWaitEvent(copy_stream, j->ev_user, 0));
+        HIP_TRY(hipEventRecord(j->ev_begin, copy_stream));
+        if (j->stencil == LSR_ST_LIFE) {   // padding cells start (and stay) 0
+            HIP_TRY(hipMemsetAsync(s0, 0, (size_t)g.rows * g.pitch * esz, copy_stream));
+            HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, copy_stream));
         }
-        if (j->stencil == LSR_ST_LIFE) {
-            int np = 0;
-            HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
-                                         parts, &np, stream));
-            HIP_TRY(lsr::launch_init_state(j->st, parts, np, stream));
-        } else {
-            HIP_TRY(hipMemcpy2DAsync(partner, g.pitch * esz, g.data, g.pitch * esz, g.cols * esz,
-                                     g.rows, hipMemcpyDeviceToDevice, stream));
-            HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream));
-        }
-        if (lsr::batch_is_small(j->desc)) {
-            // the whole loop in one workgroup on the second stream, after the init
-            hipEvent_t ready = get_event();
-            if (!ready) return fail(LSR_EDEVICE, "event pool");
-            HIP_TRY(hipEventRecord(ready, stream));
-            HIP_TRY(hipStreamWaitEvent(small_stream, ready, 0));
-            put_event(ready);
-            HIP_TRY(lsr::launch_batch_small(j->desc, small_stream));
-            j->ev_small = get_event();
-            if (!j->ev_small) return fail(LSR_EDEVICE, "event pool");
-            HIP_TRY(hipEventRecord(j->ev_small, small_stream));
-        }
+        HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz, g.rows,
+                                 hipMemcpyHostToDevice, copy_stream));
+        if (senv)
+            HIP_TRY(hipMemcpy2DAsync(senv, g.pitch * esz, ug.env0, ug.pitch * esz, g.cols * esz,
+                                     g.rows, hipMemcpyHostToDevice, copy_stream));
+        j->ev_in = get_event();
+        if (!j->ev_in) return fail(LSR_EDEVICE, "event pool");
+        HIP_TRY(hipEventRecord(j->ev_in, copy_stream));
         j->t_admit = Clock::now();
-        tables_dirty = true;
     }
+}
+
+// Host jobs whose H2D copies have completed join the device tables. With block,
+// waits for the oldest one when none is ready (nothing else to do).
+lsr_status lsr_ctx::engine_poll_ingest(bool block) {
+    if (ingesting.empty()) return LSR_OK;
+    std::vector<Job*> keep;
+    keep.reserve(ingesting.size());
+    for (size_t k = 0; k < ingesting.size(); ++k) {
+        Job* j = ingesting[k];
+        hipError_t e = (block && k == 0) ? hipEventSynchronize(j->ev_in) : hipEventQuery(j->ev_in);
+        if (e == hipErrorNotReady) {
+            keep.push_back(j);
+            continue;
+        }
+        if (e != hipSuccess) {
+            // the failure path finishes this job (now active) and the rest
+            for (size_t r = k + 1; r < ingesting.size(); ++r) keep.push_back(ingesting[r]);
+            ingesting.swap(keep);
+            active.push_back(j);
+            return fail(LSR_EDEVICE, "H2D copy: %s", hipGetErrorString(e));
+        }
+        active.push_back(j);
+        HIP_TRY(hipStreamWaitEvent(stream, j->ev_in, 0));
+        put_event(j->ev_in);
+        j->ev_in = nullptr;
+        lsr_status a = engine_activate(j);
+        if (a != LSR_OK) {
+            for (size_t r = k + 1; r < ingesting.size(); ++r) keep.push_back(ingesting[r]);
+            ingesting.swap(keep);
+            return a;
+        }
+    }
+    ingesting.swap(keep);
+    return LSR_OK;
+}
+
+// Enqueues an admitted job's initialisation on the execution stream (a device
+// job's staging copies, the partner copy or the initial live count, the state),
+// and launches a small job's whole loop on the second stream.
+lsr_status lsr_ctx::engine_activate(Job* j) {
+    const lsr_grid& g = j->xgrid;
+    const lsr_grid& ug = j->grid;
+    const size_t esz = dtype_size(g.dtype);
+    void* partner = j->buf[1];
+    if (j->staged && !j->host) {
+        if (j->stencil == LSR_ST_LIFE) {   // padding cells start (and stay) 0/1
+            HIP_TRY(hipMemsetAsync(j->buf[0], 0, (size_t)g.rows * g.pitch * esz, stream));
+            HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, stream));
+        }
+        HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+        if (j->stage_env)
+            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * esz, ug.env0, ug.pitch * esz,
+                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream));
+    }
+    if (j->stencil == LSR_ST_LIFE) {
+        int np = 0;
+        HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
+                                     j->partials, &np, stream));
+        HIP_TRY(lsr::launch_init_state(j->st, j->partials, np, stream));
+    } else {
+        HIP_TRY(hipMemcpy2DAsync(partner, g.pitch * esz, g.data, g.pitch * esz, g.cols * esz,
+                                 g.rows, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(lsr::launch_init_state(j->st, nullptr, 0, stream));
+    }
+    if (lsr::batch_is_small(j->desc)) {
+        // the whole loop in one workgroup on the second stream, after the init
+        hipEvent_t ready = get_event();
+        if (!ready) return fail(LSR_EDEVICE, "event pool");
+        HIP_TRY(hipEventRecord(ready, stream));
+        HIP_TRY(hipStreamWaitEvent(small_stream, ready, 0));
+        put_event(ready);
+        HIP_TRY(lsr::launch_batch_small(j->desc, small_stream));
+        j->ev_small = get_event();
+        if (!j->ev_small) return fail(LSR_EDEVICE, "event pool");
+        HIP_TRY(hipEventRecord(j->ev_small, small_stream));
+    }
+    if (!j->host) j->t_admit = Clock::now();
+    tables_dirty = true;
+    return LSR_OK;
 }
 
 lsr_status lsr_ctx::engine_upload() {
@@ -322,17 +411,30 @@ void lsr_ctx::engine_scan() {
         const lsr_grid& ug = j->grid;
         const size_t esz = dtype_size(g.dtype);
         // a stop inside a fused round is replayed first; then the buffer holding
-        // sweep n goes back to the caller's grid
+        // sweep n goes back to the caller's grid (a host job's by a D2H copy on
+        // the copy stream, after the execution stream's work so far)
         int last = 0;
         hipError_t e = finish_fused(j, fin, j->desc.step, j->desc.ctl, &last, stream) == LSR_OK
                            ? hipSuccess : hipErrorLaunchFailure;
-        if (e == hipSuccess && j->staged)
-            e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
-                                 g.rows, hipMemcpyDeviceToDevice, stream);
-        else if (e == hipSuccess && last)
-            e = hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
-                                 g.rows, hipMemcpyDeviceToDevice, stream);
-        if (e == hipSuccess) e = hipEventRecord(j->ev_end, stream);
+        if (e == hipSuccess && j->host) {
+            hipEvent_t done_ev = get_event();
+            if (!done_ev) e = hipErrorOutOfMemory;
+            if (e == hipSuccess) e = hipEventRecord(done_ev, stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(copy_stream, done_ev, 0);
+            if (done_ev) put_event(done_ev);
+            if (e == hipSuccess)
+                e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz,
+                                     g.cols * esz, g.rows, hipMemcpyDeviceToHost, copy_stream);
+            if (e == hipSuccess) e = hipEventRecord(j->ev_end, copy_stream);
+        } else {
+            if (e == hipSuccess && j->staged)
+                e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz,
+                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream);
+            else if (e == hipSuccess && last)
+                e = hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz,
+                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream);
+            if (e == hipSuccess) e = hipEventRecord(j->ev_end, stream);
+        }
         lsr_job_result& r = j->result;
         r.iterations = fin.n;
         r.last_reduce = fin.r;
@@ -347,7 +449,8 @@ void lsr_ctx::engine_scan() {
             j->error = hipGetErrorString(e);
             r.status = LSR_EDEVICE;
         }
-        j->release_scratch(pool);
+        // a host job's blocks are read by its D2H copy: released once that is done
+        if (!j->host) j->release_scratch(pool);
         {
             std::lock_guard<std::mutex> lk(mu);
             free_slots.push_back(j->slot);
@@ -369,6 +472,7 @@ void lsr_ctx::engine_poll_retiring(bool block) {
             continue;
         }
         j->t_done = Clock::now();
+        if (j->host) j->release_scratch(pool);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, j->ev_begin, j->ev_end);
         j->result.device_ms = ms;
@@ -390,7 +494,8 @@ void lsr_ctx::serve() {
     while (true) {
         {
             std::unique_lock<std::mutex> lk(mu);
-            const bool idle = pending.empty() && active.empty() && retiring.empty() && inflight.empty();
+            const bool idle = pending.empty() && active.empty() && retiring.empty() &&
+                              inflight.empty() && ingesting.empty();
             if (idle) {
                 if (stopping) break;
                 cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
@@ -398,6 +503,9 @@ void lsr_ctx::serve() {
             }
         }
         lsr_status s = engine_admit();
+        // host jobs whose copies are in: wait for one only when nothing else can run
+        if (s == LSR_OK)
+            s = engine_poll_ingest(active.empty() && inflight.empty() && retiring.empty());
         for (Job* j : active) {
             if (j->cancel.load() && !j->cancel_posted) {
                 j->cancel_posted = true;
@@ -443,8 +551,11 @@ void lsr_ctx::serve() {
             // a device failure ends every job of the context
             fatal = g_last_error;
             (void)hipStreamSynchronize(stream);
+            (void)hipStreamSynchronize(copy_stream);
             std::vector<Job*> all(active.begin(), active.end());
             all.insert(all.end(), retiring.begin(), retiring.end());
+            all.insert(all.end(), ingesting.begin(), ingesting.end());
+            ingesting.clear();
             {
                 std::lock_guard<std::mutex> lk(mu);
                 all.insert(all.end(), pending.begin(), pending.end());

@@ -272,10 +272,10 @@ lsr_status lsr_ctx::run_job(Job* j) {
             HIP_TRY(hipMemsetAsync(j->buf[1], 0, (size_t)g.rows * g.pitch * esz, stream));
         }
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
-                                 g.rows, hipMemcpyDeviceToDevice, stream));
+                                 g.rows, stage_kind(j, true), stream));
         if (j->stage_env)
             HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * esz, ug.env0, ug.pitch * esz,
-                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream));
+                                     g.cols * esz, g.rows, stage_kind(j, true), stream));
     }
     // Partner buffer starts as a copy: boundary ring (Jacobi) and unflagged
     // pixels (restoration) are never rewritten, so both buffers must hold them.
@@ -363,7 +363,7 @@ lsr_status lsr_ctx::run_job(Job* j) {
     if (rs != LSR_OK) return rs;
     if (j->staged)
         HIP_TRY(hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz, g.cols * esz,
-                                 g.rows, hipMemcpyDeviceToDevice, stream));
+                                 g.rows, stage_kind(j, false), stream));
     else if (last)
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, j->buf[1], g.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream));
@@ -484,11 +484,26 @@ lsr_status lsr_set_tuning(lsr_ctx* ctx, const lsr_tuning* t) {
 
 lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
                    const lsr_cond* cond, int64_t max_iter, lsr_job* job_out) {
+    return submit(ctx, grid, stencil_id, reduce_op, cond, max_iter, false, job_out);
+}
+
+lsr_status lsr_run_host(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
+                        const lsr_cond* cond, int64_t max_iter, lsr_job* job_out) {
+    return submit(ctx, grid, stencil_id, reduce_op, cond, max_iter, true, job_out);
+}
+
+}  // extern "C"
+
+lsr_status lsr_rt::submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
+                          const lsr_cond* cond, int64_t max_iter, bool host, lsr_job* job_out) {
     if (!ctx || !job_out) return fail(LSR_EINVAL, "ctx and job_out must not be NULL");
     lsr_status v = validate(grid, stencil_id, reduce_op, cond, max_iter);
     if (v != LSR_OK) return v;
+    if (host && stencil_id == LSR_ST_RESTORE)
+        return fail(LSR_EINVAL, "restoration jobs take device pointers (lsr_run)");
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<Job> j(new Job());
+    j->host = host;
     j->grid = *grid;
     j->xgrid = *grid;
     j->stencil = stencil_id;
@@ -527,8 +542,6 @@ lsr_status lsr_run(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32
     }
     return submit_plain(ctx, std::move(j), grid, stencil_id, reduce_op, cond, max_iter, tun, job_out);
 }
-
-}  // extern "C"
 
 // The plain (one job at a time) path of lsr_run with the launch settings resolved.
 lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int* nparts_out) {
@@ -623,7 +636,7 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
         ctx->free_slots.push_back(j->slot);
     };
     const size_t esz = dtype_size(grid->dtype);
-    j->staged = needs_staging(*grid, stencil_id);
+    j->staged = j->host || needs_staging(*grid, stencil_id);
     if (j->staged) j->xgrid.pitch = stage_pitch(*grid);
     const size_t bytes = (size_t)grid->rows * (size_t)j->xgrid.pitch * esz;
     // geometry needs both buffers' alignment; the pool returns 256-byte aligned blocks

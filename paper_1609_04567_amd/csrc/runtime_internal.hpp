@@ -180,6 +180,12 @@ struct Job {
     // it takes the vector / SWAR kernels; the result is copied back into the
     // caller's grid.
     bool staged = false;
+    // A host-resident job (lsr_run_host): grid and env are host memory. It always
+    // runs staged: the device copies come from the pool (under the HBM budget),
+    // are filled by H2D copies when the job is admitted and the last iterate goes
+    // back by a D2H copy when it retires.
+    bool host = false;
+    hipEvent_t ev_in = nullptr;         // batched engine: end of a host job's H2D copies
     void* stage_env = nullptr;
     void* partials = nullptr;
     lsr::JobState* st = nullptr;
@@ -268,6 +274,7 @@ struct lsr_ctx {
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;    // internal execution stream
     hipStream_t small_stream = nullptr;  // batched engine: whole-grid-in-LDS jobs
+    hipStream_t copy_stream = nullptr;   // batched engine: H2D/D2H copies of host jobs
     hipStream_t capture = nullptr;   // stream used only for graph capture
     lsr_rt::Pool pool;
     lsr_tuning tuning{};
@@ -296,6 +303,7 @@ struct lsr_ctx {
     // Batched engine (LSR_FLAG_BATCHED), see engine.cpp.
     bool batched = false;
     std::deque<lsr_rt::Job*> pending;   // submitted, waiting for admission (arrival order)
+    std::vector<lsr_rt::Job*> ingesting; // host jobs admitted, H2D copies in flight
     std::vector<lsr_rt::Job*> active;   // admitted, in the device tables
     std::vector<lsr_rt::Job*> retiring; // stopped, waiting for their end event
     lsr::BatchJob* d_jobs = nullptr;
@@ -312,6 +320,8 @@ struct lsr_ctx {
     void serve();
     lsr_status engine_submit(lsr_rt::Job* j);
     lsr_status engine_admit();
+    lsr_status engine_activate(lsr_rt::Job* j);
+    lsr_status engine_poll_ingest(bool block);
     lsr_status engine_upload();
     lsr_status engine_window();
     void engine_scan();
@@ -339,5 +349,13 @@ lsr_status finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::Loop
 lsr_status submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
                         int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
                         int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out);
+// lsr_run and lsr_run_host: validation, then the plain or the batched submission.
+lsr_status submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
+                  const lsr_cond* cond, int64_t max_iter, bool host, lsr_job* job_out);
+// Copy direction of a staged job's copy into (in = true) or out of its device grid.
+inline hipMemcpyKind stage_kind(const Job* j, bool in) {
+    if (!j->host) return hipMemcpyDeviceToDevice;
+    return in ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+}
 }  // namespace lsr_rt
 

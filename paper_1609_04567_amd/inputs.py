@@ -77,17 +77,33 @@ def uniform01_at(seed: int, index: np.ndarray) -> np.ndarray:
     return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
+def _ring_index(rows: int, cols: int):
+    """Raster indices of the ring cells and their (row, col) positions."""
+    top = np.arange(cols, dtype=np.int64)
+    bot = (rows - 1) * cols + top
+    mid = np.arange(1, rows - 1, dtype=np.int64) * cols
+    idx = np.concatenate([top, bot, mid, mid + (cols - 1)])
+    return idx, idx // cols, idx % cols
+
+
+def laplace_fill(out: np.ndarray, seed: int = 1) -> np.ndarray:
+    """Writes the Laplace recipe into a 2-D array of any float dtype (values are
+    computed in FP64, then stored): ring cell (i, j) takes draw i*cols + j of the
+    stream, every other cell 0."""
+    rows, cols = out.shape
+    out[...] = 0
+    idx, r, c = _ring_index(rows, cols)
+    out[r, c] = uniform01_at(seed, idx)
+    return out
+
+
 def laplace_input(rows: int, cols: int | None = None, seed: int = 1) -> np.ndarray:
     """FP64 grid; ring cells take draw (i*cols + j) of the stream, interior cells are 0.
 
     The side includes the ring, so only (rows-2) x (cols-2) cells are updated.
     """
     cols = rows if cols is None else cols
-    u = np.zeros((rows, cols), dtype=np.float64)
-    idx = np.arange(rows * cols, dtype=np.int64).reshape(rows, cols)
-    for sl in ((0, slice(None)), (rows - 1, slice(None)), (slice(None), 0), (slice(None), cols - 1)):
-        u[sl] = uniform01_at(seed, idx[sl])
-    return u
+    return laplace_fill(np.empty((rows, cols), dtype=np.float64), seed)
 
 
 def harmonic_input(rows: int, cols: int, kind: str) -> np.ndarray:
@@ -116,13 +132,18 @@ class HelmholtzInput:
     h: float
 
 
-def helmholtz_input(n: int, alpha: float = 1.0) -> HelmholtzInput:
-    """N x N lattice including the ring, x_i = i/(N-1), h = 1/(N-1)."""
+def _helm_factor(n: int):
     h = 1.0 / (n - 1)
     x = np.arange(n, dtype=np.float64) * h
     s = np.sin(np.pi * x)
     s[0] = 0.0
     s[-1] = 0.0
+    return s, h
+
+
+def helmholtz_input(n: int, alpha: float = 1.0) -> HelmholtzInput:
+    """N x N lattice including the ring, x_i = i/(N-1), h = 1/(N-1)."""
+    s, h = _helm_factor(n)
     ustar = np.ascontiguousarray(np.outer(s, s))
     f = (2.0 * np.pi * np.pi + alpha) * ustar
     g = np.ascontiguousarray((h * h) * f)
@@ -130,17 +151,69 @@ def helmholtz_input(n: int, alpha: float = 1.0) -> HelmholtzInput:
     return HelmholtzInput(u0=u0, g=g, ustar=ustar, s=s, alpha=float(alpha), h=float(h))
 
 
+def helmholtz_fill(u0: np.ndarray, g: np.ndarray, alpha: float = 1.0) -> float:
+    """Writes the Helmholtz recipe into two N x N arrays of any float dtype: u0 = 0
+    and g = h^2 f, evaluated per element in FP64 exactly as helmholtz_input does
+    (a block of rows at a time), then stored. Returns h."""
+    n = u0.shape[0]
+    s, h = _helm_factor(n)
+    u0[...] = 0
+    c = 2.0 * np.pi * np.pi + alpha
+    hh = h * h
+    step = max(1, (1 << 16) // n)
+    for r0 in range(0, n, step):
+        r1 = min(n, r0 + step)
+        blk = np.outer(s[r0:r1], s)
+        np.multiply(c, blk, out=blk)
+        np.multiply(hh, blk, out=blk)
+        g[r0:r1] = blk
+    return h
+
+
 # ---------------------------------------------------------------------------
 # Game of Life soup.
 # ---------------------------------------------------------------------------
+def life_fill(out: np.ndarray, seed: int = 3, density: float = 0.3) -> np.ndarray:
+    """Writes the Life soup into a 2-D uint8 array: cell (i, j) is 1 iff draw
+    i*cols + j, as a double in [0, 1), is below the density.
+
+    The test (x >> 11) * 2**-53 < d is evaluated on the integer draw: the scaling
+    by a power of two is exact, so it holds iff (x >> 11) < ceil(d * 2**53), i.e.
+    iff x < ceil(d * 2**53) * 2**11."""
+    rows, cols = out.shape
+    if not out.flags.c_contiguous or out.dtype != np.uint8:
+        raise ValueError("life_fill writes a C-contiguous uint8 array")
+    flat = out.reshape(-1)
+    if density >= 1.0 or density <= 0.0:
+        flat[...] = 1 if density >= 1.0 else 0
+        return out
+    lim = np.uint64(math.ceil(density * 2.0 ** 53) << 11)
+    s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+    blk = 1 << 16
+    z = np.empty(blk, dtype=np.uint64)
+    t = np.empty(blk, dtype=np.uint64)
+    total = rows * cols
+    with np.errstate(over="ignore"):
+        for lo in range(0, total, blk):
+            m = min(blk, total - lo)
+            zz, tt = z[:m], t[:m]
+            zz[...] = np.arange(lo + 1, lo + m + 1, dtype=np.uint64)
+            np.multiply(zz, GAMMA, out=zz)
+            np.add(zz, s, out=zz)
+            for sh, mul in ((30, _M1), (27, _M2)):
+                np.right_shift(zz, np.uint64(sh), out=tt)
+                np.bitwise_xor(zz, tt, out=zz)
+                np.multiply(zz, mul, out=zz)
+            np.right_shift(zz, np.uint64(31), out=tt)
+            np.bitwise_xor(zz, tt, out=zz)
+            np.less(zz, lim, out=flat[lo:lo + m].view(np.bool_))
+    return out
+
+
 def life_input(rows: int, cols: int | None = None, seed: int = 3, density: float = 0.3) -> np.ndarray:
     """uint8 grid, cell (i, j) alive (1) iff draw i*cols + j is below the density."""
     cols = rows if cols is None else cols
-    out = np.empty(rows * cols, dtype=np.uint8)
-    for lo in range(0, rows * cols, _CHUNK):
-        hi = min(rows * cols, lo + _CHUNK)
-        out[lo:hi] = (uniform01(seed, lo, hi - lo) < density).astype(np.uint8)
-    return out.reshape(rows, cols)
+    return life_fill(np.empty((rows, cols), dtype=np.uint8), seed, density)
 
 
 def life_pattern(rows: int, cols: int, cells) -> np.ndarray:

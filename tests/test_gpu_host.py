@@ -1,0 +1,182 @@
+"""GPU tests of host-resident jobs (lsr_run_host): the grid and env are host
+buffers; the context allocates the device copies from its pool, copies them in,
+runs the loop and copies the last iterate back.
+
+Each host job's result is compared with the oracle (FP64 and Life bit-exact,
+iteration counts exact) and with the same job run on device buffers (FP32
+bit-identical); under an HBM budget that holds a few jobs at a time, a batched
+context admits host jobs as memory frees up and every result is still exact; a
+job whose device copies can never fit ends with a memory status.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1609_04567_amd as L
+from paper_1609_04567_amd import inputs as I
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(a, pinned):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.pin_memory() if pinned else t.clone()
+
+
+def _spec(kind, side, seed, f32, mi):
+    """(grid array, env array or None, kwargs, oracle closure)."""
+    dt = np.float32 if f32 else np.float64
+    if kind == "laplace":
+        a = I.laplace_input(side, seed=seed)
+        kw = dict(stencil_id=L.LSR_ST_LAPLACE5, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), max_iter=mi, bc=L.LSR_BC_RING)
+        return a.astype(dt), None, kw, lambda: O.jacobi_run(a, thr=1e-6, max_iter=mi)
+    if kind == "helmholtz":
+        h = I.helmholtz_input(side)
+        kw = dict(stencil_id=L.LSR_ST_HELMHOLTZ5, reduce_op=L.LSR_RED_L2_DELTA,
+                  cond=L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), max_iter=mi, bc=L.LSR_BC_RING,
+                  param=(h.alpha, h.h))
+        ora = lambda: O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                                   reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10, max_iter=mi)
+        return h.u0.astype(dt), h.g.astype(dt), kw, ora
+    torus = kind == "life"
+    s = I.life_input(side, seed=seed)
+    kw = dict(stencil_id=L.LSR_ST_LIFE, reduce_op=L.LSR_RED_SUM,
+              cond=L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10), max_iter=mi,
+              bc=L.LSR_BC_TORUS if torus else L.LSR_BC_BOTTOM)
+    return s, None, kw, lambda: O.life_run(s, bc=O.BC_TORUS if torus else O.BC_BOTTOM,
+                                           stable_window=10, max_iter=mi)
+
+
+def _submit_host(ctx, grid, env, kw):
+    return ctx.submit_host(grid, kw["stencil_id"], kw["reduce_op"], kw["cond"], kw["max_iter"],
+                           kw["bc"], env0=env, param=kw.get("param", ()))
+
+
+def _run_device(ctx, a, env, kw):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    e = torch.from_numpy(env).to("cuda:0") if env is not None else None
+    r = ctx.run(t, kw["stencil_id"], kw["reduce_op"], kw["cond"], kw["max_iter"], kw["bc"],
+                env0=e, param=kw.get("param", ()))
+    torch.cuda.synchronize()
+    return t.cpu().numpy(), r
+
+
+def _check(kind, f32, x, r, ora, dev=None):
+    o, ro = ora()
+    assert r.status == L.LSR_OK, (kind, r.status)
+    assert r.iterations == ro.n, (kind, r.iterations, ro.n)
+    if kind.startswith("life"):
+        assert np.array_equal(x, o) and r.last_count == ro.count
+    elif f32:
+        assert np.array_equal(x, dev[0]) and r.iterations == dev[1].iterations
+        den = np.max(np.abs(o))
+        assert np.max(np.abs(x.astype(np.float64) - o)) <= 1e-5 * den
+    else:
+        assert np.array_equal(x, o)
+        assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
+
+
+CASES = [("laplace", 129, 1, False, 500), ("laplace", 200, 2, True, 400),
+         ("helmholtz", 257, 0, False, 300), ("helmholtz", 130, 0, True, 400),
+         ("life", 128, 3, False, 600), ("life_dead", 77, 4, False, 300),
+         ("laplace", 61, 5, False, 700), ("life", 100, 6, False, 400)]
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_plain_context_host_jobs_match_oracle(ctx, pinned):
+    say(f"plain host jobs pinned={pinned}")
+    for kind, side, seed, f32, mi in CASES:
+        a, env, kw, ora = _spec(kind, side, seed, f32, mi)
+        g = _host(a, pinned)
+        e = _host(env, pinned) if env is not None else None
+        r = ctx.result(_submit_host(ctx, g, e, kw))
+        dev = _run_device(ctx, a, env, kw) if f32 else None
+        _check(kind, f32, g.numpy(), r, ora, dev)
+
+
+def test_batched_host_jobs_mixed_with_device_jobs():
+    import torch
+    say("batched host + device jobs")
+    with L.Context(0, batched=True) as b:
+        pend = []
+        for k, (kind, side, seed, f32, mi) in enumerate(CASES * 2):
+            a, env, kw, ora = _spec(kind, side, seed + 10 * (k // len(CASES)), f32, mi)
+            if k % 3 == 2:   # every third job on device buffers
+                t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+                e = torch.from_numpy(env).to("cuda:0") if env is not None else None
+                jid = b.submit(t, kw["stencil_id"], kw["reduce_op"], kw["cond"], kw["max_iter"],
+                               kw["bc"], env0=e, param=kw.get("param", ()))
+            else:
+                t = _host(a, True)
+                e = _host(env, True) if env is not None else None
+                jid = _submit_host(b, t, e, kw)
+            pend.append((kind, f32, a, env, kw, ora, t, jid))
+        for kind, f32, a, env, kw, ora, t, jid in pend:
+            r = b.result(jid)
+            torch.cuda.synchronize()
+            x = t.cpu().numpy()
+            dev = _run_device_plain(a, env, kw) if f32 else None
+            _check(kind, f32, x, r, ora, dev)
+            assert r.latency_ms >= r.queue_ms >= 0.0
+
+
+def _run_device_plain(a, env, kw):
+    with L.Context(0) as c:
+        return _run_device(c, a, env, kw)
+
+
+def test_batched_host_jobs_wait_for_hbm_budget():
+    """A budget that holds only a few of these jobs' device copies at a time: the
+    engine admits them in arrival order as retirements free memory."""
+    import torch
+    say("batched host jobs under a small budget")
+    side = 512
+    per_job = 4 * side * side * 4 + (1 << 20)   # grid, partner, env, staged env, state
+    jobs = []
+    with L.Context(0, batched=True, hbm_budget_bytes=3 * per_job) as b:
+        for k in range(10):
+            kind = ("laplace", "helmholtz", "life")[k % 3]
+            a, env, kw, ora = _spec(kind, side, 20 + k, True, 60 + 10 * k)
+            t = _host(a, True)
+            e = _host(env, True) if env is not None else None
+            jobs.append((kind, a, env, kw, ora, t, _submit_host(b, t, e, kw)))
+        for kind, a, env, kw, ora, t, jid in jobs:
+            r = b.result(jid)
+            assert r.status == L.LSR_OK
+            x = t.numpy()
+            if kind == "life":
+                o, ro = ora()
+                assert np.array_equal(x, o) and r.iterations == ro.n
+            else:
+                dev = _run_device_plain(a, env, kw)
+                assert np.array_equal(x, dev[0]) and r.iterations == dev[1].iterations
+        torch.cuda.synchronize()
+
+
+def test_host_job_larger_than_budget_fails_cleanly():
+    say("host job over budget")
+    a, env, kw, _ = _spec("laplace", 1024, 1, False, 10)
+    with L.Context(0, batched=True, hbm_budget_bytes=1 << 20) as b:
+        jid = _submit_host(b, _host(a, True), None, kw)
+        with pytest.raises(L.LsrError) as ei:
+            b.result(jid)
+        assert ei.value.status in (L.LSR_EBUSY, L.LSR_ENOMEM)
+    with L.Context(0, hbm_budget_bytes=1 << 20) as c:
+        with pytest.raises(L.LsrError) as ei:
+            _submit_host(c, _host(a, True), None, kw)
+        assert ei.value.status in (L.LSR_EBUSY, L.LSR_ENOMEM)
+
+
+def test_host_restore_is_rejected(ctx):
+    say("host restore rejected")
+    u = np.zeros((8, 8))
+    m = np.zeros((8, 8), dtype=np.uint8)
+    with pytest.raises(L.LsrError) as ei:
+        ctx.submit_host(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA,
+                        L.make_cond(L.LSR_COND_BELOW, 0.1, 1), 10, L.LSR_BC_BOTTOM, env0=m,
+                        param=(100.0, 0.0))
+    assert ei.value.status == L.LSR_EINVAL

@@ -68,3 +68,30 @@ def test_job_stream_mix():
     # log-uniform: the median side is near sqrt(128*4096) = 724
     assert 600 < np.median(sides) < 870
     assert I.job_stream(5)[3].seed == jobs[3].seed
+
+
+def test_fill_forms_match_the_draw_definitions():
+    """The buffer-filling generators (used to build jobs at their arrival) give the
+    bytes of the draw-by-draw definitions: ring draw i*cols + j for Laplace, the
+    double draw against the density for Life, the FP64 product for Helmholtz."""
+    for rows, cols, seed in ((3, 3, 1), (5, 17, 2), (64, 40, 1), (257, 129, 99)):
+        u = I.uniform01(seed, 0, rows * cols).reshape(rows, cols)
+        ref = np.zeros((rows, cols))
+        ref[0], ref[-1], ref[:, 0], ref[:, -1] = u[0], u[-1], u[:, 0], u[:, -1]
+        assert np.array_equal(I.laplace_input(rows, cols, seed), ref)
+        f32 = np.empty((rows, cols), np.float32)
+        assert np.array_equal(I.laplace_fill(f32, seed), ref.astype(np.float32))
+        for d in (0.3, 0.5, 0.01, 0.999, 1.0, 0.0):
+            assert np.array_equal(I.life_input(rows, cols, seed, d), (u < d).astype(np.uint8)), d
+    # the threshold test on the integer draw at the exact boundary of a draw
+    x = I.splitmix64(4, 0, 1)[0]
+    d = float((x >> np.uint64(11)) * 2.0 ** -53)
+    assert I.life_input(1, 1, 4, d)[0, 0] == 0 and I.life_input(1, 1, 4, np.nextafter(d, 1))[0, 0] == 1
+    for n in (3, 65, 300):
+        h = I.helmholtz_input(n)
+        u0, g = np.ones((n, n), np.float32), np.empty((n, n), np.float32)
+        assert I.helmholtz_fill(u0, g) == h.h
+        assert not u0.any() and np.array_equal(g, h.g.astype(np.float32))
+        g64 = np.empty((n, n))
+        I.helmholtz_fill(np.empty((n, n)), g64)
+        assert np.array_equal(g64, (h.h * h.h) * ((2 * np.pi ** 2 + 1.0) * np.outer(h.s, h.s)))
