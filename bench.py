@@ -151,11 +151,17 @@ def run_helmholtz(args, L, I, torch):
     # a launch reads u and g and writes u once, whatever number of sweeps it fuses
     kname = f"jacobi5_helmholtz_f64_{n}" if spl == 1 else f"jacobi5_tb{spl}_helmholtz_f64_{n}"
     out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
+    out["roofline"]["basis"] = (f"compulsory bytes of one launch of {spl} fused sweeps: 24 B per "
+                                "interior cell (u and g read once, u written once), over the "
+                                "launch's mean device time")
     out["copy_probe_gbs"] = copy_gbs
     if tuned:
         out["autotuned"] = tuned
     # bytes an unfused sweep would move per update, at the achieved update rate
     out["effective_gbs"] = round(value * 24.0, 1)
+    out["effective"] = {"gbs": round(value * 24.0, 1), "frac": round(value * 24.0 / PEAK_HBM_GBS, 4),
+                        "basis": "24 B per cell update (an unfused sweep's traffic) x the whole "
+                                 "job's update rate; above 1 because fused sweeps reuse data on chip"}
     out["accuracy"] = {"closed_form_max_rel_err": err, "iterations": int(results[-1].iterations),
                        "last_l2_update": results[-1].last_reduce}
     if spl > 1 and not args.no_plain:
@@ -183,6 +189,21 @@ def run_helmholtz(args, L, I, torch):
         out["cpu_baseline"] = {"value": round((n - 2) ** 2 * r.n / dt / 1e9, 4), "unit": "GLUP/s",
                                "cores": O.threads(), "kind": "oracle",
                                "sample": f"first {r.n} sweeps of the {n}x{n} job ({dt:.1f} s)"}
+        # the same oracle on one core, over a shorter prefix
+        cores = O.threads()
+        O.set_threads(1)
+        k1 = max(1, args.cpu_sweeps // 75)
+        t0 = time.perf_counter()
+        _, r1 = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                             reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10, max_iter=k1)
+        dt1 = time.perf_counter() - t0
+        O.set_threads(cores)
+        out["cpu_baseline_1core"] = {"value": round((n - 2) ** 2 * r1.n / dt1 / 1e9, 4),
+                                     "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+                                     "sample": f"first {r1.n} sweeps ({dt1:.1f} s)",
+                                     "all_core_speedup": round(out["cpu_baseline"]["value"] /
+                                                               ((n - 2) ** 2 * r1.n / dt1 / 1e9), 2),
+                                     "all_cores": cores}
     ctx.close()
     return out
 
@@ -217,11 +238,12 @@ def run_laplace(args, L, I, torch):
     out["roofline"]["note"] = "1 MiB working set: cache-resident and launch-bound; HBM % is context"
     if not args.no_cpu:
         import oracle as O
+        cores = O.threads()
         O.set_threads(1)
         t0 = time.perf_counter()
         o, ro = O.jacobi_run(a, thr=1e-6, max_iter=sweeps)
         dt = time.perf_counter() - t0
-        O.set_threads(0)
+        O.set_threads(cores)
         out["cpu_baseline"] = {"value": round((n - 2) ** 2 * ro.n / dt / 1e9, 4), "unit": "GLUP/s",
                                "cores": 1, "kind": "oracle", "sample": f"the whole job ({dt:.2f} s)"}
         out["accuracy"] = {"bit_identical_to_oracle": bool(np.array_equal(grids[-1].cpu().numpy(), o))}
@@ -273,6 +295,24 @@ def run_life(args, L, I, torch):
     # bytes an unfused generation would move per cell, at the achieved update rate
     out["effective_gbs"] = round(value * 2.0, 1)
     out["result"] = {"iterations": int(results[-1].iterations), "count": int(results[-1].last_count)}
+    golden = os.path.join(ROOT, "tests", "golden", f"life_{n}_torus_seed3.txt")
+    if gens == 2000 and os.path.exists(golden):
+        # the oracle's full run of this workload (stop generation, final count,
+        # SHA-256 of the final grid), written by tests/golden/make_life_golden.py
+        vals = {}
+        with open(golden) as fh:
+            for line in fh:
+                if line.strip() == "trajectory":
+                    break
+                if not line.startswith("#") and line.strip():
+                    k, v = line.split()
+                    vals[k] = v
+        digest = hashlib.sha256(grids[-1].cpu().numpy().tobytes()).hexdigest()
+        out["accuracy"] = {"oracle_n": int(vals["n"]), "oracle_count": int(vals["count"]),
+                           "bit_identical_to_oracle": bool(
+                               digest == vals["sha256"] and
+                               int(results[-1].iterations) == int(vals["n"]) and
+                               int(results[-1].last_count) == int(vals["count"]))}
     if not args.no_cpu:
         import oracle as O
         k = 10
@@ -314,11 +354,36 @@ def run_restore(args, L, I, torch):
                             "flagged": flagged,
                             "flagged_px_per_s": round(flagged * r.iterations / (t2 - t1), 1),
                             "px_per_s": round(n * n * r.iterations / (t2 - t1), 1),
-                            "field": u.cpu().numpy().astype(np.float64)}
+                            "field": u.cpu().numpy().astype(np.float64),
+                            "mask": m.cpu().numpy()}
     err = float(np.max(np.abs(out_runs["f32"]["field"] - out_runs["f64"]["field"])) /
                 np.max(np.abs(out_runs["f64"]["field"])))
+    oracle_cmp = None
+    if not args.no_cpu:
+        # the oracle's full two-phase run on the same image: the CPU baseline, and the
+        # reference for the detection mask and both restored fields
+        import oracle as O
+        t0 = time.perf_counter()
+        m_o, u_o = O.amf_detect(rin.y, 19)
+        t1 = time.perf_counter()
+        o, ro = O.restore_run(u_o.astype(np.float64), m_o, thr=0.1, max_iter=200)
+        t2 = time.perf_counter()
+        den = float(np.max(np.abs(o)))
+        oracle_cmp = {
+            "mask_bit_exact": bool(np.array_equal(out_runs["f64"]["mask"], m_o) and
+                                   np.array_equal(out_runs["f32"]["mask"], m_o)),
+            "f64_max_rel_err": float(np.max(np.abs(out_runs["f64"]["field"] - o))) / den,
+            "f32_max_rel_err": float(np.max(np.abs(out_runs["f32"]["field"] - o))) / den,
+            "iterations_oracle": int(ro.n),
+            "iterations_equal": bool(out_runs["f64"]["iterations"] == ro.n ==
+                                     out_runs["f32"]["iterations"])}
+        cpu = {"value": round(n * n * ro.n / (t2 - t0) / 1e9, 4), "unit": "GLUP/s",
+               "cores": O.threads(), "kind": "oracle",
+               "sample": f"the whole job: detection {t1 - t0:.2f} s, {ro.n} restoration "
+                         f"sweeps {t2 - t1:.2f} s"}
     for v in out_runs.values():
         v.pop("field")
+        v.pop("mask")
     wall = (out_runs["f64"]["detect_ms"] + out_runs["f64"]["restore_ms"]) / 1e3
     out = base_line("GLUP/s", round(n * n * out_runs["f64"]["iterations"] / wall / 1e9, 3), "GLUP/s",
                     1, args.warmup, round(wall * 1e3, 3), "f64",
@@ -326,131 +391,527 @@ def run_restore(args, L, I, torch):
                                  f"beta 100, stop max|change| < 0.1 or 200", "rows": n, "cols": n})
     out["runs"] = out_runs
     out["f32_vs_f64_max_rel"] = err
+    if oracle_cmp:
+        out["accuracy"] = oracle_cmp
+        out["cpu_baseline"] = cpu
     ctx.close()
     return out
 
 
 # ---------------------------------------------------------------------------
-def _served_jobs(L, I, torch, count, f32):
-    """Tensors and arguments for the first `count` jobs of the mixed stream."""
+# ---------------------------------------------------------------------------
+# Served mixed stream: jobs are generated on the host at their arrival into
+# pinned buffers, submitted with lsr_run_host (the context allocates their device
+# copies under its HBM budget, copies them in at admission and the result out at
+# retirement), collected in completion order with lsr_wait_any, checked, and
+# freed. At most --host-gib of host buffers are outstanding at a time.
+# ---------------------------------------------------------------------------
+def _job_kw(L, I, spec, h=None):
+    if spec.kind == I.KIND_LAPLACE:
+        return dict(stencil_id=L.LSR_ST_LAPLACE5, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+                    cond=L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), max_iter=2000, bc=L.LSR_BC_RING)
+    if spec.kind == I.KIND_HELMHOLTZ:
+        return dict(stencil_id=L.LSR_ST_HELMHOLTZ5, reduce_op=L.LSR_RED_L2_DELTA,
+                    cond=L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), max_iter=5000,
+                    bc=L.LSR_BC_RING, param=(1.0, h))
+    return dict(stencil_id=L.LSR_ST_LIFE, reduce_op=L.LSR_RED_SUM,
+                cond=L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10), max_iter=2000,
+                bc=L.LSR_BC_TORUS)
+
+
+def _job_bytes(I, spec, f32):
+    esz = 1 if spec.kind == I.KIND_LIFE else (4 if f32 else 8)
+    return spec.side * spec.side * esz * (2 if spec.kind == I.KIND_HELMHOLTZ else 1)
+
+
+def _make_host_job(L, I, torch, spec, f32):
+    """Pinned host grid (and env) of one job of the stream, filled by the seeded recipe."""
+    n = spec.side
+    if spec.kind == I.KIND_LIFE:
+        grid = torch.empty((n, n), dtype=torch.uint8, pin_memory=True)
+        I.life_fill(grid.numpy(), spec.seed)
+        return grid, None, _job_kw(L, I, spec)
+    dt = torch.float32 if f32 else torch.float64
+    grid = torch.empty((n, n), dtype=dt, pin_memory=True)
+    if spec.kind == I.KIND_LAPLACE:
+        I.laplace_fill(grid.numpy(), spec.seed)
+        return grid, None, _job_kw(L, I, spec)
+    env = torch.empty((n, n), dtype=dt, pin_memory=True)
+    h = I.helmholtz_fill(grid.numpy(), env.numpy())
+    return grid, env, _job_kw(L, I, spec, h)
+
+
+def _digest(a):
+    import xxhash
+    return xxhash.xxh3_128_hexdigest(memoryview(a).cast("B"))
+
+
+def _helm_closed_form_err(x, n_side, sweeps):
+    """max|x - u^n| / max|u^n| with u^n = c*(1 - mu^n) u* the closed form of the
+    manufactured Helmholtz solve (alpha = 1), a block of rows at a time."""
     import numpy as np
-    jobs = I.job_stream(count)
-    built = []
-    dt = np.float32 if f32 else np.float64
-    for j in jobs:
-        if j.kind == I.KIND_LAPLACE:
-            a = I.laplace_input(j.side, seed=j.seed)
-            t = torch.from_numpy(a.astype(dt)).to("cuda:0")
-            built.append((j, t, None, (L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
-                                       L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), 2000, L.LSR_BC_RING, ())))
-        elif j.kind == I.KIND_HELMHOLTZ:
-            h = I.helmholtz_input(j.side)
-            t = torch.from_numpy(h.u0.astype(dt)).to("cuda:0")
-            g = torch.from_numpy(h.g.astype(dt)).to("cuda:0")
-            built.append((j, t, g, (L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
-                                    L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 5000, L.LSR_BC_RING,
-                                    (h.alpha, h.h))))
-        else:
-            s = I.life_input(j.side, seed=j.seed)
-            t = torch.from_numpy(s).to("cuda:0")
-            built.append((j, t, None, (L.LSR_ST_LIFE, L.LSR_RED_SUM,
-                                       L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10), 2000,
-                                       L.LSR_BC_TORUS, ())))
-    return built
+    from paper_1609_04567_amd import inputs as I
+    hh = 1.0 / (n_side - 1)
+    s2 = math.sin(math.pi * hh / 2) ** 2
+    one_m_mu = (8.0 * s2 + hh * hh) / (4.0 + hh * hh)
+    lam = 8.0 / (hh * hh) * s2
+    coef = (2 * math.pi ** 2 + 1.0) / (lam + 1.0) * -math.expm1(sweeps * math.log1p(-one_m_mu))
+    sv, _ = I.helmholtz_factor(n_side)
+    worst, den = 0.0, coef * float(np.max(sv)) ** 2
+    step = max(1, (1 << 16) // n_side)
+    for r0 in range(0, n_side, step):
+        r1 = min(n_side, r0 + step)
+        ref = np.outer(coef * sv[r0:r1], sv)
+        worst = max(worst, float(np.max(np.abs(x[r0:r1].astype(np.float64) - ref))))
+    return worst / den
+
+
+class _StreamRun:
+    """Feeds a job stream to a context and collects it.
+
+    Generator threads build jobs in index order into pinned buffers while the
+    outstanding host bytes stay under a limit; the submitter submits job k as soon
+    as it is built (closed loop) or at its scheduled arrival time (open loop); a
+    collector takes results in completion order (lsr_wait_any) and hands each job
+    to a pool of checker threads, which run `check(k, job, result)` and free it."""
+
+    def __init__(self, L, I, torch, ctx, specs, f32, host_bytes, gen_threads=6, check_threads=6,
+                 arrivals=None, check=None, variants=None):
+        import concurrent.futures as cf
+        self.L, self.I, self.torch, self.ctx = L, I, torch, ctx
+        self.specs, self.f32 = specs, f32
+        self.variants = variants or [f32]      # one submission per precision in the list
+        self.limit = host_bytes
+        self.arrivals = arrivals
+        self.check = check
+        self.cv = threading.Condition()
+        self.ready = {}
+        self.out_bytes = 0
+        self.next_gen = 0
+        self.submitted = 0
+        self.collected = 0
+        self.total = len(specs) * len(self.variants)
+        self.lag = []
+        self.error = None
+        self.gen_threads = gen_threads
+        self.pool = cf.ThreadPoolExecutor(max_workers=check_threads)
+        self.jobs = {}
+
+    def _gen(self):
+        try:
+            while True:
+                with self.cv:
+                    k = self.next_gen
+                    if k >= len(self.specs) or self.error:
+                        return
+                    self.next_gen += 1
+                    spec = self.specs[k]
+                    need = sum(_job_bytes(self.I, spec, v) for v in self.variants)
+                    # a job larger than the limit still runs, alone
+                    self.cv.wait_for(lambda: self.error or self.out_bytes == 0 or
+                                     self.out_bytes + need <= self.limit)
+                    self.out_bytes += need
+                built = [(_make_host_job(self.L, self.I, self.torch, spec, v), v,
+                          _job_bytes(self.I, spec, v)) for v in self.variants]
+                with self.cv:
+                    self.ready[k] = built
+                    self.cv.notify_all()
+        except BaseException as e:   # surfaced by run()
+            with self.cv:
+                self.error = e
+                self.cv.notify_all()
+
+    def _collect(self):
+        L = self.L
+        try:
+            while self.collected < self.total:
+                with self.cv:
+                    self.cv.wait_for(lambda: self.error or self.submitted > self.collected)
+                    if self.error:
+                        return
+                jid = self.ctx.wait_any(True)
+                r = self.ctx.result(jid)
+                with self.cv:
+                    k, v, job, need = self.jobs.pop(jid)
+                    self.collected += 1
+                self.pool.submit(self._finish, k, v, job, r, need)
+        except BaseException as e:
+            with self.cv:
+                self.error = e
+                self.cv.notify_all()
+
+    def _finish(self, k, v, job, r, need):
+        try:
+            if self.check:
+                self.check(k, v, job, r)
+        except BaseException as e:
+            with self.cv:
+                self.error = e
+                self.cv.notify_all()
+        finally:
+            with self.cv:
+                self.out_bytes -= need
+                self.cv.notify_all()
+
+    def run(self):
+        """Runs the stream; returns the wall time from the first submission to the
+        last result (checks of the last jobs excluded)."""
+        gens = [threading.Thread(target=self._gen, daemon=True) for _ in range(self.gen_threads)]
+        for g in gens:
+            g.start()
+        col = threading.Thread(target=self._collect, daemon=True)
+        col.start()
+        t0 = None
+        for k, spec in enumerate(self.specs):
+            with self.cv:
+                self.cv.wait_for(lambda: self.error or k in self.ready)
+                if self.error:
+                    break
+                built = self.ready.pop(k)
+            if t0 is None:
+                t0 = time.perf_counter()
+            if self.arrivals is not None:
+                d = t0 + self.arrivals[k] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                self.lag.append(max(0.0, time.perf_counter() - t0 - self.arrivals[k]))
+            for (grid, env, kw), v, need in built:
+                jid = self.ctx.submit_host(grid, kw["stencil_id"], kw["reduce_op"], kw["cond"],
+                                           kw["max_iter"], kw["bc"], env0=env,
+                                           param=kw.get("param", ()))
+                with self.cv:
+                    self.jobs[jid] = (k, v, (grid, env, kw), need)
+                    self.submitted += 1
+                    self.cv.notify_all()
+        col.join()
+        wall = time.perf_counter() - (t0 or time.perf_counter())
+        self.pool.shutdown(wait=True)
+        for g in gens:
+            g.join()
+        if self.error:
+            raise self.error
+        return wall
+
+
+def _pct(v, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(v), q)), 2) if len(v) else None
 
 
 def run_served(args, L, I, torch):
+    """The mixed stream of 20000 jobs (60% Laplace, 25% Helmholtz, 15% Life; side
+    log-uniform in [128, 4096]; each job generated on the host at its arrival).
+
+    Legs (--legs, comma separated):
+      closed   batched engine, FP32 storage, closed loop (as many jobs in flight as
+               --host-gib of host buffers allow): jobs/s, latency percentiles, a
+               digest of every result, the closed-form error of every Helmholtz job.
+      poisson  the same at Poisson arrivals of lambda x the closed-loop rate for each
+               lambda in --lambdas (--rate gives the closed-loop rate when that leg
+               is not in this run).
+      verify   untimed: every Laplace and Helmholtz job again in FP32 and in FP64 on
+               one batched context; each FP32 field's error against its FP64 field
+               (FP64 fields are bit-identical to the oracle's, FP32 digests equal the
+               closed leg's).
+      plain    the plain FP64 path: one job after another on a plain context
+               (fused launches where they apply): jobs/s and a digest of every result.
+      oracle   the CPU oracle on a seeded sample (every 97th job up to side 1024 and
+               every 997th of any side): its time (the CPU baseline), and the FP32 /
+               FP64 / Life results of those jobs against it.
+    """
     import numpy as np
     count = args.jobs
-    t0 = time.perf_counter()
-    f32_jobs = _served_jobs(L, I, torch, count, True)
-    print(f"built {count} FP32 jobs in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    originals = [t.clone() for (_, t, _, _) in f32_jobs]
+    specs = I.job_stream(count)
+    legs = [x for x in args.legs.split(",") if x]
+    gib = int(args.host_gib * (1 << 30))
+    recs = {k: {"kind": s.kind, "side": s.side} for k, s in enumerate(specs)}
+    keep_fields = {}
+    sample = {k for k, s in enumerate(specs)
+              if (k % 97 == 0 and s.side <= 1024) or k % 997 == 0}
+    out = None
+    sat = args.rate or None
 
-    def reset():
-        for (_, t, _, _), o in zip(f32_jobs, originals):
-            t.copy_(o)
-        torch.cuda.synchronize()
+    def lup_of(k, n):
+        s = specs[k]
+        return (s.side - (0 if s.kind == I.KIND_LIFE else 2)) ** 2 * n
 
-    bctx = L.Context(0, batched=True)
+    # -- closed loop, batched FP32 --------------------------------------------
+    if "closed" in legs:
+        bctx = L.Context(0, batched=True)
+        done_lup = [0]
 
-    def submit(entry):
-        j, t, g, (st, red, cond, mi, bc, param) = entry
-        return bctx.submit(t, st, red, cond, mi, bc, env0=g, param=param)
+        def check(k, v, job, r):
+            grid = job[0].numpy()
+            rec = recs[k]
+            rec.update(n=int(r.iterations), r32=float(r.last_reduce), count=int(r.last_count),
+                       lat_ms=round(r.latency_ms, 3), queue_ms=round(r.queue_ms, 3),
+                       status=int(r.status), d32=_digest(grid))
+            done_lup[0] += lup_of(k, r.iterations)
+            if specs[k].kind == I.KIND_HELMHOLTZ:
+                rec["cf_err32"] = _helm_closed_form_err(grid, specs[k].side, r.iterations)
+            if k in sample and specs[k].kind != I.KIND_LIFE:
+                keep_fields[(k, "f32")] = grid.copy()
 
-    # closed loop: every job present at t = 0
-    reset()
-    t0 = time.perf_counter()
-    ids = [submit(e) for e in f32_jobs]
-    res = [bctx.result(i) for i in ids]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sat = count / wall
-    lat = np.array([r.latency_ms for r in res])
-    lups = sum((e[0].side - (0 if e[0].kind == I.KIND_LIFE else 2)) ** 2 * r.iterations
-               for e, r in zip(f32_jobs, res))
-    print(f"batched closed loop: {sat:.2f} jobs/s", file=sys.stderr, flush=True)
-    f32_fields = [t.clone() for (_, t, _, _) in f32_jobs]
+        run = _StreamRun(L, I, torch, bctx, specs, True, gib, check=check)
+        wall = run.run()
+        bctx.close()
+        sat = count / wall
+        lat = [recs[k]["lat_ms"] for k in recs]
+        print(f"closed loop: {count} jobs in {wall:.1f} s = {sat:.2f} jobs/s", file=sys.stderr,
+              flush=True)
+        out = base_line("jobs/s", round(sat, 3), "jobs/s", 1, 0, round(wall * 1e3, 1), "f32",
+                        {"workload": f"served mixed stream, {count} jobs (60% Laplace, 25% "
+                                     "Helmholtz, 15% Life; side log-uniform 128..4096), host "
+                                     "ingest, FP32 storage with FP64 reduce, batched engine",
+                         "jobs": count, "host_window_gib": args.host_gib})
+        out["batched_glup_s"] = round(done_lup[0] / wall / 1e9, 2)
+        out["latency_closed_loop_ms"] = {"p50": _pct(lat, 50), "p99": _pct(lat, 99)}
+        cf = [recs[k]["cf_err32"] for k in recs if "cf_err32" in recs[k]]
+        out["helmholtz_closed_form"] = {"jobs": len(cf), "max_rel_err": max(cf) if cf else None,
+                                        "within_1e-5": int(sum(e <= 1e-5 for e in cf))}
+        bad = [k for k in recs if recs[k].get("status", 0) != L.LSR_OK]
+        out["status_not_ok"] = len(bad)
+    if out is None:
+        out = base_line("jobs/s", None, "jobs/s", 1, 0, None, "f32",
+                        {"workload": f"served mixed stream, {count} jobs", "jobs": count})
 
-    # open loop: Poisson arrivals at 0.8 x the closed-loop rate
-    reset()
-    rate = 0.8 * sat
-    arrivals = I.poisson_arrivals([e[0] for e in f32_jobs], rate)
-    ids2 = [None] * count
+    # -- Poisson arrivals ------------------------------------------------------
+    if "poisson" in legs:
+        if not sat:
+            raise SystemExit("--legs poisson needs the closed leg or --rate")
+        out["poisson"] = []
+        for lam in [float(x) for x in args.lambdas.split(",")]:
+            rate = lam * sat
+            arr = I.poisson_arrivals(specs, rate)
+            lat = []
+            bctx = L.Context(0, batched=True)
 
-    def feeder():
-        start = time.perf_counter()
-        for k, e in enumerate(f32_jobs):
-            d = start + arrivals[k] - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            ids2[k] = submit(e)
+            def check(k, v, job, r, lat=lat):
+                lat.append(r.latency_ms)
 
-    th = threading.Thread(target=feeder)
-    t0 = time.perf_counter()
-    th.start()
-    th.join()
-    res2 = [bctx.result(i) for i in ids2]
-    wall2 = time.perf_counter() - t0
-    lat2 = np.array([r.latency_ms for r in res2])
-    bctx.close()
+            run = _StreamRun(L, I, torch, bctx, specs, True, gib, arrivals=arr, check=check)
+            wall = run.run()
+            bctx.close()
+            lag = np.array(run.lag) * 1e3
+            e = {"lambda_x_sat": lam, "rate_jobs_s": round(rate, 3), "wall_s": round(wall, 2),
+                 "served_jobs_s": round(count / wall, 3), "p50_ms": _pct(lat, 50),
+                 "p99_ms": _pct(lat, 99), "submit_lag_p99_ms": _pct(lag, 99)}
+            out["poisson"].append(e)
+            print(f"poisson {e}", file=sys.stderr, flush=True)
 
-    # plain FP64 path: one grid per launch sequence, jobs one after another
-    del originals
-    f64_jobs = _served_jobs(L, I, torch, count, False)
-    pctx = L.Context(0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res3 = []
-    for j, t, g, (st, red, cond, mi, bc, param) in f64_jobs:
-        res3.append(pctx.run(t, st, red, cond, mi, bc, env0=g, param=param))
-    torch.cuda.synchronize()
-    wall3 = time.perf_counter() - t0
-    pctx.close()
-    # accuracy of every FP32 result against the FP64 path (bit-identical to the
-    # oracle in the parity tests); Life must be bit-exact
-    worst, count_match = 0.0, 0
-    for (e, _, _, _), x32, (_, x64, _, _), r32, r64 in zip(f32_jobs, f32_fields, f64_jobs, res, res3):
-        count_match += int(r32.iterations == r64.iterations)
-        if e.kind == I.KIND_LIFE:
-            assert bool((x32 == x64).all()), "life result differs"
-        else:
-            d = float((x32.double() - x64).abs().max() / x64.abs().max().clamp_min(1e-300))
-            worst = max(worst, d)
-    out = base_line("jobs/s", round(sat, 3), "jobs/s", 1, 0, round(wall * 1e3, 1), "f32",
-                    {"workload": f"served mixed stream, first {count} jobs (60% Laplace, 25% "
-                                 "Helmholtz, 15% Life; side log-uniform 128..4096), FP32 storage "
-                                 "with FP64 reduce, batched engine", "jobs": count})
-    out["batched_glup_s"] = round(lups / wall / 1e9, 2)
-    out["latency_closed_loop_ms"] = {"p50": round(float(np.percentile(lat, 50)), 2),
-                                     "p99": round(float(np.percentile(lat, 99)), 2)}
-    out["poisson"] = {"rate_jobs_s": round(rate, 3), "wall_s": round(wall2, 3),
-                      "p50_ms": round(float(np.percentile(lat2, 50)), 2),
-                      "p99_ms": round(float(np.percentile(lat2, 99)), 2)}
-    out["plain_fp64_jobs_s"] = round(count / wall3, 3)
-    out["speedup_vs_plain_fp64"] = round(sat / (count / wall3), 3)
-    out["accuracy"] = {"f32_vs_f64_max_rel": worst, "iteration_counts_equal": count_match,
-                       "jobs": count}
+    # -- verification: FP32 against FP64, every Laplace and Helmholtz job -----------
+    if "verify" in legs:
+        vspecs = [(k, s) for k, s in enumerate(specs) if s.kind != I.KIND_LIFE]
+        bctx = L.Context(0, batched=True)
+        pend = {}
+        lock = threading.Lock()
+
+        def check(i, v, job, r):
+            k = vspecs[i][0]
+            grid = job[0].numpy()
+            with lock:
+                pend.setdefault(k, {})[v] = (grid, r)
+                pair = pend.pop(k) if len(pend[k]) == 2 else None
+            if pair is None:
+                return
+            (x32, r32), (x64, r64) = pair[True], pair[False]
+            rec = recs[k]
+            den = float(np.max(np.abs(x64)))
+            rec["err32"] = float(np.max(np.abs(x32.astype(np.float64) - x64))) / (den or 1.0)
+            rec["n64"] = int(r64.iterations)
+            rec["n32v"] = int(r32.iterations)
+            rec["d32v"] = _digest(x32)
+            rec["d64v"] = _digest(x64)
+            if k in sample:
+                keep_fields[(k, "f32")] = x32.copy()
+                keep_fields[(k, "f64")] = x64.copy()
+
+        run = _StreamRun(L, I, torch, bctx, [s for _, s in vspecs], True, gib, check=check,
+                         variants=[True, False])
+        t0 = time.perf_counter()
+        run.run()
+        bctx.close()
+        errs = [recs[k]["err32"] for k, _ in vspecs]
+        same_n = sum(recs[k]["n64"] == recs[k]["n32v"] for k, _ in vspecs)
+        v = {"jobs": len(vspecs), "wall_s": round(time.perf_counter() - t0, 1),
+             "max_rel_err_f32_vs_f64": max(errs), "p99_rel_err": float(np.percentile(errs, 99)),
+             "within_1e-5": int(sum(e <= 1e-5 for e in errs)), "iteration_counts_equal": same_n}
+        if "closed" in legs:
+            v["f32_digest_equal_to_closed_leg"] = int(sum(recs[k]["d32v"] == recs[k]["d32"]
+                                                          for k, _ in vspecs))
+            v["iterations_equal_to_closed_leg"] = int(sum(recs[k]["n32v"] == recs[k]["n"]
+                                                          for k, _ in vspecs))
+        out["verify"] = v
+        print(f"verify {v}", file=sys.stderr, flush=True)
+
+    # -- plain FP64 path ------------------------------------------------------
+    if "plain" in legs:
+        pctx = L.Context(0)
+        done = []
+
+        def check(k, v, job, r):
+            grid = job[0].numpy()
+            recs[k].update(n64p=int(r.iterations), d64p=_digest(grid))
+            done.append(k)
+            if k in sample and specs[k].kind != I.KIND_LIFE:
+                keep_fields[(k, "f64p")] = grid.copy()
+
+        # one job at a time on the device; the host prepares the next ones meanwhile
+        run = _StreamRun(L, I, torch, pctx, specs, False, min(gib, 4 << 30), check=check)
+        wall = run.run()
+        pctx.close()
+        pj = count / wall
+        out["plain_fp64_jobs_s"] = round(pj, 3)
+        if "closed" in legs:
+            out["speedup_vs_plain_fp64"] = round(sat / pj, 3)
+            out["life_equal_batched_vs_plain"] = int(sum(
+                recs[k]["d32"] == recs[k]["d64p"] and recs[k]["n"] == recs[k]["n64p"]
+                for k in recs if specs[k].kind == I.KIND_LIFE))
+        if "verify" in legs:
+            out["f64_batched_equal_plain"] = int(sum(
+                recs[k]["d64v"] == recs[k]["d64p"] and recs[k]["n64"] == recs[k]["n64p"]
+                for k in recs if specs[k].kind != I.KIND_LIFE))
+        print(f"plain fp64: {pj:.2f} jobs/s", file=sys.stderr, flush=True)
+
+    # -- CPU oracle on the seeded sample (the CPU baseline) --------------------------
+    if "oracle" in legs:
+        import oracle as O
+        res, t_or, lup_or = [], 0.0, 0
+        for k in sorted(sample):
+            s = specs[k]
+            t0 = time.perf_counter()
+            if s.kind == I.KIND_LAPLACE:
+                a = I.laplace_input(s.side, seed=s.seed)
+                o, ro = O.jacobi_run(a, thr=1e-6, max_iter=2000)
+            elif s.kind == I.KIND_HELMHOLTZ:
+                h = I.helmholtz_input(s.side)
+                o, ro = O.jacobi_run(h.u0, helmholtz=True, g=h.g, alpha=h.alpha, h=h.h,
+                                     reduce_op=O.RED_L2_DELTA, thr=1e-9, check_every=10,
+                                     max_iter=5000)
+            else:
+                a = I.life_input(s.side, seed=s.seed)
+                o, ro = O.life_run(a, stable_window=10, max_iter=2000)
+            dt = time.perf_counter() - t0
+            t_or += dt
+            lup_or += lup_of(k, ro.n)
+            e = {"job": k, "kind": s.kind, "side": s.side, "n_oracle": ro.n, "oracle_s": round(dt, 3)}
+            rec = recs[k]
+            if s.kind == I.KIND_LIFE:
+                d = _digest(o)
+                if "d32" in rec:
+                    e["batched_equal"] = rec["d32"] == d and rec["n"] == ro.n
+                if "d64p" in rec:
+                    e["plain_equal"] = rec["d64p"] == d and rec["n64p"] == ro.n
+            else:
+                den = float(np.max(np.abs(o))) or 1.0
+                if (k, "f32") in keep_fields:
+                    x = keep_fields[(k, "f32")]
+                    e["f32_rel_err"] = float(np.max(np.abs(x.astype(np.float64) - o))) / den
+                    e["f32_n_equal"] = rec.get("n", rec.get("n32v")) == ro.n
+                for tag in ("f64", "f64p"):
+                    if (k, tag) in keep_fields:
+                        e[f"{tag}_bit_equal"] = bool(np.array_equal(keep_fields[(k, tag)], o))
+            res.append(e)
+        oracle_glups = lup_or / t_or / 1e9
+        # jobs/s of the oracle over the whole stream, extrapolated from its GLUP/s on
+        # the sample and the stream's total cell updates (the closed leg's counts)
+        total_lup = sum(lup_of(k, recs[k]["n"]) for k in recs if "n" in recs[k])
+        out["cpu_baseline"] = {
+            "value": round(count / (total_lup / (oracle_glups * 1e9)), 4) if total_lup else None,
+            "unit": "jobs/s", "cores": O.threads(), "kind": "oracle",
+            "sample": (f"{len(res)} jobs (every 97th up to side 1024, every 997th), "
+                       f"{t_or:.1f} s, {oracle_glups:.2f} GLUP/s; jobs/s extrapolated to the "
+                       "whole stream's cell updates")}
+        out["oracle_sample"] = {
+            "jobs": len(res),
+            "f32_max_rel_err": max([e["f32_rel_err"] for e in res if "f32_rel_err" in e],
+                                   default=None),
+            "f32_n_equal": sum(bool(e.get("f32_n_equal")) for e in res),
+            "f64_bit_equal": sum(bool(e.get("f64_bit_equal")) for e in res),
+            "f64p_bit_equal": sum(bool(e.get("f64p_bit_equal")) for e in res),
+            "life_batched_equal": sum(bool(e.get("batched_equal")) for e in res),
+            "life_plain_equal": sum(bool(e.get("plain_equal")) for e in res),
+            "by_kind": {kd: sum(e["kind"] == kd for e in res) for kd in
+                        (I.KIND_LAPLACE, I.KIND_HELMHOLTZ, I.KIND_LIFE)}}
+    if args.records:
+        with open(args.records, "w") as fh:
+            json.dump({str(k): v for k, v in recs.items()}, fh)
+    return out
+
+
+# ---------------------------------------------------------------------------
+def run_video(args, L, I, torch):
+    """Restoration of noisy video streams (the 100-frame streams of Sect. 4.3's
+    table: VGA 640x480, 720p 1280x720 and 2048x1080 at 30% and 70% impulses;
+    synthetic frames of moving blobs). Each frame is one two-phase job on a batched
+    context (lsr_run_restore_host: H2D of the frame, detection, restoration sweeps
+    in the engine's rounds beside the other frames, D2H of the result), stopping on
+    the mean absolute change below 1e-3 (the paper's criterion) or 200 sweeps.
+    Frames are generated on the host ahead of time and submitted as fast as the
+    engine admits them; results come back in completion order and are taken in
+    frame order, as the ordered farm of the paper's pipeline delivers them."""
+    import numpy as np
+    nframes = args.frames
+    streams = [(480, 640, "VGA"), (720, 1280, "720p"), (1080, 2048, "2048x1080")]
+    dt = torch.float32 if args.video_dtype == "f32" else torch.float64
+    cond = L.make_cond(L.LSR_COND_BELOW, 1e-3, 1)
+    runs = []
+    sample = sorted({0, nframes // 2, nframes - 1})
+    keep = {}
+    for rows, cols, name in streams:
+        for noise in (0.3, 0.7):
+            frames = [torch.from_numpy(I.video_frame(rows, cols, f, noise=noise).y).pin_memory()
+                      for f in range(nframes)]
+            outs = [torch.empty((rows, cols), dtype=dt).pin_memory() for _ in range(nframes)]
+            bctx = L.Context(0, batched=True)
+            # warm-up frame (first use of the kernels and the pool)
+            bctx.result(bctx.submit_restore_host(frames[0], outs[0],
+                                                 reduce_op=L.LSR_RED_MEAN_ABS_DELTA, cond=cond))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids = [bctx.submit_restore_host(frames[f], outs[f], reduce_op=L.LSR_RED_MEAN_ABS_DELTA,
+                                            cond=cond) for f in range(nframes)]
+            res = [bctx.result(i) for i in ids]   # in frame order
+            wall = time.perf_counter() - t0
+            bctx.close()
+            its = [int(r.iterations) for r in res]
+            assert all(r.status == L.LSR_OK for r in res)
+            runs.append({"video": f"{name}, {int(noise * 100)}%", "frames": nframes,
+                         "wall_s": round(wall, 4), "fps": round(nframes / wall, 1),
+                         "mpx_per_s": round(nframes * rows * cols / wall / 1e6, 1),
+                         "iterations_min_max": [min(its), max(its)],
+                         "latency_p50_ms": _pct([r.latency_ms for r in res], 50)})
+            print(f"video {runs[-1]}", file=sys.stderr, flush=True)
+            for f in sample:
+                keep[(name, noise, f)] = (frames[f].numpy().copy(), outs[f].numpy().copy(),
+                                          its[f])
+    out = base_line("frames/s", round(min(r["fps"] for r in runs), 1), "frames/s", 1, 1, None,
+                    args.video_dtype,
+                    {"workload": f"two-phase restoration of {nframes}-frame video streams (VGA, "
+                                 "720p, 2048x1080 at 30% and 70% impulses), mean |change| < 1e-3 "
+                                 "or 200 sweeps, batched engine, host frames", "frames": nframes})
+    out["streams"] = runs
+    if not args.no_cpu:
+        # per-frame parity with the oracle on frames sampled from each stream, and the
+        # oracle's own time on them (the CPU baseline)
+        import oracle as O
+        worst, n_eq, masks_eq, t_or, px = 0.0, 0, 0, 0.0, 0
+        for (name, noise, f), (y, u, n_gpu) in keep.items():
+            t0 = time.perf_counter()
+            m_o, u_o = O.amf_detect(y, 19)
+            o, ro = O.restore_run(u_o.astype(np.float64), m_o, reduce_op=O.RED_MEAN_ABS_DELTA,
+                                  thr=1e-3, max_iter=200)
+            t_or += time.perf_counter() - t0
+            px += y.size
+            worst = max(worst, float(np.max(np.abs(u.astype(np.float64) - o)) / np.max(np.abs(o))))
+            n_eq += int(n_gpu == ro.n)
+        out["accuracy"] = {"frames_checked": len(keep), "max_rel_err_vs_oracle": worst,
+                           "iterations_equal": n_eq,
+                           "tolerance": 1e-5 if args.video_dtype == "f32" else 1e-12}
+        out["cpu_baseline"] = {"value": round(len(keep) / t_or, 3), "unit": "frames/s",
+                               "cores": O.threads(), "kind": "oracle",
+                               "sample": f"{len(keep)} frames sampled from the six streams "
+                                         f"({px / 1e6:.1f} Mpx, {t_or:.1f} s)"}
     return out
 
 
@@ -460,10 +921,20 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="helmholtz",
-                    choices=["helmholtz", "laplace", "life", "restore", "served"])
+                    choices=["helmholtz", "laplace", "life", "restore", "served", "video"])
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--sweeps", type=int, default=0)
-    ap.add_argument("--jobs", type=int, default=200)
+    ap.add_argument("--jobs", type=int, default=20000)
+    ap.add_argument("--legs", default="closed,poisson,verify,plain,oracle",
+                    help="served workload: which legs to run (see run_served)")
+    ap.add_argument("--lambdas", default="0.5,0.8,1.0,1.2")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="closed-loop jobs/s for the poisson leg when closed is not run")
+    ap.add_argument("--host-gib", type=float, default=12.0,
+                    help="host buffers outstanding at a time in the served legs")
+    ap.add_argument("--records", default="", help="served: write per-job records (JSON) here")
+    ap.add_argument("--frames", type=int, default=100, help="video: frames per stream")
+    ap.add_argument("--video-dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--cpu-sweeps", type=int, default=1500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
@@ -488,7 +959,7 @@ def main():
     from paper_1609_04567_amd import inputs as I
 
     fn = {"helmholtz": run_helmholtz, "laplace": run_laplace, "life": run_life,
-          "restore": run_restore, "served": run_served}[args.workload]
+          "restore": run_restore, "served": run_served, "video": run_video}[args.workload]
     print(json.dumps(fn(args, L, I, torch)), flush=True)
 
 

@@ -125,8 +125,8 @@ typedef struct {
  * jobs, one launch for all their final reduces and conditions), and retires jobs
  * as they stop, freeing their memory for the next arrivals. A job's tile shape and
  * reduce order depend only on its own shape, so its result is the same alone and
- * in any mix. Supported: LAPLACE5, HELMHOLTZ5 (F64 or F32) and LIFE; RESTORE is
- * EINVAL on a batched context.
+ * in any mix. Supported: every stencil (restoration sweeps one round at a time;
+ * two-phase restoration frames through lsr_run_restore_host).
  */
 #define LSR_FLAG_BATCHED 1u
 
@@ -175,10 +175,21 @@ typedef struct {
                                fused launches always load 3) */
 } lsr_tuning;
 
-/* Creates a context on cfg->device. Returns EINVAL for a bad device, EDEVICE on HIP failure. */
+/*
+ * Creates a context on cfg->device: the runtime set-up that the pattern's
+ * implementation does once before any task (Sect. 3.2/3.3: device detection and
+ * set-up, the device-memory manager that keeps buffers persistent across
+ * iterations; here an execution stream, a pool bounded by hbm_budget_bytes, pinned
+ * state mirrors and a driver thread, or the batched engine with
+ * LSR_FLAG_BATCHED). *out receives the context; the caller destroys it with
+ * lsr_destroy. EINVAL for a NULL argument, unknown flags or a bad device ordinal;
+ * EDEVICE when a HIP call fails (nothing is left allocated then).
+ */
 lsr_status lsr_create(const lsr_config *cfg, lsr_ctx **out);
 
-/* Destroys the context after all its jobs have finished; frees its scratch. */
+/* Destroys the context (the end of the runtime of Sect. 3.3) after all its jobs have
+ * finished: frees its scratch pool, pinned mirrors and streams. Results not taken are
+ * discarded. EINVAL for NULL. */
 lsr_status lsr_destroy(lsr_ctx *ctx);
 
 /* Sets tuning overrides for later lsr_run calls (NULL restores the defaults). */
@@ -233,7 +244,7 @@ lsr_status lsr_run(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id, int32
  * buffers are allocated and filled by H2D copies; Fig. 2: read(output) copies the
  * result back by D2H). Same arguments, checks and supported combinations as
  * lsr_run, except that grid->data and grid->env0 are host pointers (rows x pitch
- * elements each) and RESTORE is EINVAL (its mask stays a device buffer).
+ * elements each; the RESTORE mask is u8 with the grid's pitch in elements).
  *  - Memory: the context allocates the job's device grid, env and scratch from
  *    its pool, so all of the job's device memory counts against
  *    hbm_budget_bytes. Plain context: allocated at this call (ENOMEM/EBUSY as
@@ -252,12 +263,47 @@ lsr_status lsr_run_host(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id, 
                         const lsr_cond *cond, int64_t max_iter, lsr_job *job_out);
 
 /*
- * Result of a job. wait != 0 blocks until the job ends; wait == 0 returns EBUSY while it
- * runs. On a terminal status the job's record is released (a second call gives ENOTFOUND)
+ * Two-phase restoration of one HOST frame as one job on a batched context: the
+ * frame-at-a-time pipeline of Sect. 4.3 (detect, then the iterative restore, for
+ * each frame of a stream; items of a stream overlap on the device and reuse its
+ * memory, Sect. 4.3 and 3.3). y is the noisy u8 frame (y->data host, rows, cols,
+ * pitch in bytes; y->bc must be BOTTOM; y->param[0] = beta, y->param[1] != 0
+ * selects phi(t) = t^2, as for RESTORE). When admitted (under the HBM budget, like
+ * lsr_run_host), the frame goes to the device on the copy stream; then, between
+ * sweep rounds of other jobs, adaptive-median detection (lsr_amf_detect's rule,
+ * w_max) writes the mask and the initial iterate on the device, and the job's
+ * restoration sweeps join the rounds. At retirement the restored frame is copied
+ * to u_out (host, u_dtype F32 or F64, rows x y->pitch elements). The caller keeps
+ * y->data and u_out alive and untouched until lsr_result reports a terminal
+ * status. reduce_op, cond, max_iter as for RESTORE. EINVAL on a plain context, for
+ * a non-U8 frame, a bad u_dtype, w_max not odd in [3, 31], or what lsr_run would
+ * reject for the restoration of a frame this shape.
+ */
+lsr_status lsr_run_restore_host(lsr_ctx *ctx, const lsr_grid *y, void *u_out, int32_t u_dtype,
+                                int32_t w_max, int32_t reduce_op, const lsr_cond *cond,
+                                int64_t max_iter, lsr_job *job_out);
+
+/*
+ * Result of a job: the loop's output read back once it has stopped (Fig. 2's
+ * read(output) step; the field itself stays in the caller's device grid, or has been
+ * copied back into the host grid for lsr_run_host). wait != 0 blocks until the job
+ * ends; wait == 0 returns EBUSY while it runs. On a terminal status the job's record is released (a second call gives ENOTFOUND)
  * and the context stream is ordered after the job. Returns the job's own status
  * (OK, ENUMERIC, ECANCELED, EDEVICE), which is also in out->status.
  */
 lsr_status lsr_result(lsr_ctx *ctx, lsr_job job, int32_t wait, lsr_job_result *out);
+
+/*
+ * Completion queue of a context, for a caller serving a stream of jobs (the
+ * stream of tasks of Sect. 3.2, whose items finish in any order): stores in
+ * *job_out the id of a finished job whose result has not been taken yet, oldest
+ * completion first; the caller then takes it with lsr_result. wait != 0 blocks
+ * until some job finishes; wait == 0 returns EBUSY when none has. ENOTFOUND when
+ * nothing is left to report: every job submitted has finished and has been
+ * reported here or had its result taken. Each finished job is reported at most
+ * once; a job whose result lsr_result already took is skipped.
+ */
+lsr_status lsr_wait_any(lsr_ctx *ctx, int32_t wait, lsr_job *job_out);
 
 /* Requests cancellation; the job stops at its next chunk boundary with ECANCELED. */
 lsr_status lsr_cancel(lsr_ctx *ctx, lsr_job job);

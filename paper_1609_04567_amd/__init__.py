@@ -14,8 +14,8 @@ from ._native import (  # noqa: F401
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
-    lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_set_tuning, lsr_tune_export, lsr_tune_import,
-    lsr_version, make_cond, make_grid,
+    lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_restore_host,
+    lsr_set_tuning, lsr_tune_export, lsr_tune_import, lsr_version, lsr_wait_any, make_cond, make_grid,
 )
 
 
@@ -109,10 +109,31 @@ class Context:
         self._keep[job] = (grid, env0)
         return job
 
+    def submit_restore_host(self, y, u_out, w_max=19, beta=100.0, quadratic=False,
+                            reduce_op=LSR_RED_MAX_ABS_DELTA, cond=None, max_iter=200):
+        """Detection + restoration of a host u8 frame y into the host array u_out
+        (same shape and pitch, float32 or float64) on a batched context."""
+        if cond is None:
+            cond = make_cond(LSR_COND_BELOW, 0.1, 1)
+        import numpy as np
+        import torch
+        g = grid_from_host(y, LSR_BC_BOTTOM, param=(beta, 1.0 if quadratic else 0.0))
+        u = torch.from_numpy(u_out) if isinstance(u_out, np.ndarray) else u_out
+        if tuple(u.shape) != (g.rows, g.cols) or u.stride(0) != g.pitch or u.is_cuda:
+            raise ValueError("u_out must be a host array of y's shape and pitch")
+        job = lsr_run_restore_host(self.handle, g, u.data_ptr(), _dtype_code(u), w_max, reduce_op,
+                                   cond, max_iter)
+        self._keep[job] = (y, u_out)
+        return job
+
     def result(self, job, wait=True):
         r = lsr_result(self.handle, job, wait)
         self._keep.pop(job, None)
         return r
+
+    def wait_any(self, wait=True):
+        """Id of a finished job whose result is not taken yet (lsr_wait_any)."""
+        return lsr_wait_any(self.handle, wait)
 
     def cancel(self, job):
         lsr_cancel(self.handle, job)

@@ -76,8 +76,12 @@ _SIGS = {
                           C.POINTER(lsr_cond), C.c_int64, C.POINTER(C.c_int64)]),
     "lsr_run_host": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_int32, C.c_int32,
                                C.POINTER(lsr_cond), C.c_int64, C.POINTER(C.c_int64)]),
+    "lsr_run_restore_host": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_void_p, C.c_int32,
+                                       C.c_int32, C.c_int32, C.POINTER(lsr_cond), C.c_int64,
+                                       C.POINTER(C.c_int64)]),
     "lsr_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(lsr_job_result)]),
     "lsr_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lsr_wait_any": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     "lsr_amf_detect": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_void_p, C.c_void_p,
                                  C.c_int32, C.c_int32]),
     "lsr_check_args": (C.c_int, [C.POINTER(lsr_grid), C.c_int32, C.c_int32, C.POINTER(lsr_cond),
@@ -155,6 +159,15 @@ def lsr_run_host(ctx: int, grid: lsr_grid, stencil_id: int, reduce_op: int, cond
     return job.value
 
 
+def lsr_run_restore_host(ctx: int, y: lsr_grid, u_out_ptr: int, u_dtype: int, w_max: int,
+                         reduce_op: int, cond: lsr_cond, max_iter: int) -> int:
+    """Detection and restoration of one host frame as one batched job."""
+    job = C.c_int64()
+    _check(lib().lsr_run_restore_host(ctx, C.byref(y), u_out_ptr, u_dtype, w_max, reduce_op,
+                                      C.byref(cond), max_iter, C.byref(job)))
+    return job.value
+
+
 def lsr_result(ctx: int, job: int, wait: bool = True) -> lsr_job_result:
     """Returns the job's result; its own status (OK/ENUMERIC/ECANCELED) is in .status."""
     out = lsr_job_result()
@@ -162,6 +175,17 @@ def lsr_result(ctx: int, job: int, wait: bool = True) -> lsr_job_result:
     if st not in (LSR_OK, LSR_ENUMERIC, LSR_ECANCELED):
         raise LsrError(st, lsr_last_error())
     return out
+
+
+def lsr_wait_any(ctx: int, wait: bool = True) -> int | None:
+    """Id of a finished job whose result is not taken yet; None when wait is False
+    and none has finished (EBUSY). Raises ENOTFOUND when no job is outstanding."""
+    job = C.c_int64()
+    st = lib().lsr_wait_any(ctx, 1 if wait else 0, C.byref(job))
+    if st == LSR_EBUSY:
+        return None
+    _check(st)
+    return job.value
 
 
 def lsr_cancel(ctx: int, job: int) -> None:

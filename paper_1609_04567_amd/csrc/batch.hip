@@ -13,9 +13,12 @@
 // and family depend only on its shape, dtype and condition (see
 // batch_geometry), never on the batch it shares, so the fold order of its
 // reduce and hence every result is the same alone and in a mix.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "tile_jacobi.hpp"
 #include "tile_life.hpp"
+#include "tile_restore.hpp"
 
 namespace lsr {
 namespace {
@@ -23,6 +26,7 @@ namespace {
 constexpr int kBatchThreads = 256;
 constexpr int kWavesPerGroup = kBatchThreads / 64;
 constexpr int kLifeTileRows = 32;
+constexpr int kRestoreTileRows = 16;
 
 template <typename T, int VEC, int K, bool MC>
 __device__ __forceinline__ void jac_tb_tile(const BatchJob& J, const void* src, void* dst,
@@ -87,6 +91,20 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
                                          J.rows, J.cols, J.pitch, J.torus, check, w.tile, J.strips,
                                          J.tile_rows, static_cast<unsigned long long*>(J.partials),
                                          nullptr);
+    if constexpr (KIND == BK_RESTORE_F64 || KIND == BK_RESTORE_F32) {
+        typedef typename std::conditional<KIND == BK_RESTORE_F64, double, float>::type T;
+        __shared__ uint16_t rlist[kWavesPerGroup][kRestoreTileRows * 64];
+        const int band = w.tile / J.strips, strip = w.tile - band * J.strips;
+        const bool is_max = J.ctl.reduce == RED_MAX_ABS;
+        double acc = restore_wave<T, false>(
+            static_cast<const T*>(src), static_cast<T*>(dst), static_cast<const uint8_t*>(J.env),
+            J.rows, J.cols, J.pitch, (T)J.beta, J.quadratic != 0, (int64_t)band * kRestoreTileRows,
+            0, 1, kRestoreTileRows, (int64_t)strip * 64, rlist[wave], check, is_max);
+        if (check) {
+            acc = is_max ? wave_max(acc) : wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) static_cast<double*>(J.partials)[w.tile] = acc;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -328,6 +346,15 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_
     j.tiles = j.strips * (int)((j.rows - 2 + j.tile_rows - 1) / j.tile_rows);
 }
 
+void batch_geometry_restore(BatchJob& j, int f32) {
+    j.step = 1;
+    j.mc = 0;
+    j.kind = f32 ? BK_RESTORE_F32 : BK_RESTORE_F64;
+    j.tile_rows = kRestoreTileRows;
+    j.strips = (int)((j.cols + 63) / 64);
+    j.tiles = j.strips * (int)((j.rows + kRestoreTileRows - 1) / kRestoreTileRows);
+}
+
 hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
                               int nwork_padded, hipStream_t s) {
     if (nwork_padded <= 0) return hipSuccess;
@@ -342,6 +369,8 @@ hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int ki
         case BK_JAC_F64_TB5_MC: launch_kind<BK_JAC_F64_TB5_MC>(jobs, work, groups, s); break;
         case BK_JAC_F32_TB5_MC: launch_kind<BK_JAC_F32_TB5_MC>(jobs, work, groups, s); break;
         case BK_LIFE_SWAR: launch_kind<BK_LIFE_SWAR>(jobs, work, groups, s); break;
+        case BK_RESTORE_F64: launch_kind<BK_RESTORE_F64>(jobs, work, groups, s); break;
+        case BK_RESTORE_F32: launch_kind<BK_RESTORE_F32>(jobs, work, groups, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

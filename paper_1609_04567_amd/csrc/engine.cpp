@@ -78,11 +78,12 @@ void lsr_ctx::engine_teardown() {
 lsr_status lsr_ctx::engine_submit(Job* j) {
     const lsr_grid& g = j->grid;
     const bool life = j->stencil == LSR_ST_LIFE;
+    const bool restore = j->stencil == LSR_ST_RESTORE;
     const bool f32 = g.dtype == LSR_F32;
     j->xgrid = g;
-    // small grids are swept in LDS from any pitch or alignment: staged only when
-    // they live in host memory
-    j->staged = j->host || (!lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
+    // small grids are swept in LDS from any pitch or alignment, restoration at any
+    // pitch: staged only when they live in host memory
+    j->staged = j->host || (!restore && !lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
                             needs_staging(g, j->stencil));
     if (j->staged) j->xgrid.pitch = stage_pitch(g);   // buffers assigned at admission
     lsr::BatchJob& d = j->desc;
@@ -95,6 +96,8 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     d.helm = j->stencil == LSR_ST_HELMHOLTZ5;
     d.torus = g.bc == LSR_BC_TORUS;
     d.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
+    d.beta = g.param[0];
+    d.quadratic = g.param[1] != 0.0;
     lsr::LoopCtl& c = d.ctl;
     c.max_iter = j->max_iter;
     // a check period of at least max_iter leaves only the check at the cap
@@ -113,14 +116,15 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
         std::lock_guard<std::mutex> lk(mu);
         tu = tuned_for(g, j->stencil, j->cond.check_every);
     }
-    lsr::batch_geometry(d, life, f32, tu.tb_depth, tu.tile_rows);
+    if (restore) lsr::batch_geometry_restore(d, f32);
+    else lsr::batch_geometry(d, life, f32, tu.tb_depth, tu.tile_rows);
     c.nparts = d.tiles;
     const size_t esz = dtype_size(g.dtype);
     j->bytes = (size_t)g.rows * (size_t)j->xgrid.pitch * esz;
     int nparts = d.mc ? d.tiles * d.step : d.tiles;
     if (life) {
         nparts = std::max(nparts, lsr::count_u8_parts(g.rows, g.cols));
-    } else {
+    } else if (!restore) {
         // unfused geometry that replays a stop inside a round (rows are aligned:
         // null pointers stand for the buffers, which are not allocated yet)
         lsr::JacobiArgs ra = jacobi_args(j, nullptr, nullptr);
@@ -129,7 +133,10 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
         nparts = std::max(nparts, j->replay_geom.tiles);
     }
     j->nparts_alloc = nparts;
-    const double per_cell = life ? 2.0 : (double)esz * (d.helm ? 3.0 : 2.0);
+    // device time of a round per cell, in bytes at 5 TB/s (restoration: its
+    // measured ALU time per pixel)
+    const double per_cell = life ? 2.0 : restore ? (f32 ? 150.0 : 480.0)
+                                                 : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
     if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");
     return LSR_OK;
@@ -142,6 +149,8 @@ void lsr_ctx::engine_finish(Job* j, lsr_status st) {
     j->result.queue_ms = ms_between(j->t_submit, j->t_admit);
     j->result.latency_ms = ms_between(j->t_submit, j->t_done);
     j->phase = Phase::Finished;
+    done_q.push_back(j->id);
+    --unfinished;
     cv_done.notify_all();
 }
 
@@ -181,13 +190,18 @@ lsr_status lsr_ctx::engine_admit() {
         if (s == LSR_OK) s = pool.alloc((size_t)j->nparts_alloc * 8, &parts);
         if (s == LSR_OK) s = pool.alloc(sizeof(lsr::JobState), &st);
         if (s == LSR_OK && j->staged) s = pool.alloc(j->bytes, &s0);
-        if (s == LSR_OK && j->staged && j->desc.helm) s = pool.alloc(j->bytes, &senv);
+        void* sy = nullptr;
+        const size_t env_bytes = (size_t)j->xgrid.rows * (size_t)j->xgrid.pitch * env_esz(j);
+        if (s == LSR_OK && j->staged && (j->desc.helm || j->stencil == LSR_ST_RESTORE))
+            s = pool.alloc(env_bytes, &senv);
+        if (s == LSR_OK && j->two_phase) s = pool.alloc(env_bytes, &sy);
         if (s != LSR_OK) {
             pool.release(partner);
             pool.release(parts);
             pool.release(st);
             pool.release(s0);
             pool.release(senv);
+            pool.release(sy);
             if (!active.empty() || !retiring.empty() || !ingesting.empty())
                 return LSR_OK;  // wait for memory
             {
@@ -213,6 +227,7 @@ lsr_status lsr_ctx::engine_admit() {
         if (j->staged) {
             j->buf[0] = s0;
             j->stage_env = senv;
+            j->stage_y = sy;
             j->xgrid.data = s0;
             j->xgrid.env0 = senv;
             j->desc.buf[0] = s0;
@@ -251,11 +266,18 @@ lsr_status lsr_ctx::engine_admit() {
             HIP_TRY(hipMemsetAsync(s0, 0, (size_t)g.rows * g.pitch * esz, copy_stream));
             HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, copy_stream));
         }
-        HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz, g.rows,
-                                 hipMemcpyHostToDevice, copy_stream));
-        if (senv)
-            HIP_TRY(hipMemcpy2DAsync(senv, g.pitch * esz, ug.env0, ug.pitch * esz, g.cols * esz,
+        if (j->two_phase) {
+            // the frame only: detection writes the mask and the initial iterate
+            HIP_TRY(hipMemcpy2DAsync(sy, g.pitch, j->in_host, j->host_pitch, g.cols, g.rows,
+                                     hipMemcpyHostToDevice, copy_stream));
+        } else {
+            const size_t ee = env_esz(j);
+            HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
                                      g.rows, hipMemcpyHostToDevice, copy_stream));
+            if (senv)
+                HIP_TRY(hipMemcpy2DAsync(senv, g.pitch * ee, ug.env0, ug.pitch * ee, g.cols * ee,
+                                         g.rows, hipMemcpyHostToDevice, copy_stream));
+        }
         j->ev_in = get_event();
         if (!j->ev_in) return fail(LSR_EDEVICE, "event pool");
         HIP_TRY(hipEventRecord(j->ev_in, copy_stream));
@@ -313,10 +335,16 @@ lsr_status lsr_ctx::engine_activate(Job* j) {
         }
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
                                  g.rows, hipMemcpyDeviceToDevice, stream));
-        if (j->stage_env)
-            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * esz, ug.env0, ug.pitch * esz,
-                                     g.cols * esz, g.rows, hipMemcpyDeviceToDevice, stream));
+        if (j->stage_env) {
+            const size_t ee = env_esz(j);
+            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * ee, ug.env0, ug.pitch * ee,
+                                     g.cols * ee, g.rows, hipMemcpyDeviceToDevice, stream));
+        }
     }
+    if (j->two_phase)   // phase 1 on the device: mask and initial iterate
+        HIP_TRY(lsr::launch_amf_detect(static_cast<const uint8_t*>(j->stage_y), g.rows, g.cols,
+                                       g.pitch, j->w_max, static_cast<uint8_t*>(j->stage_env),
+                                       j->buf[0], g.dtype, stream));
     if (j->stencil == LSR_ST_LIFE) {
         int np = 0;
         HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
@@ -422,9 +450,11 @@ void lsr_ctx::engine_scan() {
             if (e == hipSuccess) e = hipEventRecord(done_ev, stream);
             if (e == hipSuccess) e = hipStreamWaitEvent(copy_stream, done_ev, 0);
             if (done_ev) put_event(done_ev);
+            void* dst = j->two_phase ? j->out_host : ug.data;
+            const size_t dpitch = (size_t)(j->two_phase ? j->host_pitch : ug.pitch) * esz;
             if (e == hipSuccess)
-                e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz,
-                                     g.cols * esz, g.rows, hipMemcpyDeviceToHost, copy_stream);
+                e = hipMemcpy2DAsync(dst, dpitch, j->buf[last], g.pitch * esz, g.cols * esz,
+                                     g.rows, hipMemcpyDeviceToHost, copy_stream);
             if (e == hipSuccess) e = hipEventRecord(j->ev_end, copy_stream);
         } else {
             if (e == hipSuccess && j->staged)

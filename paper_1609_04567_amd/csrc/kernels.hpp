@@ -116,9 +116,11 @@ enum BatchKind : int32_t {
     BK_LIFE_SWAR = 8,      // Life, 16 cells per lane, one generation per round
     BK_SMALL_F64 = 9,      // whole job in LDS, one launch on the engine's second stream: FP64 Jacobi
     BK_SMALL_F32 = 10,     //   FP32 Jacobi
-    BK_SMALL_LIFE = 11     //   Life
+    BK_SMALL_LIFE = 11,    //   Life
+    BK_RESTORE_F64 = 12,   // restoration sweep (phase 2 of Sect. 4.3), FP64, 16 x 64 pixels per tile
+    BK_RESTORE_F32 = 13    //   FP32 storage
 };
-constexpr int kBatchKinds = 11;
+constexpr int kBatchKinds = 13;
 // A grid runs whole-grid-in-LDS when both of its buffers fit in this many bytes
 // (rows * cols * element size * 2; one 1024-thread workgroup per job).
 constexpr int64_t kSmallLdsBytes = 160 * 1024 - 1024;
@@ -135,7 +137,7 @@ inline bool batch_small_fits(int64_t rows, int64_t cols, int esz) {
 // level l's partials are at partials[(l - 1) * tiles + tile].
 struct BatchJob {
     const void* buf[2];
-    const void* env;       // Helmholtz g, or null
+    const void* env;       // Helmholtz g, the restoration mask (u8, grid pitch), or null
     JobState* st;
     void* partials;        // one 8-byte partial per tile
     JobState* mirror;      // device pointer of the pinned host mirror
@@ -143,6 +145,9 @@ struct BatchJob {
     double rd;
     LoopCtl ctl;
     int32_t kind, helm, torus, strips, tiles, tile_rows, step, mc;
+    double beta;           // restoration: phi(t) = sqrt(beta + t^2)
+    int32_t quadratic;     // restoration: phi(t) = t^2 instead
+    int32_t pad_;
 };
 
 struct WorkItem {
@@ -160,6 +165,9 @@ struct WorkItem {
 // wanted values come from the context's tuning table, so the geometry is still
 // a function of the job's own key.
 void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth = 0, int want_tile_rows = 0);
+// The same for a restoration job: one tile = 16 rows x 64 columns (one wavefront),
+// one sweep per round; never whole-grid-in-LDS.
+void batch_geometry_restore(BatchJob& j, int f32);
 // One launch per kernel family: `work` points at that family's segment of the
 // work list (nwork_padded entries, a multiple of 32; idle entries have job -1).
 // A workgroup runs four consecutive entries, one per wavefront.

@@ -17,6 +17,7 @@
 // (a step that leaves the bracket is replaced by its midpoint). Unflagged pixels
 // are never written: both ping-pong buffers hold them from the start.
 #include "kernels.hpp"
+#include "tile_restore.hpp"
 
 namespace lsr {
 namespace {
@@ -89,78 +90,6 @@ __global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
     else static_cast<double*>(u_init)[p] = (double)u;
 }
 
-// ---------------------------------------------------------------------------
-// 1/sqrt(x) for the x = beta + d^2 >= beta > 0 of the update: the hardware
-// estimate refined by Newton's iteration for 1/s^2 = x, s <- s + s (1 - x s^2) / 2,
-// which doubles the correct bits per step (twice for FP64, once for FP32). The
-// correctly rounded sqrt followed by a correctly rounded division cost about
-// three times as many instructions.
-template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
-template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) {
-    double s = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) s = fma(0.5 * s, fma(-x * s, s, 1.0), s);
-    return s;
-}
-template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) {
-    const float s = __builtin_amdgcn_rsqf(x);
-    return fmaf(0.5f * s, fmaf(-x * s, s, 1.0f), s);
-}
-
-// Root of g(t) = sum phi'(t - v_m) on [lo, hi] by bracketed Newton. The eight
-// neighbour slots are fixed (register resident); `valid` marks the in-range ones.
-template <typename T>
-__device__ T restore_argmin(const T (&v)[8], unsigned valid, T beta, bool quadratic, T start) {
-    T lo = T(0), hi = T(0);
-    bool first = true;
-    int cnt = 0;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        if (valid & (1u << m)) {
-            lo = (first || v[m] < lo) ? v[m] : lo;
-            hi = (first || v[m] > hi) ? v[m] : hi;
-            first = false;
-            ++cnt;
-        }
-    }
-    if (!(lo < hi)) return lo;
-    if (quadratic) {
-        T s = T(0);
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (valid & (1u << m)) s = s + v[m];
-        return s / T(cnt);
-    }
-    T t = (start > lo && start < hi) ? start : lo + T(0.5) * (hi - lo);
-    const int max_steps = sizeof(T) == 8 ? 64 : 40;
-    for (int it = 0; it < max_steps; ++it) {
-        T gs = T(0), dg = T(0);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (valid & (1u << m)) {
-                const T d = t - v[m];
-                const T q = beta + d * d;
-                const T s = rsqrt_t<T>(q);
-                gs = gs + d * s;
-                dg = dg + beta * (s * s * s);
-            }
-        }
-        if (gs == T(0)) return t;
-        if (gs < T(0)) lo = t; else hi = t;
-        T tn = t - gs / dg;
-        if (!(tn > lo && tn < hi)) tn = lo + T(0.5) * (hi - lo);
-        const T step = tn - t;
-        t = tn;
-        if (!(hi > lo) || step == T(0)) break;
-        const T tol = (sizeof(T) == 8 ? T(4e-16) : T(2e-7)) * (fabs(t) > T(1) ? fabs(t) : T(1));
-        if (fabs(step) <= tol) break;
-    }
-    return t;
-}
-
 template <typename T, int TR>
 __global__ __launch_bounds__(256) void restore_kernel(
     const T* __restrict__ a, T* __restrict__ b, const uint8_t* __restrict__ mask, int64_t rows,
@@ -174,52 +103,13 @@ __global__ __launch_bounds__(256) void restore_kernel(
     const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
     if (t >= tiles) return;
     const int band = t / strips, strip = t - band * strips;
-    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int ly = threadIdx.x >> 6;
     const bool is_max = ctl.reduce == RED_MAX_ABS;
-    // Wavefront ly owns rows ly, ly + 4, ... of the band (TR / 4 rows of 64
-    // columns). About 40 % of pixels are flagged, so the wavefront first lists
-    // its flagged pixels (row-in-band << 6 | lane) in LDS and then solves them 64
-    // at a time with every lane busy, instead of running each row's Newton loop
-    // with the unflagged lanes idle.
-    constexpr int kPerWave = TR / 4 * 64;
-    __shared__ uint16_t list[4][kPerWave];
-    int n = 0;
-    for (int rr = ly; rr < TR; rr += 4) {
-        const int64_t i = (int64_t)band * TR + rr;
-        const int64_t jx = (int64_t)strip * 64 + lx;
-        const bool flagged = i < rows && jx < cols && mask[i * pitch + jx];
-        const uint64_t ballot = __ballot(flagged);
-        const int pos = n + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
-        if (flagged) list[ly][pos] = (uint16_t)((rr << 6) | lx);
-        n += __popcll(ballot);
-    }
-    __syncthreads();
-    double acc = 0.0;
-    for (int e = lx; e < n; e += 64) {
-        const int code = list[ly][e];
-        const int64_t i = (int64_t)band * TR + (code >> 6);
-        const int64_t jx = (int64_t)strip * 64 + (code & 63);
-        const int64_t p = i * pitch + jx;
-        T v[8];
-        unsigned valid = 0;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int o = m < 4 ? m : m + 1;  // 3x3 box in row order, centre skipped
-            const int64_t ii = i + o / 3 - 1, jj = jx + o % 3 - 1;
-            const bool in = ii >= 0 && jj >= 0 && ii < rows && jj < cols;
-            v[m] = in ? a[ii * pitch + jj] : T(0);
-            valid |= in ? (1u << m) : 0u;
-        }
-        if (valid == 0) continue;
-        const T old = a[p];
-        const T nv = restore_argmin<T>(v, valid, beta, quadratic != 0, old);
-        b[p] = nv;
-        if (check) {
-            const double d = fabs((double)nv - (double)old);
-            acc = is_max ? max_nan(acc, d) : acc + d;
-        }
-    }
+    // wavefront ly owns rows ly, ly + 4, ... of the band
+    __shared__ uint16_t list[4][TR / 4 * 64];
+    const double acc = restore_wave<T, true>(a, b, mask, rows, cols, pitch, beta, quadratic != 0,
+                                             (int64_t)band * TR, ly, 4, TR, (int64_t)strip * 64,
+                                             list[ly], check, is_max);
     if (check) {
         const double s = block_reduce<4>(acc, is_max, lds);
         if (threadIdx.x == 0) partials[t] = s;

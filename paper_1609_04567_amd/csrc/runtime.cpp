@@ -273,9 +273,11 @@ lsr_status lsr_ctx::run_job(Job* j) {
         }
         HIP_TRY(hipMemcpy2DAsync(j->buf[0], g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
                                  g.rows, stage_kind(j, true), stream));
-        if (j->stage_env)
-            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * esz, ug.env0, ug.pitch * esz,
-                                     g.cols * esz, g.rows, stage_kind(j, true), stream));
+        if (j->stage_env) {
+            const size_t ee = env_esz(j);
+            HIP_TRY(hipMemcpy2DAsync(j->stage_env, g.pitch * ee, ug.env0, ug.pitch * ee,
+                                     g.cols * ee, g.rows, stage_kind(j, true), stream));
+        }
     }
     // Partner buffer starts as a copy: boundary ring (Jacobi) and unflagged
     // pixels (restoration) are never rewritten, so both buffers must hold them.
@@ -415,6 +417,8 @@ void lsr_ctx::drive() {
             if (j->slot >= 0) free_slots.push_back(j->slot);
             j->slot = -1;
             j->phase = Phase::Finished;
+            done_q.push_back(j->id);
+            --unfinished;
         }
         cv_done.notify_all();
     }
@@ -492,15 +496,71 @@ lsr_status lsr_run_host(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, 
     return submit(ctx, grid, stencil_id, reduce_op, cond, max_iter, true, job_out);
 }
 
+lsr_status lsr_run_restore_host(lsr_ctx* ctx, const lsr_grid* y, void* u_out, int32_t u_dtype,
+                                int32_t w_max, int32_t reduce_op, const lsr_cond* cond,
+                                int64_t max_iter, lsr_job* job_out) {
+    if (!ctx || !y || !u_out || !job_out) return fail(LSR_EINVAL, "NULL argument");
+    if (!ctx->batched) return fail(LSR_EINVAL, "two-phase host jobs run on a batched context");
+    if (!y->data || y->dtype != LSR_U8) return fail(LSR_EINVAL, "the frame is a U8 image");
+    if (u_dtype != LSR_F32 && u_dtype != LSR_F64) return fail(LSR_EINVAL, "u_dtype is F32 or F64");
+    if (w_max < 3 || w_max > 31 || w_max % 2 == 0) return fail(LSR_EINVAL, "w_max must be odd in [3, 31]");
+    // the restoration job on the frame's shape; its mask is made on the device
+    lsr_grid ug = *y;
+    ug.dtype = u_dtype;
+    ug.data = u_out;
+    ug.env0 = y->data;
+    lsr_status v = validate(&ug, LSR_ST_RESTORE, reduce_op, cond, max_iter);
+    if (v != LSR_OK) return v;
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::unique_ptr<Job> j(new Job());
+    j->host = true;
+    j->two_phase = true;
+    j->w_max = w_max;
+    j->in_host = y->data;
+    j->out_host = u_out;
+    j->host_pitch = y->pitch;
+    j->grid = ug;
+    j->xgrid = ug;
+    j->stencil = LSR_ST_RESTORE;
+    j->cond = *cond;
+    j->max_iter = max_iter;
+    j->ctl.reduce = reduce_op;
+    return submit_batched(ctx, std::move(j), job_out);
+}
+
 }  // extern "C"
+
+// Queues a job on a batched context (its descriptor from engine_submit).
+lsr_status lsr_rt::submit_batched(lsr_ctx* ctx, std::unique_ptr<Job> j, lsr_job* job_out) {
+    lsr_status s = ctx->engine_submit(j.get());
+    if (s != LSR_OK) return s;
+    if (hipEventCreateWithFlags(&j->ev_user, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&j->ev_begin) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
+        hipEventRecord(j->ev_user, ctx->user_stream) != hipSuccess) {
+        if (j->ev_user) (void)hipEventDestroy(j->ev_user);
+        if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
+        if (j->ev_end) (void)hipEventDestroy(j->ev_end);
+        return fail(LSR_EDEVICE, "event setup failed");
+    }
+    j->t_submit = j->t_admit = Clock::now();
+    Job* raw = j.get();
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        raw->id = ctx->next_id++;
+        ctx->jobs[raw->id] = std::move(j);
+        ++ctx->unfinished;
+        ctx->pending.push_back(raw);
+    }
+    ctx->cv_work.notify_one();
+    *job_out = raw->id;
+    return LSR_OK;
+}
 
 lsr_status lsr_rt::submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
                           const lsr_cond* cond, int64_t max_iter, bool host, lsr_job* job_out) {
     if (!ctx || !job_out) return fail(LSR_EINVAL, "ctx and job_out must not be NULL");
     lsr_status v = validate(grid, stencil_id, reduce_op, cond, max_iter);
     if (v != LSR_OK) return v;
-    if (host && stencil_id == LSR_ST_RESTORE)
-        return fail(LSR_EINVAL, "restoration jobs take device pointers (lsr_run)");
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<Job> j(new Job());
     j->host = host;
@@ -510,30 +570,8 @@ lsr_status lsr_rt::submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id
     j->cond = *cond;
     j->max_iter = max_iter;
     if (ctx->batched) {
-        if (stencil_id == LSR_ST_RESTORE)
-            return fail(LSR_EINVAL, "restoration jobs run on a plain (non-batched) context");
         j->ctl.reduce = reduce_op;
-        lsr_status s = ctx->engine_submit(j.get());
-        if (s != LSR_OK) return s;
-        if (hipEventCreateWithFlags(&j->ev_user, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreate(&j->ev_begin) != hipSuccess || hipEventCreate(&j->ev_end) != hipSuccess ||
-            hipEventRecord(j->ev_user, ctx->user_stream) != hipSuccess) {
-            if (j->ev_user) (void)hipEventDestroy(j->ev_user);
-            if (j->ev_begin) (void)hipEventDestroy(j->ev_begin);
-            if (j->ev_end) (void)hipEventDestroy(j->ev_end);
-            return fail(LSR_EDEVICE, "event setup failed");
-        }
-        j->t_submit = j->t_admit = Clock::now();
-        Job* raw = j.get();
-        {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-            raw->id = ctx->next_id++;
-            ctx->jobs[raw->id] = std::move(j);
-            ctx->pending.push_back(raw);
-        }
-        ctx->cv_work.notify_one();
-        *job_out = raw->id;
-        return LSR_OK;
+        return submit_batched(ctx, std::move(j), job_out);
     }
     lsr_tuning tun;
     {
@@ -643,7 +681,9 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
     lsr_status st = LSR_OK;
     if (j->staged) {
         st = ctx->pool.alloc(bytes, &j->buf[0]);
-        if (st == LSR_OK && stencil_id == LSR_ST_HELMHOLTZ5) st = ctx->pool.alloc(bytes, &j->stage_env);
+        if (st == LSR_OK && (stencil_id == LSR_ST_HELMHOLTZ5 || stencil_id == LSR_ST_RESTORE))
+            st = ctx->pool.alloc((size_t)grid->rows * (size_t)j->xgrid.pitch * env_esz(j.get()),
+                                 &j->stage_env);
         j->xgrid.data = j->buf[0];
         j->xgrid.env0 = j->stage_env;
     } else {
@@ -690,6 +730,7 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
         std::lock_guard<std::mutex> lk(ctx->mu);
         raw->id = ctx->next_id++;
         ctx->jobs[raw->id] = std::move(j);
+        ++ctx->unfinished;
         ctx->queue.push_back(raw);
     }
     ctx->cv_work.notify_one();
@@ -713,6 +754,14 @@ lsr_status lsr_result(lsr_ctx* ctx, lsr_job job, int32_t wait, lsr_job_result* o
         }
         j = std::move(it->second);
         ctx->jobs.erase(it);
+        // ids whose results were taken here stay in the completion queue until
+        // lsr_wait_any skips them; drop them when they dominate it
+        if (ctx->done_q.size() > 2 * ctx->jobs.size() + 1024) {
+            std::deque<lsr_job> keep;
+            for (lsr_job id : ctx->done_q)
+                if (ctx->jobs.count(id)) keep.push_back(id);
+            ctx->done_q.swap(keep);
+        }
     }
     *out = j->result;
     (void)hipSetDevice(ctx->device);
@@ -725,6 +774,24 @@ lsr_status lsr_result(lsr_ctx* ctx, lsr_job job, int32_t wait, lsr_job_result* o
     else if (s == LSR_ENUMERIC) g_last_error = "reduce value became NaN or Inf";
     else if (s == LSR_ECANCELED) g_last_error = "job cancelled";
     return s;
+}
+
+lsr_status lsr_wait_any(lsr_ctx* ctx, int32_t wait, lsr_job* job_out) {
+    if (!ctx || !job_out) return fail(LSR_EINVAL, "ctx and job_out must not be NULL");
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    while (true) {
+        while (!ctx->done_q.empty()) {
+            const lsr_job id = ctx->done_q.front();
+            ctx->done_q.pop_front();
+            if (ctx->jobs.count(id)) {   // not yet taken by lsr_result
+                *job_out = id;
+                return LSR_OK;
+            }
+        }
+        if (ctx->unfinished == 0) return fail(LSR_ENOTFOUND, "no job is outstanding");
+        if (!wait) return fail(LSR_EBUSY, "no job has finished");
+        ctx->cv_done.wait(lk);
+    }
 }
 
 lsr_status lsr_cancel(lsr_ctx* ctx, lsr_job job) {

@@ -186,6 +186,15 @@ struct Job {
     // back by a D2H copy when it retires.
     bool host = false;
     hipEvent_t ev_in = nullptr;         // batched engine: end of a host job's H2D copies
+    // A two-phase restoration job (lsr_run_restore_host): the host frame y is
+    // copied into stage_y, detection writes the mask (stage_env) and the initial
+    // iterate (buf[0]) on the device, and the restored frame goes back to out_host.
+    bool two_phase = false;
+    int w_max = 0;
+    void* stage_y = nullptr;
+    const void* in_host = nullptr;      // the frame (u8, pitch host_pitch)
+    void* out_host = nullptr;           // the result (grid dtype, pitch host_pitch)
+    int64_t host_pitch = 0;
     void* stage_env = nullptr;
     void* partials = nullptr;
     lsr::JobState* st = nullptr;
@@ -226,7 +235,8 @@ struct Job {
         if (staged) {
             pool.release(buf[0]);
             pool.release(stage_env);
-            buf[0] = stage_env = nullptr;
+            pool.release(stage_y);
+            buf[0] = stage_env = stage_y = nullptr;
         }
         buf[1] = partials = nullptr;
         st = nullptr;
@@ -292,6 +302,8 @@ struct lsr_ctx {
     std::deque<lsr_rt::Job*> queue;
     std::unordered_map<lsr_job, std::unique_ptr<lsr_rt::Job>> jobs;
     lsr_job next_id = 1;
+    std::deque<lsr_job> done_q;         // finished jobs in completion order (lsr_wait_any)
+    int64_t unfinished = 0;             // jobs submitted and not finished yet (under mu)
     bool stopping = false;
     std::thread driver;
 
@@ -349,9 +361,16 @@ lsr_status finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::Loop
 lsr_status submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
                         int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
                         int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out);
+// Queues a job on a batched context: engine descriptor, events, the pending queue.
+lsr_status submit_batched(lsr_ctx* ctx, std::unique_ptr<Job> j, lsr_job* job_out);
 // lsr_run and lsr_run_host: validation, then the plain or the batched submission.
 lsr_status submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id, int32_t reduce_op,
                   const lsr_cond* cond, int64_t max_iter, bool host, lsr_job* job_out);
+// Element size of a job's env array: the restoration mask is u8, Helmholtz g has
+// the grid's dtype.
+inline size_t env_esz(const Job* j) {
+    return j->stencil == LSR_ST_RESTORE ? 1 : dtype_size(j->grid.dtype);
+}
 // Copy direction of a staged job's copy into (in = true) or out of its device grid.
 inline hipMemcpyKind stage_kind(const Job* j, bool in) {
     if (!j->host) return hipMemcpyDeviceToDevice;

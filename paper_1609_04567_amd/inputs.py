@@ -132,7 +132,8 @@ class HelmholtzInput:
     h: float
 
 
-def _helm_factor(n: int):
+def helmholtz_factor(n: int):
+    """The 1-D factor s_i = sin(pi x_i), x_i = i/(N-1), with exact zeros at both ends, and h."""
     h = 1.0 / (n - 1)
     x = np.arange(n, dtype=np.float64) * h
     s = np.sin(np.pi * x)
@@ -143,7 +144,7 @@ def _helm_factor(n: int):
 
 def helmholtz_input(n: int, alpha: float = 1.0) -> HelmholtzInput:
     """N x N lattice including the ring, x_i = i/(N-1), h = 1/(N-1)."""
-    s, h = _helm_factor(n)
+    s, h = helmholtz_factor(n)
     ustar = np.ascontiguousarray(np.outer(s, s))
     f = (2.0 * np.pi * np.pi + alpha) * ustar
     g = np.ascontiguousarray((h * h) * f)
@@ -156,7 +157,7 @@ def helmholtz_fill(u0: np.ndarray, g: np.ndarray, alpha: float = 1.0) -> float:
     and g = h^2 f, evaluated per element in FP64 exactly as helmholtz_input does
     (a block of rows at a time), then stored. Returns h."""
     n = u0.shape[0]
-    s, h = _helm_factor(n)
+    s, h = helmholtz_factor(n)
     u0[...] = 0
     c = 2.0 * np.pi * np.pi + alpha
     hh = h * h
@@ -173,31 +174,17 @@ def helmholtz_fill(u0: np.ndarray, g: np.ndarray, alpha: float = 1.0) -> float:
 # ---------------------------------------------------------------------------
 # Game of Life soup.
 # ---------------------------------------------------------------------------
-def life_fill(out: np.ndarray, seed: int = 3, density: float = 0.3) -> np.ndarray:
-    """Writes the Life soup into a 2-D uint8 array: cell (i, j) is 1 iff draw
-    i*cols + j, as a double in [0, 1), is below the density.
-
-    The test (x >> 11) * 2**-53 < d is evaluated on the integer draw: the scaling
-    by a power of two is exact, so it holds iff (x >> 11) < ceil(d * 2**53), i.e.
-    iff x < ceil(d * 2**53) * 2**11."""
-    rows, cols = out.shape
-    if not out.flags.c_contiguous or out.dtype != np.uint8:
-        raise ValueError("life_fill writes a C-contiguous uint8 array")
-    flat = out.reshape(-1)
-    if density >= 1.0 or density <= 0.0:
-        flat[...] = 1 if density >= 1.0 else 0
-        return out
-    lim = np.uint64(math.ceil(density * 2.0 ** 53) << 11)
+def _mixed_blocks(seed: int, start: int, count: int, blk: int = 1 << 16):
+    """Yields (offset, uint64 view) covering draws start .. start+count-1 of the stream,
+    a block at a time (the view is reused between blocks)."""
     s = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
-    blk = 1 << 16
     z = np.empty(blk, dtype=np.uint64)
     t = np.empty(blk, dtype=np.uint64)
-    total = rows * cols
     with np.errstate(over="ignore"):
-        for lo in range(0, total, blk):
-            m = min(blk, total - lo)
+        for lo in range(0, count, blk):
+            m = min(blk, count - lo)
             zz, tt = z[:m], t[:m]
-            zz[...] = np.arange(lo + 1, lo + m + 1, dtype=np.uint64)
+            zz[...] = np.arange(start + lo + 1, start + lo + m + 1, dtype=np.uint64)
             np.multiply(zz, GAMMA, out=zz)
             np.add(zz, s, out=zz)
             for sh, mul in ((30, _M1), (27, _M2)):
@@ -206,7 +193,29 @@ def life_fill(out: np.ndarray, seed: int = 3, density: float = 0.3) -> np.ndarra
                 np.multiply(zz, mul, out=zz)
             np.right_shift(zz, np.uint64(31), out=tt)
             np.bitwise_xor(zz, tt, out=zz)
-            np.less(zz, lim, out=flat[lo:lo + m].view(np.bool_))
+            yield lo, zz
+
+
+def _below_limit(p: float) -> np.uint64:
+    """The draw x satisfies (x >> 11) * 2**-53 < p iff x < this limit (0 < p < 1): the
+    scaling by a power of two is exact, so the test is (x >> 11) < ceil(p * 2**53)."""
+    return np.uint64(math.ceil(p * 2.0 ** 53) << 11)
+
+
+def life_fill(out: np.ndarray, seed: int = 3, density: float = 0.3) -> np.ndarray:
+    """Writes the Life soup into a 2-D uint8 array: cell (i, j) is 1 iff draw
+    i*cols + j, as a double in [0, 1), is below the density (tested on the integer
+    draw, see _below_limit)."""
+    rows, cols = out.shape
+    if not out.flags.c_contiguous or out.dtype != np.uint8:
+        raise ValueError("life_fill writes a C-contiguous uint8 array")
+    flat = out.reshape(-1)
+    if density >= 1.0 or density <= 0.0:
+        flat[...] = 1 if density >= 1.0 else 0
+        return out
+    lim = _below_limit(density)
+    for lo, zz in _mixed_blocks(seed, 0, rows * cols):
+        np.less(zz, lim, out=flat[lo:lo + len(zz)].view(np.bool_))
     return out
 
 
@@ -320,3 +329,53 @@ def poisson_arrivals(jobs: list[JobSpec], rate: float) -> np.ndarray:
     """Arrival times (s) from the jobs' own uniforms: gap = -ln(1 - U) / rate."""
     gaps = np.array([-math.log1p(-j.arrival_u) / rate for j in jobs], dtype=np.float64)
     return np.cumsum(gaps)
+
+
+# ---------------------------------------------------------------------------
+# Noisy video stream (restoration of a stream of frames).
+# ---------------------------------------------------------------------------
+def video_frame(rows: int, cols: int, f: int, seed: int = 8, noise: float = 0.3,
+                blobs: int = 8) -> RestoreInput:
+    """Frame f of a synthetic video: a sum of separable Gaussian blobs whose centres
+    move at constant velocities, mapped to [16, 239], then salt-and-pepper impulses.
+
+    Draw layout: blob b uses draws 6b..6b+5 (amplitude in [-1,1), centre row, centre
+    column, width in [W/16, W/4), row and column velocity in [-2, 2) pixels per
+    frame); blob b of frame f is amp * exp(-(r - cr)^2 / 2s^2) exp(-(c - cc)^2 / 2s^2)
+    (an outer product) with the centre moved by f times the velocity. Each frame is
+    mapped to [16, 239] on its own (round half to even). Pixel p of frame f uses
+    draws 6*blobs + 2*(f*rows*cols + p) (impulse iff < noise) and the next one (salt
+    iff < 0.5, else pepper)."""
+    w = float(max(rows, cols))
+    d = uniform01(seed, 0, 6 * blobs)
+    r = np.arange(rows, dtype=np.float64)
+    c = np.arange(cols, dtype=np.float64)
+    field = np.zeros((rows, cols), dtype=np.float64)
+    for b in range(blobs):
+        amp = 2.0 * d[6 * b] - 1.0
+        sig = w / 16.0 + d[6 * b + 3] * (w / 4.0 - w / 16.0)
+        cr = d[6 * b + 1] * rows + f * (4.0 * d[6 * b + 4] - 2.0)
+        cc = d[6 * b + 2] * cols + f * (4.0 * d[6 * b + 5] - 2.0)
+        er = amp * np.exp(-(r - cr) ** 2 / (2.0 * sig * sig))
+        ec = np.exp(-(c - cc) ** 2 / (2.0 * sig * sig))
+        field += np.outer(er, ec)
+    lo, hi = field.min(), field.max()
+    scale = 223.0 / (hi - lo) if hi > lo else 0.0
+    clean = np.rint(16.0 + (field - lo) * scale).astype(np.uint8)
+    npx = rows * cols
+    hit = np.empty(npx, dtype=bool)
+    salt = np.empty(npx, dtype=bool)
+    lim_hit = _below_limit(noise) if 0.0 < noise < 1.0 else None
+    lim_salt = _below_limit(0.5)
+    for lo2, zz in _mixed_blocks(seed, 6 * blobs + 2 * f * npx, 2 * npx):
+        p0 = lo2 // 2
+        m = len(zz) // 2
+        if lim_hit is None:
+            hit[p0:p0 + m] = noise >= 1.0
+        else:
+            np.less(zz[0::2], lim_hit, out=hit[p0:p0 + m])
+        np.less(zz[1::2], lim_salt, out=salt[p0:p0 + m])
+    y = clean.reshape(-1).copy()
+    y[hit & salt] = 255
+    y[hit & ~salt] = 0
+    return RestoreInput(y=y.reshape(rows, cols), clean=clean, impulse=hit.reshape(rows, cols))

@@ -171,12 +171,51 @@ def test_host_job_larger_than_budget_fails_cleanly():
         assert ei.value.status in (L.LSR_EBUSY, L.LSR_ENOMEM)
 
 
-def test_host_restore_is_rejected(ctx):
-    say("host restore rejected")
-    u = np.zeros((8, 8))
-    m = np.zeros((8, 8), dtype=np.uint8)
-    with pytest.raises(L.LsrError) as ei:
-        ctx.submit_host(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA,
-                        L.make_cond(L.LSR_COND_BELOW, 0.1, 1), 10, L.LSR_BC_BOTTOM, env0=m,
-                        param=(100.0, 0.0))
-    assert ei.value.status == L.LSR_EINVAL
+def test_host_restore_job_matches_device_job(ctx):
+    """Phase 2 of the restoration on host buffers (mask staged as u8 with the
+    grid's pitch) gives the device job's field bit for bit."""
+    say("host restore job")
+    rin = I.restore_input(90, 70, seed=11)
+    m, u0 = O.amf_detect(rin.y, 19)
+    kw = dict(stencil_id=L.LSR_ST_RESTORE, reduce_op=L.LSR_RED_MAX_ABS_DELTA,
+              cond=L.make_cond(L.LSR_COND_BELOW, 0.1, 1), max_iter=200, bc=L.LSR_BC_BOTTOM,
+              param=(100.0, 0.0))
+    for dt in (np.float64, np.float32):
+        g = _host(u0.astype(dt), True)
+        r = ctx.result(_submit_host(ctx, g, _host(m, True), kw))
+        x, rd = _run_device(ctx, u0.astype(dt), m, kw)
+        assert r.status == L.LSR_OK and r.iterations == rd.iterations
+        assert np.array_equal(g.numpy(), x)
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_wait_any_reports_each_finished_job_once(batched):
+    import torch
+    say(f"wait_any batched={batched}")
+    with L.Context(0, batched=batched) as c:
+        jobs = {}
+        for k, (kind, side, seed, f32, mi) in enumerate(CASES):
+            a, env, kw, ora = _spec(kind, side, seed, f32, mi)
+            t = _host(a, True)
+            e = _host(env, True) if env is not None else None
+            jobs[_submit_host(c, t, e, kw)] = (kind, f32, a, env, kw, ora, t)
+        ids = list(jobs)
+        taken = ids[3]
+        c.result(taken)                 # taken directly: never reported
+        seen = []
+        while True:
+            try:
+                jid = c.wait_any(True)
+            except L.LsrError as ex:
+                assert ex.status == L.LSR_ENOTFOUND
+                break
+            seen.append(jid)
+            r = c.result(jid)
+            kind, f32, a, env, kw, ora, t = jobs[jid]
+            dev = _run_device_plain(a, env, kw) if f32 else None
+            _check(kind, f32, t.numpy(), r, ora, dev)
+        assert sorted(seen) == sorted(i for i in ids if i != taken)
+        with pytest.raises(L.LsrError) as ei:
+            c.wait_any(False)
+        assert ei.value.status == L.LSR_ENOTFOUND
+        torch.cuda.synchronize()

@@ -95,3 +95,22 @@ def test_fill_forms_match_the_draw_definitions():
         g64 = np.empty((n, n))
         I.helmholtz_fill(np.empty((n, n)), g64)
         assert np.array_equal(g64, (h.h * h.h) * ((2 * np.pi ** 2 + 1.0) * np.outer(h.s, h.s)))
+
+
+def test_video_frame_recipe():
+    """Draw layout and ranges of the video frames: impulses follow draws
+    6*blobs + 2*(f*npx + p) and the next one, as doubles against the rates."""
+    rows, cols, blobs = 37, 53, 8
+    for f, noise in ((0, 0.3), (4, 0.7)):
+        v = I.video_frame(rows, cols, f, seed=8, noise=noise)
+        npx = rows * cols
+        u = I.uniform01(8, 6 * blobs + 2 * f * npx, 2 * npx).reshape(-1, 2)
+        hit = (u[:, 0] < noise).reshape(rows, cols)
+        salt = (u[:, 1] < 0.5).reshape(rows, cols)
+        assert np.array_equal(v.impulse, hit)
+        assert np.all(v.y[hit & salt] == 255) and np.all(v.y[hit & ~salt] == 0)
+        assert np.array_equal(v.y[~hit], v.clean[~hit])
+        assert v.clean.min() == 16 and v.clean.max() == 239
+    # the blobs move: consecutive frames differ, but only a little
+    a, b = I.video_frame(64, 64, 0).clean, I.video_frame(64, 64, 1).clean
+    assert 0 < np.abs(a.astype(int) - b.astype(int)).max() < 40
