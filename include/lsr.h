@@ -309,6 +309,33 @@ lsr_status lsr_wait_any(lsr_ctx *ctx, int32_t wait, lsr_job *job_out);
 lsr_status lsr_cancel(lsr_ctx *ctx, lsr_job job);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lsr_run followed by a waiting
+ * lsr_result, with the job's scratch (partner grid, per-tile partials, loop state)
+ * taken from one fixed device array of LSR_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, instead of the pool.
+ *  - Allocates nothing: no device or pinned memory, no graph, no event. Runs on
+ *    the context's stream (lsr_config.stream), after the work already enqueued on
+ *    it, and returns once the job has finished and its last iterate is in
+ *    grid->data; the result is written to *out.
+ *  - Same arguments, checks and supported combinations as lsr_run (device
+ *    pointers), and the same kernels, so results are bit for bit those of lsr_run.
+ *    EINVAL also when the partner grid plus partials exceed the scratch
+ *    (rows * pitch * element size must stay below LSR_NOALLOC_SCRATCH_BYTES minus
+ *    the partials), or when the grid would need staged copies (rows not 16-byte
+ *    aligned; Life rows not a multiple of 16 cells).
+ *  - out->device_ms and out->latency_ms are host wall time of the call.
+ *  - Every call on one device shares that device's array: calls that overlap on
+ *    one device (from several threads, or on streams that run concurrently) race
+ *    and give wrong results. Calls in sequence are safe: each job initialises all
+ *    the scratch it reads.
+ */
+#define LSR_NOALLOC_SCRATCH_BYTES ((uint64_t)65 << 20)
+lsr_status lsr_run_noalloc(lsr_ctx *ctx, const lsr_grid *grid, int32_t stencil_id,
+                           int32_t reduce_op, const lsr_cond *cond, int64_t max_iter,
+                           lsr_job_result *out);
+
+/*
  * Adaptive-median impulse detection, phase 1 of the two-phase restoration (Sect. 4.3;
  * a window grown up to a static bound, Sect. 3.2). For each pixel of the u8 image y,
  * windows w = 3, 5, ..., w_max of in-range pixels are tried; med is the lower median

@@ -14,7 +14,7 @@ from ._native import (  # noqa: F401
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
-    lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_restore_host,
+    lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_noalloc, lsr_run_restore_host,
     lsr_set_tuning, lsr_tune_export, lsr_tune_import, lsr_version, lsr_wait_any, make_cond, make_grid,
 )
 
@@ -125,6 +125,11 @@ class Context:
                                    cond, max_iter)
         self._keep[job] = (y, u_out)
         return job
+
+    def run_noalloc(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+        """The job on the library's fixed scratch, synchronously (lsr_run_noalloc)."""
+        g = grid_from_tensor(grid_t, bc, env0, param)
+        return lsr_run_noalloc(self.handle, g, stencil_id, reduce_op, cond, max_iter)
 
     def result(self, job, wait=True):
         r = lsr_result(self.handle, job, wait)

@@ -79,6 +79,8 @@ _SIGS = {
     "lsr_run_restore_host": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_void_p, C.c_int32,
                                        C.c_int32, C.c_int32, C.POINTER(lsr_cond), C.c_int64,
                                        C.POINTER(C.c_int64)]),
+    "lsr_run_noalloc": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_int32, C.c_int32,
+                                  C.POINTER(lsr_cond), C.c_int64, C.POINTER(lsr_job_result)]),
     "lsr_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(lsr_job_result)]),
     "lsr_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "lsr_wait_any": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
@@ -166,6 +168,17 @@ def lsr_run_restore_host(ctx: int, y: lsr_grid, u_out_ptr: int, u_dtype: int, w_
     _check(lib().lsr_run_restore_host(ctx, C.byref(y), u_out_ptr, u_dtype, w_max, reduce_op,
                                       C.byref(cond), max_iter, C.byref(job)))
     return job.value
+
+
+def lsr_run_noalloc(ctx: int, grid: lsr_grid, stencil_id: int, reduce_op: int, cond: lsr_cond,
+                    max_iter: int) -> lsr_job_result:
+    """lsr_run + a waiting lsr_result on the library's fixed scratch (no allocation)."""
+    out = lsr_job_result()
+    st = lib().lsr_run_noalloc(ctx, C.byref(grid), stencil_id, reduce_op, C.byref(cond), max_iter,
+                               C.byref(out))
+    if st not in (LSR_OK, LSR_ENUMERIC):
+        raise LsrError(st, lsr_last_error())
+    return out
 
 
 def lsr_result(ctx: int, job: int, wait: bool = True) -> lsr_job_result:

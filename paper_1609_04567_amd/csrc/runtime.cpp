@@ -444,6 +444,8 @@ lsr_status lsr_create(const lsr_config* cfg, lsr_ctx** out) {
     if (e != hipSuccess || ndev == 0) return fail(LSR_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
     if (cfg->device < 0 || cfg->device >= ndev) return fail(LSR_EINVAL, "device %d out of range", cfg->device);
     HIP_TRY(hipSetDevice(cfg->device));
+    lsr_status ns = noalloc_setup(cfg->device);
+    if (ns != LSR_OK) return ns;
     std::unique_ptr<lsr_ctx> c(new lsr_ctx());
     c->device = cfg->device;
     c->user_stream = static_cast<hipStream_t>(cfg->stream);

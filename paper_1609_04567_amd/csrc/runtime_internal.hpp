@@ -361,6 +361,9 @@ lsr_status finish_fused(Job* j, const lsr::JobState& fin, int K, const lsr::Loop
 lsr_status submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_grid* grid,
                         int32_t stencil_id, int32_t reduce_op, const lsr_cond* cond,
                         int64_t max_iter, const lsr_tuning& tun, lsr_job* job_out);
+// Records the device address of lsr_run_noalloc's scratch array on `device`
+// (current); called once per context creation.
+lsr_status noalloc_setup(int device);
 // Queues a job on a batched context: engine descriptor, events, the pending queue.
 lsr_status submit_batched(lsr_ctx* ctx, std::unique_ptr<Job> j, lsr_job* job_out);
 // lsr_run and lsr_run_host: validation, then the plain or the batched submission.
