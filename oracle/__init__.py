@@ -64,6 +64,8 @@ def _load():
         lib.orc_restore_run.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int,
                                         C.c_int, C.c_double, C.c_int, C.c_int64, P, C.c_int64,
                                         C.POINTER(_Res)]
+        lib.orc_sobel_run.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int64, P, C.c_int64,
+                                      C.POINTER(_Res)]
         lib.orc_restore_argmin.argtypes = [P, C.c_int, C.c_double, C.c_int]
         lib.orc_restore_argmin.restype = C.c_double
         lib.orc_threads.restype = C.c_int
@@ -161,3 +163,18 @@ def restore_run(u: np.ndarray, mask: np.ndarray, *, beta: float = 100.0, quadrat
 def restore_argmin(v, beta: float = 100.0, quadratic: bool = False) -> float:
     v = np.ascontiguousarray(v, dtype=np.float64)
     return float(_load().orc_restore_argmin(_ptr(v), len(v), float(beta), int(quadratic)))
+
+
+def sobel_run(a: np.ndarray, *, check_every: int = 1, max_iter: int = 1,
+              trace_cap: int = 0) -> tuple[np.ndarray, OracleResult]:
+    """Sobel magnitude sweeps of a u8 image (Sect. 4.2): floor(sqrt(Gx^2 + Gy^2))
+    clamped to 255, outside samples 0; the reduce is the sum of the new image."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.uint8).copy()
+    trace = np.zeros(max(trace_cap, 1), dtype=np.uint64)
+    res = _Res()
+    rc = lib.orc_sobel_run(_ptr(a), a.shape[0], a.shape[1], int(check_every), int(max_iter),
+                           _ptr(trace), int(trace_cap), C.byref(res))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return a, _result(res, trace[:trace_cap])

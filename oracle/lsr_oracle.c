@@ -358,3 +358,78 @@ int orc_restore_run(double *u, const uint8_t *mask, int64_t rows, int64_t cols, 
     free(nxt);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Sobel edge detector (Sect. 4.2): a single-iteration stencil on a u8 image.  */
+/* Gx and Gy are the two 3x3 Sobel derivative masks; a sample outside the     */
+/* image is bottom and counts as 0 (the convention of Fig. 1). The output is  */
+/* the gradient magnitude floor(sqrt(Gx^2 + Gy^2)) clamped to 255, computed   */
+/* exactly in integers. The reduce is the plain variant over the new image:   */
+/* the sum of its values (u64).                                               */
+/* ------------------------------------------------------------------------- */
+
+static int pixel_or_zero(const uint8_t *a, int64_t rows, int64_t cols, int64_t i, int64_t j) {
+    if (i < 0 || j < 0 || i >= rows || j >= cols) return 0;
+    return a[i * cols + j];
+}
+
+static int isqrt_floor(int m) {
+    int s = 0;
+    while ((s + 1) * (s + 1) <= m) s = s + 1;
+    return s;
+}
+
+static void sobel_sweep(const uint8_t *a, uint8_t *b, int64_t rows, int64_t cols) {
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < rows; ++i) {
+        for (int64_t j = 0; j < cols; ++j) {
+            int nw = pixel_or_zero(a, rows, cols, i - 1, j - 1);
+            int n = pixel_or_zero(a, rows, cols, i - 1, j);
+            int ne = pixel_or_zero(a, rows, cols, i - 1, j + 1);
+            int w = pixel_or_zero(a, rows, cols, i, j - 1);
+            int e = pixel_or_zero(a, rows, cols, i, j + 1);
+            int sw = pixel_or_zero(a, rows, cols, i + 1, j - 1);
+            int s = pixel_or_zero(a, rows, cols, i + 1, j);
+            int se = pixel_or_zero(a, rows, cols, i + 1, j + 1);
+            int gx = (ne + 2 * e + se) - (nw + 2 * w + sw);
+            int gy = (sw + 2 * s + se) - (nw + 2 * n + ne);
+            int mag = isqrt_floor(gx * gx + gy * gy);
+            b[i * cols + j] = (uint8_t)(mag > 255 ? 255 : mag);
+        }
+    }
+}
+
+static uint64_t value_sum(const uint8_t *a, int64_t rows, int64_t cols) {
+    uint64_t total = 0;
+    for (int64_t i = 0; i < rows * cols; ++i) total += a[i];
+    return total;
+}
+
+int orc_sobel_run(uint8_t *a, int64_t rows, int64_t cols, int check_every, int64_t max_iter,
+                  uint64_t *trace, int64_t trace_cap, orc_result *out) {
+    if (!a || !out || rows < 1 || cols < 1 || check_every < 1 || max_iter < 1) return -1;
+    size_t bytes = (size_t)(rows * cols);
+    uint8_t *cur = (uint8_t *)malloc(bytes), *nxt = (uint8_t *)malloc(bytes);
+    memcpy(cur, a, bytes);
+    memset(out, 0, sizeof *out);
+    out->r = NAN;
+    int64_t n = 0;
+    do {
+        sobel_sweep(cur, nxt, rows, cols);
+        n = n + 1;
+        if (is_check_sweep(n, check_every, max_iter)) {
+            uint64_t total = value_sum(nxt, rows, cols);
+            if (trace && out->checks < trace_cap) trace[out->checks] = total;
+            out->checks += 1;
+            out->count = total;
+            out->r = (double)total;
+        }
+        uint8_t *t = cur; cur = nxt; nxt = t;
+    } while (n < max_iter);
+    memcpy(a, cur, bytes);
+    out->n = n;
+    free(cur);
+    free(nxt);
+    return 0;
+}

@@ -100,6 +100,17 @@ int orc_restore_run(double *u, const uint8_t *mask, int64_t rows, int64_t cols, 
 /* One restoration update of a single pixel from explicit neighbour values. */
 double orc_restore_argmin(const double *v, int count, double beta, int quadratic);
 
+/*
+ * Sobel edge detector (Sect. 4.2) as a loop-of-stencil-reduce on a u8 image:
+ * each sweep writes floor(sqrt(Gx^2 + Gy^2)) clamped to 255 for every pixel,
+ * where Gx, Gy are the 3x3 Sobel derivative masks and samples outside the image
+ * are 0; at a check (every check_every sweeps and at max_iter) the reduce is the
+ * sum of the new image's values (u64, in out->count and out->r). The paper's use
+ * is max_iter = 1. a is updated in place with the last image.
+ */
+int orc_sobel_run(uint8_t *a, int64_t rows, int64_t cols, int check_every, int64_t max_iter,
+                  uint64_t *trace, int64_t trace_cap, orc_result *out);
+
 #ifdef __cplusplus
 }
 #endif
