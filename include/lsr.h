@@ -76,10 +76,14 @@ typedef enum {
                                F32 storage needs alpha*h*h in [-4/3, 4] (EINVAL otherwise): its
                                stochastically rounded update relies on |0.25 - rd| <= 1/8 */
     LSR_ST_LIFE = 3,        /* B3/S23 on u8 cells (Fig. 1); non-zero bytes are alive; output is 0/1 */
-    LSR_ST_RESTORE = 4      /* flagged pixels (env0 = u8 mask) take argmin_t sum phi(t - u_m) over
+    LSR_ST_RESTORE = 4,     /* flagged pixels (env0 = u8 mask) take argmin_t sum phi(t - u_m) over
                                their in-range 8-neighbourhood (phase 2 of Sect. 4.3);
                                phi(t) = sqrt(beta + t^2), param[0] = beta,
                                param[1] != 0 selects phi(t) = t^2 */
+    LSR_ST_SOBEL = 5        /* u8 image: b = min(255, floor(sqrt(Gx^2 + Gy^2))) with Gx, Gy the 3x3
+                               Sobel derivative masks and samples outside the image 0 (the edge
+                               detector of Sect. 4.2, a single-iteration pattern: max_iter = 1,
+                               cond NEVER; the reduce SUM is the sum of the new image) */
 } lsr_stencil_id;
 
 typedef enum {
@@ -232,6 +236,7 @@ lsr_status lsr_tune_import(lsr_ctx *ctx, const char *json);
  *   HELMHOLTZ5 F64|F32  RING            env0 g (dtype)   MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
  *   LIFE       U8       TORUS|BOTTOM    env0 NULL        SUM                  STABLE_FOR|NEVER
  *   RESTORE    F64|F32  BOTTOM          env0 mask (u8)   MAX_ABS|MEAN_ABS     BELOW|NEVER
+ *   SOBEL      U8       BOTTOM          env0 NULL        SUM                  NEVER
  * EINVAL: null pointers, rows/cols too small, pitch < cols, a combination outside the table,
  * check_every < 1, max_iter < 1, stable_window < 1 with STABLE_FOR. ENOMEM/EBUSY: scratch.
  */

@@ -19,6 +19,7 @@
 #include "tile_jacobi.hpp"
 #include "tile_life.hpp"
 #include "tile_restore.hpp"
+#include "tile_sobel.hpp"
 
 namespace lsr {
 namespace {
@@ -103,6 +104,17 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
         if (check) {
             acc = is_max ? wave_max(acc) : wave_sum(acc);
             if ((threadIdx.x & 63) == 0) static_cast<double*>(J.partials)[w.tile] = acc;
+        }
+    }
+    if constexpr (KIND == BK_SOBEL) {
+        __shared__ __attribute__((aligned(16))) uint8_t slds[kWavesPerGroup][kSobelLdsBytes];
+        const int band = w.tile / J.strips, strip = w.tile - band * J.strips;
+        unsigned long long acc =
+            sobel_wave(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), J.rows, J.cols,
+                       J.pitch, (int64_t)band * kSobelRows, (int64_t)strip * kSobelCols, slds[wave]);
+        if (check) {
+            acc = wave_sum_u64(acc);
+            if ((threadIdx.x & 63) == 0) static_cast<unsigned long long*>(J.partials)[w.tile] = acc;
         }
     }
 }
@@ -355,6 +367,15 @@ void batch_geometry_restore(BatchJob& j, int f32) {
     j.tiles = j.strips * (int)((j.rows + kRestoreTileRows - 1) / kRestoreTileRows);
 }
 
+void batch_geometry_sobel(BatchJob& j) {
+    j.step = 1;
+    j.mc = 0;
+    j.kind = BK_SOBEL;
+    j.tile_rows = kSobelRows;
+    j.strips = (int)((j.cols + kSobelCols - 1) / kSobelCols);
+    j.tiles = j.strips * (int)((j.rows + kSobelRows - 1) / kSobelRows);
+}
+
 hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int kind,
                               int nwork_padded, hipStream_t s) {
     if (nwork_padded <= 0) return hipSuccess;
@@ -371,6 +392,7 @@ hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int ki
         case BK_LIFE_SWAR: launch_kind<BK_LIFE_SWAR>(jobs, work, groups, s); break;
         case BK_RESTORE_F64: launch_kind<BK_RESTORE_F64>(jobs, work, groups, s); break;
         case BK_RESTORE_F32: launch_kind<BK_RESTORE_F32>(jobs, work, groups, s); break;
+        case BK_SOBEL: launch_kind<BK_SOBEL>(jobs, work, groups, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

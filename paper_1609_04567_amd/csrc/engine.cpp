@@ -79,11 +79,13 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     const lsr_grid& g = j->grid;
     const bool life = j->stencil == LSR_ST_LIFE;
     const bool restore = j->stencil == LSR_ST_RESTORE;
+    const bool sobel = j->stencil == LSR_ST_SOBEL;
     const bool f32 = g.dtype == LSR_F32;
     j->xgrid = g;
     // small grids are swept in LDS from any pitch or alignment, restoration at any
     // pitch: staged only when they live in host memory
-    j->staged = j->host || (!restore && !lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
+    j->staged = j->host || (!restore && !sobel &&
+                            !lsr::batch_small_fits(g.rows, g.cols, (int)dtype_size(g.dtype)) &&
                             needs_staging(g, j->stencil));
     if (j->staged) j->xgrid.pitch = stage_pitch(g);   // buffers assigned at admission
     lsr::BatchJob& d = j->desc;
@@ -117,6 +119,7 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
         tu = tuned_for(g, j->stencil, j->cond.check_every);
     }
     if (restore) lsr::batch_geometry_restore(d, f32);
+    else if (sobel) lsr::batch_geometry_sobel(d);
     else lsr::batch_geometry(d, life, f32, tu.tb_depth, tu.tile_rows);
     c.nparts = d.tiles;
     const size_t esz = dtype_size(g.dtype);
@@ -124,7 +127,7 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     int nparts = d.mc ? d.tiles * d.step : d.tiles;
     if (life) {
         nparts = std::max(nparts, lsr::count_u8_parts(g.rows, g.cols));
-    } else if (!restore) {
+    } else if (!restore && !sobel) {
         // unfused geometry that replays a stop inside a round (rows are aligned:
         // null pointers stand for the buffers, which are not allocated yet)
         lsr::JacobiArgs ra = jacobi_args(j, nullptr, nullptr);
@@ -135,8 +138,8 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     j->nparts_alloc = nparts;
     // device time of a round per cell, in bytes at 5 TB/s (restoration: its
     // measured ALU time per pixel)
-    const double per_cell = life ? 2.0 : restore ? (f32 ? 150.0 : 480.0)
-                                                 : (double)esz * (d.helm ? 3.0 : 2.0);
+    const double per_cell = life || sobel ? 2.0 : restore ? (f32 ? 150.0 : 480.0)
+                                                          : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
     if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");
     return LSR_OK;

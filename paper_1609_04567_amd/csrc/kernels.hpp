@@ -102,6 +102,12 @@ hipError_t launch_restore(const RestoreArgs& a, const SweepGeom& g, JobState* st
 hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64_t pitch,
                              int w_max, uint8_t* mask, void* u_init, int u_dtype, hipStream_t s);
 
+// Sobel edge detector (u8 in, u8 out; partials are u64 sums of the new image) ----
+SweepGeom sobel_geom(int64_t rows, int64_t cols);
+hipError_t launch_sobel(const uint8_t* a, uint8_t* b, int64_t rows, int64_t cols, int64_t pitch,
+                        const SweepGeom& g, JobState* st, void* partials, const LoopCtl& c, int j,
+                        hipStream_t s);
+
 // Batched execution ----------------------------------------------------------
 // Kernel family of one job inside a batch; every batch kernel uses 256-thread
 // workgroups (4 wavefronts).
@@ -118,9 +124,10 @@ enum BatchKind : int32_t {
     BK_SMALL_F32 = 10,     //   FP32 Jacobi
     BK_SMALL_LIFE = 11,    //   Life
     BK_RESTORE_F64 = 12,   // restoration sweep (phase 2 of Sect. 4.3), FP64, 16 x 64 pixels per tile
-    BK_RESTORE_F32 = 13    //   FP32 storage
+    BK_RESTORE_F32 = 13,   //   FP32 storage
+    BK_SOBEL = 14          // Sobel edge detector, 8 rows x 256 columns per tile
 };
-constexpr int kBatchKinds = 13;
+constexpr int kBatchKinds = 14;
 // A grid runs whole-grid-in-LDS when both of its buffers fit in this many bytes
 // (rows * cols * element size * 2; one 1024-thread workgroup per job).
 constexpr int64_t kSmallLdsBytes = 160 * 1024 - 1024;
@@ -168,6 +175,8 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth = 0, int w
 // The same for a restoration job: one tile = 16 rows x 64 columns (one wavefront),
 // one sweep per round; never whole-grid-in-LDS.
 void batch_geometry_restore(BatchJob& j, int f32);
+// The same for a Sobel job: one tile = 8 rows x 256 columns (one wavefront).
+void batch_geometry_sobel(BatchJob& j);
 // One launch per kernel family: `work` points at that family's segment of the
 // work list (nwork_padded entries, a multiple of 32; idle entries have job -1).
 // A workgroup runs four consecutive entries, one per wavefront.

@@ -89,6 +89,14 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
             if (c->kind != LSR_COND_BELOW && c->kind != LSR_COND_NEVER)
                 return fail(LSR_EINVAL, "restoration conditions are BELOW or NEVER");
             break;
+        case LSR_ST_SOBEL:
+            if (g->rows < 1 || g->cols < 1) return fail(LSR_EINVAL, "empty grid");
+            if (g->dtype != LSR_U8) return fail(LSR_EINVAL, "Sobel images are U8");
+            if (g->bc != LSR_BC_BOTTOM) return fail(LSR_EINVAL, "Sobel uses the BOTTOM boundary");
+            if (g->env0) return fail(LSR_EINVAL, "Sobel takes no env0");
+            if (reduce != LSR_RED_SUM) return fail(LSR_EINVAL, "Sobel reduces with SUM");
+            if (c->kind != LSR_COND_NEVER) return fail(LSR_EINVAL, "Sobel runs to max_iter (NEVER)");
+            break;
         default:
             return fail(LSR_EINVAL, "unknown stencil_id %d", stencil);
     }
@@ -187,6 +195,10 @@ lsr_status lsr_rt::launch_sweep(Job* j, int off, hipStream_t s) {
             break;
         case LSR_ST_LIFE:
             e = lsr::launch_life(life_args(j, src, dst), j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        case LSR_ST_SOBEL:
+            e = lsr::launch_sobel(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), g.rows,
+                                  g.cols, g.pitch, j->geom, j->st, j->partials, j->ctl, off, s);
             break;
         case LSR_ST_RESTORE: {
             lsr::RestoreArgs a;
@@ -626,6 +638,9 @@ lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int*
                 j->replay_geom = lsr::life_geom(a, 0);
                 break;
             }
+            case LSR_ST_SOBEL:
+                j->geom = lsr::sobel_geom(g.rows, g.cols);
+                break;
             default: {
                 lsr::RestoreArgs a{};
                 a.rows = g.rows;

@@ -363,9 +363,11 @@ def video_frame(rows: int, cols: int, f: int, seed: int = 8, noise: float = 0.3,
     scale = 223.0 / (hi - lo) if hi > lo else 0.0
     clean = np.rint(16.0 + (field - lo) * scale).astype(np.uint8)
     npx = rows * cols
+    if noise <= 0.0:   # no impulse can be drawn
+        return RestoreInput(y=clean.copy(), clean=clean, impulse=np.zeros((rows, cols), dtype=bool))
     hit = np.empty(npx, dtype=bool)
     salt = np.empty(npx, dtype=bool)
-    lim_hit = _below_limit(noise) if 0.0 < noise < 1.0 else None
+    lim_hit = _below_limit(noise) if noise < 1.0 else None
     lim_salt = _below_limit(0.5)
     for lo2, zz in _mixed_blocks(seed, 6 * blobs + 2 * f * npx, 2 * npx):
         p0 = lo2 // 2

@@ -75,6 +75,7 @@ VALID = [
     (_g(1, 1, dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_LIFE, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER)),
     (_g(dtype=L.LSR_F32, bc=L.LSR_BC_BOTTOM, env0=FAKE, param=(100.0,)), L.LSR_ST_RESTORE,
      L.LSR_RED_MEAN_ABS_DELTA, _c(thr=0.1)),
+    (_g(1, 1, dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER)),
 ]
 
 
@@ -113,6 +114,14 @@ INVALID = [
     ("restore ring", _g(env0=FAKE, param=(100.0,)), L.LSR_ST_RESTORE, 1, _c(), 10),
     ("restore beta 0", _g(bc=L.LSR_BC_BOTTOM, env0=FAKE, param=(0.0,)), L.LSR_ST_RESTORE, 1, _c(), 10),
     ("restore l2", _g(bc=L.LSR_BC_BOTTOM, env0=FAKE, param=(100.0,)), L.LSR_ST_RESTORE, 2, _c(), 10),
+    ("sobel f64", _g(bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER), 1),
+    ("sobel torus", _g(dtype=L.LSR_U8, bc=L.LSR_BC_TORUS), L.LSR_ST_SOBEL, L.LSR_RED_SUM,
+     _c(L.LSR_COND_NEVER), 1),
+    ("sobel max reduce", _g(dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, 1,
+     _c(L.LSR_COND_NEVER), 1),
+    ("sobel below", _g(dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(), 1),
+    ("sobel env", _g(dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM, env0=FAKE), L.LSR_ST_SOBEL, L.LSR_RED_SUM,
+     _c(L.LSR_COND_NEVER), 1),
     ("unknown stencil", _g(), 99, 1, _c(), 10),
     ("env1 set", None, L.LSR_ST_LAPLACE5, 1, _c(), 10),
 ]

@@ -187,15 +187,20 @@ def test_cancel_pending_and_running(bctx):
         assert 0 <= r.iterations < 2_000_000 and not r.converged
 
 
-def test_restoration_rejected_on_batched_context(bctx):
+def test_restoration_with_nothing_flagged_stops_at_once(bctx):
+    """A restoration job with an all-zero mask on a batched context: no pixel
+    changes, so the first check (r = 0 < 0.1) stops it and the field is unchanged."""
     import torch
-    say("restore on batched")
-    u = torch.zeros((16, 16), dtype=torch.float64, device="cuda:0")
+    say("restore on batched, empty mask")
+    u0 = torch.arange(256, dtype=torch.float64, device="cuda:0").reshape(16, 16)
+    u = u0.clone()
     m = torch.zeros((16, 16), dtype=torch.uint8, device="cuda:0")
-    with pytest.raises(L.LsrError) as ei:
-        bctx.submit(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA, L.make_cond(L.LSR_COND_BELOW, 0.1),
-                    10, L.LSR_BC_BOTTOM, env0=m, param=(100.0, 0.0))
-    assert ei.value.status == L.LSR_EINVAL
+    r = bctx.result(bctx.submit(u, L.LSR_ST_RESTORE, L.LSR_RED_MAX_ABS_DELTA,
+                                L.make_cond(L.LSR_COND_BELOW, 0.1), 10, L.LSR_BC_BOTTOM, env0=m,
+                                param=(100.0, 0.0)))
+    torch.cuda.synchronize()
+    assert r.status == L.LSR_OK and r.iterations == 1 and r.converged and r.last_reduce == 0.0
+    assert torch.equal(u, u0)
 
 
 def test_stops_inside_rounds_are_replayed(bctx):
