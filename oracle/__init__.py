@@ -64,6 +64,9 @@ def _load():
         lib.orc_restore_run.argtypes = [P, P, C.c_int64, C.c_int64, C.c_double, C.c_int, C.c_int,
                                         C.c_int, C.c_double, C.c_int, C.c_int64, P, C.c_int64,
                                         C.POINTER(_Res)]
+        lib.orc_jacobi_sep_run.argtypes = [P, P, P, C.c_double, C.c_double, C.c_int64, C.c_int64,
+                                           C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
+                                           C.c_int, C.c_int64, P, C.c_int64, C.POINTER(_Res)]
         lib.orc_sobel_run.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int64, P, C.c_int64,
                                       C.POINTER(_Res)]
         lib.orc_restore_argmin.argtypes = [P, C.c_int, C.c_double, C.c_int]
@@ -110,6 +113,28 @@ def jacobi_run(a: np.ndarray, *, helmholtz: bool = False, g: np.ndarray | None =
     rc = lib.orc_jacobi_run(int(helmholtz), _ptr(a), gp, a.shape[0], a.shape[1], float(alpha),
                             float(h), int(reduce_op), int(cond), float(thr), int(check_every),
                             int(max_iter), _ptr(trace), int(trace_cap), C.byref(res))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return a, _result(res, trace[:trace_cap])
+
+
+def jacobi_sep_run(a: np.ndarray, p: np.ndarray, q: np.ndarray, c1: float, c2: float, *,
+                   alpha: float, h: float, reduce_op: int = RED_L2_DELTA, cond: int = COND_BELOW,
+                   thr: float = 1e-9, check_every: int = 10, max_iter: int = 5000,
+                   trace_cap: int = 0) -> tuple[np.ndarray, OracleResult]:
+    """The -i form of the Helmholtz sweep: g(i, j) = c2 * (c1 * (p[i] * q[j])) from the
+    cell's indices (FP64)."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64).copy()
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert p.shape == (a.shape[0],) and q.shape == (a.shape[1],)
+    trace = np.zeros(max(trace_cap, 1), dtype=np.float64)
+    res = _Res()
+    rc = lib.orc_jacobi_sep_run(_ptr(a), _ptr(p), _ptr(q), float(c1), float(c2), a.shape[0],
+                                a.shape[1], float(alpha), float(h), int(reduce_op), int(cond),
+                                float(thr), int(check_every), int(max_iter), _ptr(trace),
+                                int(trace_cap), C.byref(res))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return a, _result(res, trace[:trace_cap])

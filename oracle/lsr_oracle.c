@@ -77,8 +77,15 @@ static double reduce_delta(int op, const double *b, const double *a, int64_t row
  * 5-point Jacobi sweep (Helmholtz solver of Sect. 4.1, Laplace as alpha = 0,
  * f = 0). The outer ring is boundary data: copied, never updated.
  * ------------------------------------------------------------------------- */
+/* The right-hand side of the -i form (index-aware elemental function, Sect. 3.1):
+ * g(i, j) = c2 * (c1 * (p_i * q_j)), evaluated from the cell's indices. */
+typedef struct {
+    const double *p, *q;
+    double c1, c2;
+} sep_source;
+
 static void jacobi_sweep(int helmholtz, const double *a, double *b, const double *g,
-                         int64_t rows, int64_t cols, double rd) {
+                         const sep_source *sep, int64_t rows, int64_t cols, double rd) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < rows; ++i) {
         for (int64_t j = 0; j < cols; ++j) {
@@ -88,20 +95,47 @@ static void jacobi_sweep(int helmholtz, const double *a, double *b, const double
                 continue;
             }
             double nn = a[p - cols], ss = a[p + cols], ww = a[p - 1], ee = a[p + 1];
-            if (helmholtz)
+            if (sep) {
+                double gij = sep->c2 * (sep->c1 * (sep->p[i] * sep->q[j]));
+                b[p] = (((nn + ss) + (ww + ee)) + gij) * rd;
+            } else if (helmholtz) {
                 b[p] = (((nn + ss) + (ww + ee)) + g[p]) * rd;
-            else
+            } else {
                 b[p] = 0.25 * ((nn + ss) + (ww + ee));
+            }
         }
     }
 }
+
+static int jacobi_loop(int helmholtz, double *a, const double *g, const sep_source *sep,
+                       int64_t rows, int64_t cols, double alpha, double h, int reduce_op,
+                       int cond_kind, double thr, int check_every, int64_t max_iter,
+                       double *trace, int64_t trace_cap, orc_result *out);
 
 int orc_jacobi_run(int helmholtz, double *a, const double *g, int64_t rows, int64_t cols,
                    double alpha, double h, int reduce_op, int cond_kind, double thr,
                    int check_every, int64_t max_iter, double *trace, int64_t trace_cap,
                    orc_result *out) {
-    if (!a || !out || rows < 3 || cols < 3 || check_every < 1 || max_iter < 1) return -1;
     if (helmholtz && !g) return -1;
+    return jacobi_loop(helmholtz, a, g, NULL, rows, cols, alpha, h, reduce_op, cond_kind, thr,
+                       check_every, max_iter, trace, trace_cap, out);
+}
+
+int orc_jacobi_sep_run(double *a, const double *p, const double *q, double c1, double c2,
+                       int64_t rows, int64_t cols, double alpha, double h, int reduce_op,
+                       int cond_kind, double thr, int check_every, int64_t max_iter,
+                       double *trace, int64_t trace_cap, orc_result *out) {
+    if (!p || !q) return -1;
+    sep_source sep = {p, q, c1, c2};
+    return jacobi_loop(1, a, NULL, &sep, rows, cols, alpha, h, reduce_op, cond_kind, thr,
+                       check_every, max_iter, trace, trace_cap, out);
+}
+
+static int jacobi_loop(int helmholtz, double *a, const double *g, const sep_source *sep,
+                       int64_t rows, int64_t cols, double alpha, double h, int reduce_op,
+                       int cond_kind, double thr, int check_every, int64_t max_iter,
+                       double *trace, int64_t trace_cap, orc_result *out) {
+    if (!a || !out || rows < 3 || cols < 3 || check_every < 1 || max_iter < 1) return -1;
     if (reduce_op != ORC_RED_MAX_ABS_DELTA && reduce_op != ORC_RED_L2_DELTA &&
         reduce_op != ORC_RED_MEAN_ABS_DELTA) return -1;
     if (cond_kind != ORC_COND_BELOW && cond_kind != ORC_COND_NEVER) return -1;
@@ -114,7 +148,7 @@ int orc_jacobi_run(int helmholtz, double *a, const double *g, int64_t rows, int6
     int64_t n = 0;
     int stop = 0;
     do {
-        jacobi_sweep(helmholtz, cur, nxt, g, rows, cols, rd);          /* b = stencil(f'):a */
+        jacobi_sweep(helmholtz, cur, nxt, g, sep, rows, cols, rd);     /* b = stencil(f'):a */
         n = n + 1;
         if (is_check_sweep(n, check_every, max_iter)) {
             double r = reduce_delta(reduce_op, nxt, cur, rows, cols);  /* /(+):alpha(delta):b */

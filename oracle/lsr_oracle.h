@@ -62,6 +62,17 @@ int orc_jacobi_run(int helmholtz, double *a, const double *g, int64_t rows, int6
                    orc_result *out);
 
 /*
+ * The -i form of the Helmholtz sweep (Sect. 3.1: the elemental function also
+ * receives the cell's index): the right-hand side is evaluated from the indices
+ * as g(i, j) = c2 * (c1 * (p[i] * q[j])) instead of being read from an env
+ * array; everything else as orc_jacobi_run with helmholtz = 1.
+ */
+int orc_jacobi_sep_run(double *a, const double *p, const double *q, double c1, double c2,
+                       int64_t rows, int64_t cols, double alpha, double h, int reduce_op,
+                       int cond_kind, double thr, int check_every, int64_t max_iter,
+                       double *trace, int64_t trace_cap, orc_result *out);
+
+/*
  * Conway's Life B3/S23 (the rule of the paper's Fig. 1). bc = TORUS wraps both
  * axes; bc = BOTTOM treats out-of-range cells as dead (Fig. 1's guards).
  * A cell is alive iff its byte is non-zero; the output holds 0/1.
