@@ -534,7 +534,10 @@ class _StreamRun:
                 with self.cv:
                     k, v, job, need = self.jobs.pop(jid)
                     self.collected += 1
+                    done = self.collected
                 self.pool.submit(self._finish, k, v, job, r, need)
+                if done % 1000 == 0:   # progress of long streams
+                    print(f"  {done} / {self.total} results", file=sys.stderr, flush=True)
         except BaseException as e:
             with self.cv:
                 self.error = e
@@ -625,6 +628,15 @@ def run_served(args, L, I, torch):
     legs = [x for x in args.legs.split(",") if x]
     gib = int(args.host_gib * (1 << 30))
     recs = {k: {"kind": s.kind, "side": s.side} for k, s in enumerate(specs)}
+    prior = False
+    if args.prior_records:
+        # per-job records of earlier legs of the same stream (another run of this
+        # workload): their digests and counts join the cross-checks below
+        with open(args.prior_records) as fh:
+            for k, v in json.load(fh).items():
+                if int(k) in recs:
+                    recs[int(k)].update(v)
+        prior = True
     keep_fields = {}
     sample = {k for k, s in enumerate(specs)
               if (k % 97 == 0 and s.side <= 1024) or k % 997 == 0}
@@ -762,15 +774,18 @@ def run_served(args, L, I, torch):
         pctx.close()
         pj = count / wall
         out["plain_fp64_jobs_s"] = round(pj, 3)
-        if "closed" in legs:
+        if sat:
             out["speedup_vs_plain_fp64"] = round(sat / pj, 3)
+        if "closed" in legs or prior:
             out["life_equal_batched_vs_plain"] = int(sum(
-                recs[k]["d32"] == recs[k]["d64p"] and recs[k]["n"] == recs[k]["n64p"]
+                recs[k].get("d32") == recs[k]["d64p"] and recs[k].get("n") == recs[k]["n64p"]
                 for k in recs if specs[k].kind == I.KIND_LIFE))
-        if "verify" in legs:
+            out["life_jobs"] = int(sum(specs[k].kind == I.KIND_LIFE for k in recs))
+        if "verify" in legs or prior:
             out["f64_batched_equal_plain"] = int(sum(
-                recs[k]["d64v"] == recs[k]["d64p"] and recs[k]["n64"] == recs[k]["n64p"]
+                recs[k].get("d64v") == recs[k]["d64p"] and recs[k].get("n64") == recs[k]["n64p"]
                 for k in recs if specs[k].kind != I.KIND_LIFE))
+            out["jacobi_jobs"] = int(sum(specs[k].kind != I.KIND_LIFE for k in recs))
         print(f"plain fp64: {pj:.2f} jobs/s", file=sys.stderr, flush=True)
 
     # -- CPU oracle on the seeded sample (the CPU baseline) --------------------------
@@ -1005,6 +1020,8 @@ def main():
     ap.add_argument("--host-gib", type=float, default=12.0,
                     help="host buffers outstanding at a time in the served legs")
     ap.add_argument("--records", default="", help="served: write per-job records (JSON) here")
+    ap.add_argument("--prior-records", default="",
+                    help="served: per-job records of an earlier run of other legs, for cross-checks")
     ap.add_argument("--frames", type=int, default=100, help="video: frames per stream")
     ap.add_argument("--video-dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--sobel-sizes", type=int, default=3, help="sobel: how many of 512, 4096, 16384")

@@ -80,10 +80,18 @@ typedef enum {
                                their in-range 8-neighbourhood (phase 2 of Sect. 4.3);
                                phi(t) = sqrt(beta + t^2), param[0] = beta,
                                param[1] != 0 selects phi(t) = t^2 */
-    LSR_ST_SOBEL = 5        /* u8 image: b = min(255, floor(sqrt(Gx^2 + Gy^2))) with Gx, Gy the 3x3
+    LSR_ST_SOBEL = 5,       /* u8 image: b = min(255, floor(sqrt(Gx^2 + Gy^2))) with Gx, Gy the 3x3
                                Sobel derivative masks and samples outside the image 0 (the edge
                                detector of Sect. 4.2, a single-iteration pattern: max_iter = 1,
                                cond NEVER; the reduce SUM is the sum of the new image) */
+    LSR_ST_HELMHOLTZ5_SEP = 6 /* the -i form of HELMHOLTZ5 (Sect. 3.1: the elemental function also
+                               receives the cell's index): g(i, j) = c2 * (c1 * (p[i] * q[j])),
+                               evaluated in FP64 from the cell's indices, replaces the env array;
+                               env0 = p (rows FP64 values), env1 = q (cols FP64 values), both
+                               device vectors; param[0] = alpha, param[1] = h, param[2] = c1,
+                               param[3] = c2. With the factors of a separable right-hand side it
+                               gives HELMHOLTZ5's result bit for bit while reading 16 instead of
+                               24 bytes per cell update. Plain contexts and device buffers only */
 } lsr_stencil_id;
 
 typedef enum {
@@ -116,7 +124,7 @@ typedef struct {
                                in FP64) for Jacobi/restoration; U8 for Life */
     int32_t bc;             /* lsr_bc */
     const void *env0;       /* read-only env: Helmholtz g (grid dtype), restoration mask (u8) */
-    const void *env1;       /* reserved, must be NULL */
+    const void *env1;       /* HELMHOLTZ5_SEP: the column factor q; otherwise NULL */
     double param[4];        /* stencil parameters, see lsr_stencil_id */
 } lsr_grid;
 
@@ -237,6 +245,7 @@ lsr_status lsr_tune_import(lsr_ctx *ctx, const char *json);
  *   LIFE       U8       TORUS|BOTTOM    env0 NULL        SUM                  STABLE_FOR|NEVER
  *   RESTORE    F64|F32  BOTTOM          env0 mask (u8)   MAX_ABS|MEAN_ABS     BELOW|NEVER
  *   SOBEL      U8       BOTTOM          env0 NULL        SUM                  NEVER
+ *   HELMHOLTZ5_SEP F64|F32 RING         env0 p, env1 q   as HELMHOLTZ5        as HELMHOLTZ5
  * EINVAL: null pointers, rows/cols too small, pitch < cols, a combination outside the table,
  * check_every < 1, max_iter < 1, stable_window < 1 with STABLE_FOR. ENOMEM/EBUSY: scratch.
  */

@@ -12,6 +12,7 @@ from ._native import (  # noqa: F401
     LSR_COND_STABLE_FOR, LSR_FLAG_BATCHED, LSR_EBUSY, LSR_ECANCELED, LSR_EDEVICE, LSR_EINVAL, LSR_ENOMEM,
     LSR_ENOTFOUND, LSR_ENUMERIC, LSR_F32, LSR_F64, LSR_OK, LSR_RED_L2_DELTA,
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
+    LSR_ST_HELMHOLTZ5_SEP,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_ST_SOBEL, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
     lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_noalloc, lsr_run_restore_host,
@@ -96,7 +97,20 @@ class Context:
         with open(path) as fh:
             lsr_tune_import(self.handle, fh.read())
 
-    def submit(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+    def submit(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=(),
+               env1=None):
+        if stencil_id == LSR_ST_HELMHOLTZ5_SEP:
+            import torch
+            # env0 / env1 are the factor vectors p (rows) and q (cols), FP64 on the device
+            for v, n in ((env0, grid_t.shape[0]), (env1, grid_t.shape[1])):
+                if v is None or v.dim() != 1 or v.shape[0] != n or v.dtype != torch.float64 \
+                        or not v.is_cuda or not v.is_contiguous():
+                    raise ValueError("the -i form needs FP64 device vectors p (rows) and q (cols)")
+            g = grid_from_tensor(grid_t, bc, None, param)
+            g.env0, g.env1 = env0.data_ptr(), env1.data_ptr()
+            job = lsr_run(self.handle, g, stencil_id, reduce_op, cond, max_iter)
+            self._keep[job] = (grid_t, env0, env1)
+            return job
         g = grid_from_tensor(grid_t, bc, env0, param)
         job = lsr_run(self.handle, g, stencil_id, reduce_op, cond, max_iter)
         self._keep[job] = (grid_t, env0)  # the caller's buffers stay alive until the result
@@ -143,9 +157,10 @@ class Context:
     def cancel(self, job):
         lsr_cancel(self.handle, job)
 
-    def run(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=()):
+    def run(self, grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0=None, param=(),
+            env1=None):
         return self.result(self.submit(grid_t, stencil_id, reduce_op, cond, max_iter, bc, env0,
-                                       param))
+                                       param, env1))
 
     def amf_detect(self, y_t, w_max=19, u_dtype=None):
         """Phase-1 detection; returns (mask u8, u_init) tensors on y's device."""

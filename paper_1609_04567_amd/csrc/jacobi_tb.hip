@@ -18,13 +18,14 @@ namespace {
 // FP64: at least three wavefronts per SIMD (168 VGPRs). At depth 10 the register
 // pipeline needs about 174, and the compiler fits it in 168 with a few values
 // spilled, which the third wavefront repays (8192^2 Helmholtz +10 %).
-template <typename T, bool HELM, int VEC, int NW, int K, bool MC>
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP = false>
 __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
-    double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles, int tile_rows) {
+    double* __restrict__ partials, LoopCtl ctl, int j, int strips, int tiles, int tile_rows,
+    SepSource sep) {
     __shared__ double lds[NW];
-    __shared__ __attribute__((aligned(16))) T gring[HELM ? tb_gring_elems<VEC, NW, K>() : 1];
+    __shared__ __attribute__((aligned(16))) T gring[HELM && !SEP ? tb_gring_elems<VEC, NW, K>() : 1];
     if (__hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     // sweeps n1 .. n1 + K - 1 (sweeps past the cap are computed and never kept:
     // the stop lands inside the launch and the driver replays up to it)
@@ -39,9 +40,9 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_ke
     if (!MC) mask &= 1u << (K - 1);   // K divides the check period and the cap
     const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
     if (t >= tiles) return;
-    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM, false, MC>(
+    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM && !SEP, false, MC, SEP>(
         a, b, g, rows, cols, pitch, rd, rd_lo, (uint32_t)n1, mask, ctl.reduce, t, strips, tiles,
-        tile_rows, partials, lds, gring);
+        tile_rows, partials, lds, gring, sep);
 }
 
 // Fused depths and wavefronts per workgroup compiled for the vector (16-byte
@@ -54,15 +55,27 @@ bool waves_ok(int waves) { return waves == 1 || waves == 2 || waves == 4; }
 // until it has them; 1024^2 measured best at 4-row bands, 1280 tiles).
 constexpr int64_t kMinTiles = 1024;
 
-template <typename T, bool HELM, int VEC, int NW, int K, bool MC = false>
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC = false, bool SEP = false>
 hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC>), dim3(g.blocks), dim3(NW * 64), 0,
-                       s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC, SEP>), dim3(g.blocks),
+                       dim3(NW * 64), 0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
                        T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,
-                       g.tiles, g.tile_rows);
+                       g.tiles, g.tile_rows, SepSource{a.sp, a.sq, a.c1, a.c2});
     return hipGetLastError();
+}
+
+// The -i form: compiled for two wavefronts per workgroup at depths 10 and 5.
+template <typename T, int VEC>
+hipError_t launch_sep(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                      const LoopCtl& c, int j, hipStream_t s) {
+    if (g.waves != 2) return hipErrorInvalidValue;
+    if (g.tb == 10 && !g.mc) return launch_t<T, true, VEC, 2, 10, false, true>(a, g, st, partials, c, j, s);
+    if (g.tb == 5)
+        return g.mc ? launch_t<T, true, VEC, 2, 5, true, true>(a, g, st, partials, c, j, s)
+                    : launch_t<T, true, VEC, 2, 5, false, true>(a, g, st, partials, c, j, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename T, bool HELM, int VEC, int K>
@@ -109,6 +122,14 @@ void jacobi_tb_choose(const JacobiArgs& a, int check_every, int64_t max_iter, in
                       int* depth, int* mc) {
     static constexpr int kPrefF64[] = {10, 8, 5, 4, 2};
     static constexpr int kPrefF32[] = {5, 4, 10, 8, 2};
+    if (a.sep) {   // the -i form's compiled depths: FP64 10 (checks on the last level) or 5
+        int k = requested == 1 ? 1 : 5;
+        if (!a.f32 && requested != 1 && requested != 5 && check_every % 10 == 0 && max_iter % 10 == 0)
+            k = 10;
+        *depth = k;
+        *mc = k > 1 && !(check_every % k == 0 && max_iter % k == 0);
+        return;
+    }
     int k = 1;
     if (requested > 1) {
         k = jacobi_tb_depth_ok(requested) ? requested : 1;
@@ -124,7 +145,7 @@ void jacobi_tb_choose(const JacobiArgs& a, int check_every, int64_t max_iter, in
 void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int waves, int unroll,
                     SweepGeom& g) {
     (void)unroll;   // rows always stream in groups of three
-    if (!waves_ok(waves) || mc) waves = 2;   // per-level checks: compiled for 2 waves
+    if (!waves_ok(waves) || mc || a.sep) waves = 2;   // per-level checks, -i form: 2 waves
     g.tb = depth;
     g.mc = mc;
     g.waves = waves;
@@ -151,6 +172,11 @@ void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int w
 
 hipError_t launch_jacobi_tb(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                             const LoopCtl& c, int j, hipStream_t s) {
+    if (a.sep) {
+        if (g.vec != (a.f32 ? 4 : 2)) return hipErrorInvalidValue;
+        return a.f32 ? launch_sep<float, 4>(a, g, st, partials, c, j, s)
+                     : launch_sep<double, 2>(a, g, st, partials, c, j, s);
+    }
     if (a.f32) {
         if (g.vec != 4) return hipErrorInvalidValue;
         return a.helm ? launch_depth<float, true, 4>(a, g, st, partials, c, j, s)

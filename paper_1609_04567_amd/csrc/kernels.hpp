@@ -32,6 +32,12 @@ struct JacobiArgs {
     double rd;           // 1 / (4 + alpha h^2) (Helmholtz)
     int helm;            // 0 Laplace, 1 Helmholtz
     int f32;             // 0 FP64 storage, 1 FP32 storage
+    // the -i form (helm must be set): g(i, j) = c2 * (c1 * (sp[i] * sq[j])) from the
+    // cell's indices instead of the env array g
+    int sep = 0;
+    const double* sp = nullptr;
+    const double* sq = nullptr;
+    double c1 = 0.0, c2 = 0.0;
 };
 // tile_rows / waves / unroll of 0 (or an unsupported pair) select the measured default.
 // depth > 1 selects the temporally blocked kernel (one launch = `depth` sweeps)

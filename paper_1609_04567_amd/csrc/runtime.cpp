@@ -43,9 +43,16 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
     if (g->pitch < g->cols) return fail(LSR_EINVAL, "pitch (%lld) < cols (%lld)", (long long)g->pitch, (long long)g->cols);
     if (c->check_every < 1) return fail(LSR_EINVAL, "check_every must be >= 1");
     if (max_iter < 1) return fail(LSR_EINVAL, "max_iter must be >= 1");
-    if (g->env1) return fail(LSR_EINVAL, "env1 is reserved and must be NULL");
+    if (g->env1 && stencil != LSR_ST_HELMHOLTZ5_SEP)
+        return fail(LSR_EINVAL, "env1 is reserved and must be NULL");
     const bool fp = g->dtype == LSR_F64 || g->dtype == LSR_F32;
     switch (stencil) {
+        case LSR_ST_HELMHOLTZ5_SEP:
+            if (!g->env0 || !g->env1)
+                return fail(LSR_EINVAL, "the -i Helmholtz form needs env0 = p (rows) and env1 = q (cols)");
+            if (!std::isfinite(g->param[2]) || !std::isfinite(g->param[3]))
+                return fail(LSR_EINVAL, "c1 and c2 must be finite");
+            [[fallthrough]];
         case LSR_ST_LAPLACE5:
         case LSR_ST_HELMHOLTZ5:
             if (g->rows < 3 || g->cols < 3) return fail(LSR_EINVAL, "Jacobi grids need rows, cols >= 3");
@@ -53,7 +60,7 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
             if (g->bc != LSR_BC_RING) return fail(LSR_EINVAL, "Jacobi stencils use the RING boundary");
             if (stencil == LSR_ST_HELMHOLTZ5 && !g->env0) return fail(LSR_EINVAL, "Helmholtz needs env0 = h^2 f");
             if (stencil == LSR_ST_LAPLACE5 && g->env0) return fail(LSR_EINVAL, "Laplace takes no env0");
-            if (stencil == LSR_ST_HELMHOLTZ5) {
+            if (stencil != LSR_ST_LAPLACE5) {
                 const double rd = 1.0 / (4.0 + g->param[0] * (g->param[1] * g->param[1]));
                 if (!std::isfinite(rd)) return fail(LSR_EINVAL, "1/(4 + alpha h^2) is not finite");
                 // the FP32 update rounds 0.25 t + (0.25 e - (0.25 - rd) t) with an add
@@ -161,8 +168,16 @@ lsr::JacobiArgs lsr_rt::jacobi_args(const Job* j, const void* src, void* dst) {
     a.cols = g.cols;
     a.pitch = g.pitch;
     a.rd = 1.0 / (4.0 + g.param[0] * (g.param[1] * g.param[1]));
-    a.helm = j->stencil == LSR_ST_HELMHOLTZ5;
+    a.helm = j->stencil == LSR_ST_HELMHOLTZ5 || j->stencil == LSR_ST_HELMHOLTZ5_SEP;
     a.f32 = g.dtype == LSR_F32;
+    if (j->stencil == LSR_ST_HELMHOLTZ5_SEP) {
+        a.g = nullptr;
+        a.sep = 1;
+        a.sp = static_cast<const double*>(g.env0);
+        a.sq = static_cast<const double*>(g.env1);
+        a.c1 = g.param[2];
+        a.c2 = g.param[3];
+    }
     return a;
 }
 
@@ -190,6 +205,7 @@ lsr_status lsr_rt::launch_sweep(Job* j, int off, hipStream_t s) {
     switch (j->stencil) {
         case LSR_ST_LAPLACE5:
         case LSR_ST_HELMHOLTZ5:
+        case LSR_ST_HELMHOLTZ5_SEP:
             e = lsr::launch_jacobi(jacobi_args(j, src, dst), j->geom, j->st, j->partials, j->ctl,
                                    off, s);
             break;
@@ -575,6 +591,8 @@ lsr_status lsr_rt::submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id
     if (!ctx || !job_out) return fail(LSR_EINVAL, "ctx and job_out must not be NULL");
     lsr_status v = validate(grid, stencil_id, reduce_op, cond, max_iter);
     if (v != LSR_OK) return v;
+    if (stencil_id == LSR_ST_HELMHOLTZ5_SEP && (host || ctx->batched))
+        return fail(LSR_EINVAL, "the -i Helmholtz form runs on device buffers on a plain context");
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<Job> j(new Job());
     j->host = host;
@@ -605,16 +623,9 @@ lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int*
     auto plan = [&](int want_depth) {
         switch (stencil_id) {
             case LSR_ST_LAPLACE5:
-            case LSR_ST_HELMHOLTZ5: {
-                lsr::JacobiArgs a{};
-                a.a = j->buf[0];
-                a.b = j->buf[1];
-                a.g = g.env0;
-                a.rows = g.rows;
-                a.cols = g.cols;
-                a.pitch = g.pitch;
-                a.helm = stencil_id == LSR_ST_HELMHOLTZ5;
-                a.f32 = g.dtype == LSR_F32;
+            case LSR_ST_HELMHOLTZ5:
+            case LSR_ST_HELMHOLTZ5_SEP: {
+                lsr::JacobiArgs a = jacobi_args(j, j->buf[0], j->buf[1]);
                 int depth = 1, mc = 0;
                 lsr::jacobi_tb_choose(a, check_every, j->max_iter, want_depth, &depth, &mc);
                 j->geom = lsr::jacobi_geom(a, tun.tile_rows, tun.waves, tun.unroll, depth, mc);
@@ -702,7 +713,8 @@ lsr_status lsr_rt::submit_plain(lsr_ctx* ctx, std::unique_ptr<Job> j, const lsr_
             st = ctx->pool.alloc((size_t)grid->rows * (size_t)j->xgrid.pitch * env_esz(j.get()),
                                  &j->stage_env);
         j->xgrid.data = j->buf[0];
-        j->xgrid.env0 = j->stage_env;
+        // the -i form's env arrays are the factor vectors, used in place
+        if (stencil_id != LSR_ST_HELMHOLTZ5_SEP) j->xgrid.env0 = j->stage_env;
     } else {
         j->buf[0] = grid->data;
     }

@@ -128,19 +128,34 @@ __device__ __forceinline__ double jacobi_accum(int red, double acc, double d) {
     return acc + fabs(d);
 }
 
+// The right-hand side of the -i form (Sect. 3.1: the elemental function also sees
+// the cell's index): g(i, j) = c2 * (c1 * (p[i] * q[j])) in FP64, then stored in T,
+// evaluated per cell from its indices instead of read from an env array.
+struct SepSource {
+    const double* p;   // rows values
+    const double* q;   // cols values
+    double c1, c2;
+};
+template <typename T>
+__device__ __forceinline__ T sep_value(const SepSource& s, double pi, double qj) {
+    return (T)(s.c2 * (s.c1 * (pi * qj)));
+}
+
 // Tile t of a grid split into `strips` column strips and bands of `tile_rows`
 // rows (band-major). The workgroup must have NW*64 threads; lds holds NW doubles.
 // WT (wavefront tile): the calling wavefront alone owns tile t (NW must be 1);
 // other wavefronts of the workgroup may run other tiles, so the reduce stays
 // inside the wavefront and its lane 0 writes the partial.
+// SEP: the -i form (HELM must be set): g comes from `sep`, not from `g`.
 template <typename T, bool HELM, int VEC, int NW, int U, bool NT, bool NTG, bool NTU = false,
-          bool WT = false>
+          bool WT = false, bool SEP = false>
 __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restrict__ b,
                                              const T* __restrict__ g, int64_t rows, int64_t cols,
                                              int64_t pitch, T rd, T rd_lo, uint32_t sweep,
                                              bool check, int red, int t,
                                              int strips, int tile_rows,
-                                             double* __restrict__ partials, double* lds) {
+                                             double* __restrict__ partials, double* lds,
+                                             SepSource sep = SepSource{}) {
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     const int band = t / strips, strip = t - band * strips;
     // (the wavefront index stays a vector value here: made scalar, the edge
@@ -158,6 +173,11 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
 
     T up[VEC], mid[VEC];
     T mid_w = T(0), mid_e = T(0);
+    double qv[SEP ? VEC : 1];
+    if constexpr (SEP) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qv[e] = (c + e < cols) ? sep.q[c + e] : 0.0;
+    }
     load_row<T, VEC>(a + (r0 - 1) * pitch, c, cols, up);
     load_row<T, VEC>(a + r0 * pitch, c, cols, mid);
     if (has_w) mid_w = a[r0 * pitch + cw - 1];
@@ -173,7 +193,7 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
                 load_row<T, VEC, NTU>(prow, c, cols, dn[k]);
                 dn_w[k] = has_w ? prow[cw - 1] : T(0);
                 dn_e[k] = has_e ? prow[ce] : T(0);
-                if (HELM) load_row<T, VEC, NTG>(g + (r + k) * pitch, c, cols, gr[k]);
+                if (HELM && !SEP) load_row<T, VEC, NTG>(g + (r + k) * pitch, c, cols, gr[k]);
             }
         }
 #pragma unroll
@@ -184,13 +204,15 @@ __device__ __forceinline__ void jacobi5_tile(const T* __restrict__ a, T* __restr
                 if (lane == 0) wl = mid_w;
                 if (lane == 63) er = mid_e;
                 T out[VEC];
+                const double prow = SEP ? sep.p[r + k] : 0.0;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
                     const T W = (e > 0) ? mid[e - 1] : wl;
                     const T E = (e < VEC - 1) ? mid[e + 1] : er;
                     const T N = up[e], S = dn[k][e];
-                    const T nv = jacobi_update<T, HELM>(N, S, W, E, HELM ? gr[k][e] : T(0), rd,
-                                                        rd_lo, r + k, c + e, sweep);
+                    const T gv = SEP ? sep_value<T>(sep, prow, qv[e]) : HELM ? gr[k][e] : T(0);
+                    const T nv = jacobi_update<T, HELM>(N, S, W, E, gv, rd, rd_lo, r + k, c + e,
+                                                        sweep);
                     const int64_t col = c + e;
                     const bool inner = col >= 1 && col <= cols - 2;
                     out[e] = inner ? nv : mid[e];
@@ -277,15 +299,18 @@ constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 // Without MC only bit K-1 may be set and the tile's partial goes to partials[t];
 // with MC (several checks per launch) level j's partial goes to
 // partials[(j-1) * tiles + t], its delta taken against level j-1.
+// SEP: the -i form (HELM must be set): level j computes g of its row from `sep`
+// (no g rows are loaded and gring is unused).
 template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false,
-          bool MC = false>
+          bool MC = false, bool SEP = false>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
                                                 uint32_t sweep0, uint32_t check_mask, int red,
                                                 int t, int strips, int tiles, int tile_rows,
                                                 double* __restrict__ partials, double* lds,
-                                                T* gring) {
+                                                T* gring, SepSource sep = SepSource{}) {
+    constexpr bool GRING = HELM && !SEP;   // g rows stream through the LDS ring
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
@@ -314,6 +339,11 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     const bool vec_ok = c + VEC <= cols;
     const bool store_vec = c >= olo && c + VEC <= ohi;
     V* ring = reinterpret_cast<V*>(gring) + (size_t)hw_wave * K * 64 + lane;  // slot s at ring[s * 64]
+    double qv[SEP ? VEC : 1];
+    if constexpr (SEP) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) qv[e] = (c + e < cols) ? sep.q[c + e] : 0.0;
+    }
 
     // W[j][s]: three rows of level j in registers; the slot that receives a
     // level's new row rotates with the row index (phase P = step % 3), so the
@@ -325,7 +355,7 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
         for (int s2 = 0; s2 < 3; ++s2)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) W[j][s2][e] = T(0);
-    if (HELM) {
+    if (GRING) {
         V z;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) z[e] = T(0);
@@ -371,7 +401,7 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
         constexpr int PN = (P + 1) % 3, PC = (P + 2) % 3;   // older rows: north, centre
 #pragma unroll
         for (int e = 0; e < VEC; ++e) W[0][P][e] = inrow[e];
-        if (HELM) {
+        if (GRING) {
             V x;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) x[e] = grow[e];
@@ -384,7 +414,12 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
             const T wl = lane_shift<kDppWaveShr1>(src[PC][VEC - 1]);
             const T er = lane_shift<kDppWaveShl1>(src[PC][0]);
             T gv[VEC];
-            if (HELM) {
+            if (SEP) {
+                // rows outside the grid only feed cells that are never stored
+                const double pr = (row >= 0 && row < rows) ? sep.p[row] : 0.0;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) gv[e] = sep_value<T>(sep, pr, qv[e]);
+            } else if (HELM) {
                 int s2 = slot - (j - 1);
                 if (s2 < 0) s2 += K;
                 const V x = ring[s2 * 64];   // g row i - j
@@ -464,7 +499,7 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 load(fast_tag, a, i0 + q, in[q], false);
-                if (HELM) load(fast_tag, g, i0 + q - 1, gin[q], NTG);
+                if (GRING) load(fast_tag, g, i0 + q - 1, gin[q], NTG);
             }
             step(fast_tag, std::integral_constant<int, 0>{}, i0, in[0], gin[0]);
             step(fast_tag, std::integral_constant<int, 1>{}, i0 + 1, in[1], gin[1]);

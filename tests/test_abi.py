@@ -61,6 +61,12 @@ def _c(kind=L.LSR_COND_BELOW, thr=1e-6, every=1, window=10):
     return L.make_cond(kind, thr, every, window)
 
 
+def _sep(dtype=L.LSR_F64, env1=True, param=(1.0, 0.1, 20.7, 0.01)):
+    g = _g(dtype=dtype, env0=FAKE, param=param)
+    g.env1 = FAKE if env1 else None
+    return g
+
+
 VALID = [
     (_g(), L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA, _c()),
     (_g(dtype=L.LSR_F32), L.LSR_ST_LAPLACE5, L.LSR_RED_L2_DELTA, _c(L.LSR_COND_NEVER)),
@@ -76,6 +82,8 @@ VALID = [
     (_g(dtype=L.LSR_F32, bc=L.LSR_BC_BOTTOM, env0=FAKE, param=(100.0,)), L.LSR_ST_RESTORE,
      L.LSR_RED_MEAN_ABS_DELTA, _c(thr=0.1)),
     (_g(1, 1, dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER)),
+    (_sep(), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_L2_DELTA, _c(every=10)),
+    (_sep(dtype=L.LSR_F32), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_MAX_ABS_DELTA, _c()),
 ]
 
 
@@ -122,6 +130,13 @@ INVALID = [
     ("sobel below", _g(dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(), 1),
     ("sobel env", _g(dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM, env0=FAKE), L.LSR_ST_SOBEL, L.LSR_RED_SUM,
      _c(L.LSR_COND_NEVER), 1),
+    ("sep without q", _sep(env1=False), L.LSR_ST_HELMHOLTZ5_SEP, 2, _c(), 10),
+    ("sep without p", _g(), L.LSR_ST_HELMHOLTZ5_SEP, 2, _c(), 10),
+    ("sep nan c1", _sep(param=(1.0, 0.1, float("nan"), 1.0)), L.LSR_ST_HELMHOLTZ5_SEP, 2, _c(), 10),
+    ("sep f32 alpha h^2 > 4", _sep(dtype=L.LSR_F32, param=(4.5, 1.0, 1.0, 1.0)),
+     L.LSR_ST_HELMHOLTZ5_SEP, 2, _c(), 10),
+    ("sep sum reduce", _sep(), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_SUM, _c(), 10),
+    ("env1 on helmholtz", _sep(), L.LSR_ST_HELMHOLTZ5, 2, _c(), 10),
     ("unknown stencil", _g(), 99, 1, _c(), 10),
     ("env1 set", None, L.LSR_ST_LAPLACE5, 1, _c(), 10),
 ]
