@@ -67,6 +67,11 @@ def _load():
         lib.orc_jacobi_sep_run.argtypes = [P, P, P, C.c_double, C.c_double, C.c_int64, C.c_int64,
                                            C.c_double, C.c_double, C.c_int, C.c_int, C.c_double,
                                            C.c_int, C.c_int64, P, C.c_int64, C.POINTER(_Res)]
+        lib.orc_box_run.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_double,
+                                    C.c_int, C.c_int64, P, C.c_int64, C.POINTER(_Res)]
+        lib.orc_jacobi3d_run.argtypes = [P, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                         C.c_double, C.c_int, C.c_int64, P, C.c_int64,
+                                         C.POINTER(_Res)]
         lib.orc_sobel_run.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int64, P, C.c_int64,
                                       C.POINTER(_Res)]
         lib.orc_restore_argmin.argtypes = [P, C.c_int, C.c_double, C.c_int]
@@ -200,6 +205,39 @@ def sobel_run(a: np.ndarray, *, check_every: int = 1, max_iter: int = 1,
     res = _Res()
     rc = lib.orc_sobel_run(_ptr(a), a.shape[0], a.shape[1], int(check_every), int(max_iter),
                            _ptr(trace), int(trace_cap), C.byref(res))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return a, _result(res, trace[:trace_cap])
+
+
+def box_run(a: np.ndarray, k: int, *, reduce_op: int = RED_MAX_ABS_DELTA, cond: int = COND_BELOW,
+            thr: float = 1e-6, check_every: int = 1, max_iter: int = 100,
+            trace_cap: int = 0) -> tuple[np.ndarray, OracleResult]:
+    """Radius-k box-mean Jacobi (sigma_k): FP64, band of width k fixed."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64).copy()
+    trace = np.zeros(max(trace_cap, 1), dtype=np.float64)
+    res = _Res()
+    rc = lib.orc_box_run(_ptr(a), a.shape[0], a.shape[1], int(k), int(reduce_op), int(cond),
+                         float(thr), int(check_every), int(max_iter), _ptr(trace), int(trace_cap),
+                         C.byref(res))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return a, _result(res, trace[:trace_cap])
+
+
+def jacobi3d_run(a: np.ndarray, *, reduce_op: int = RED_MAX_ABS_DELTA, cond: int = COND_BELOW,
+                 thr: float = 1e-6, check_every: int = 1, max_iter: int = 100,
+                 trace_cap: int = 0) -> tuple[np.ndarray, OracleResult]:
+    """3D 7-point Jacobi on an (nz, ny, nx) FP64 array with fixed faces."""
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64).copy()
+    nz, ny, nx = a.shape
+    trace = np.zeros(max(trace_cap, 1), dtype=np.float64)
+    res = _Res()
+    rc = lib.orc_jacobi3d_run(_ptr(a), nz, ny, nx, int(reduce_op), int(cond), float(thr),
+                              int(check_every), int(max_iter), _ptr(trace), int(trace_cap),
+                              C.byref(res))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return a, _result(res, trace[:trace_cap])

@@ -467,3 +467,128 @@ int orc_sobel_run(uint8_t *a, int64_t rows, int64_t cols, int check_every, int64
     free(nxt);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Radius-k box stencil (sigma_k of Sect. 3.1 with k > 1): every cell at least */
+/* k from the edge takes the mean of its (2k+1) x (2k+1) neighbourhood; the     */
+/* outer band of width k is boundary data, never updated. Summation order:     */
+/* each row of the box left to right, then the row sums top to bottom, then one */
+/* division by the cell count (2k+1)^2.                                         */
+/* ------------------------------------------------------------------------- */
+static void box_sweep(const double *a, double *b, int64_t rows, int64_t cols, int k) {
+    const double cnt = (double)((2 * k + 1) * (2 * k + 1));
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < rows; ++i) {
+        for (int64_t j = 0; j < cols; ++j) {
+            int64_t p = i * cols + j;
+            if (i < k || j < k || i >= rows - k || j >= cols - k) {
+                b[p] = a[p];
+                continue;
+            }
+            double total = 0.0;
+            for (int di = -k; di <= k; ++di) {
+                double row = 0.0;
+                for (int dj = -k; dj <= k; ++dj) row = row + a[(i + di) * cols + (j + dj)];
+                total = total + row;
+            }
+            b[p] = total / cnt;
+        }
+    }
+}
+
+int orc_box_run(double *a, int64_t rows, int64_t cols, int k, int reduce_op, int cond_kind,
+                double thr, int check_every, int64_t max_iter, double *trace, int64_t trace_cap,
+                orc_result *out) {
+    if (!a || !out || k < 1 || rows < 2 * k + 1 || cols < 2 * k + 1 || check_every < 1 ||
+        max_iter < 1) return -1;
+    if (reduce_op != ORC_RED_MAX_ABS_DELTA && reduce_op != ORC_RED_L2_DELTA &&
+        reduce_op != ORC_RED_MEAN_ABS_DELTA) return -1;
+    if (cond_kind != ORC_COND_BELOW && cond_kind != ORC_COND_NEVER) return -1;
+    size_t bytes = sizeof(double) * (size_t)(rows * cols);
+    double *cur = (double *)malloc(bytes), *nxt = (double *)malloc(bytes);
+    memcpy(cur, a, bytes);
+    memset(out, 0, sizeof *out);
+    out->r = NAN;
+    int64_t n = 0;
+    int stop = 0;
+    do {
+        box_sweep(cur, nxt, rows, cols, k);
+        n = n + 1;
+        if (is_check_sweep(n, check_every, max_iter)) {
+            double r = reduce_delta(reduce_op, nxt, cur, rows, cols);
+            if (trace && out->checks < trace_cap) trace[out->checks] = r;
+            out->checks += 1;
+            out->r = r;
+            if (isnan(r) || isinf(r)) { out->numeric_error = 1; stop = 1; }
+            else if (cond_kind == ORC_COND_BELOW && r < thr) { out->converged = 1; stop = 1; }
+        }
+        double *t = cur; cur = nxt; nxt = t;
+    } while (!stop && n < max_iter);
+    memcpy(a, cur, bytes);
+    out->n = n;
+    free(cur);
+    free(nxt);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* 3D 7-point Jacobi (Laplace): a grid of nz planes of ny rows of nx cells,     */
+/* stored plane after plane; the six faces are boundary data. Interior update:  */
+/* b = (((W + E) + (N + S)) + (U + D)) / 6, W/E along x, N/S along y, U/D along  */
+/* z. reduce and condition as for the 2D Jacobi.                                */
+/* ------------------------------------------------------------------------- */
+static void jacobi3d_sweep(const double *a, double *b, int64_t nz, int64_t ny, int64_t nx) {
+    const int64_t plane = ny * nx;
+    int64_t z;
+#pragma omp parallel for schedule(static)
+    for (z = 0; z < nz; ++z) {
+        for (int64_t y = 0; y < ny; ++y) {
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t p = z * plane + y * nx + x;
+                if (z == 0 || y == 0 || x == 0 || z == nz - 1 || y == ny - 1 || x == nx - 1) {
+                    b[p] = a[p];
+                    continue;
+                }
+                double w = a[p - 1], e = a[p + 1], n = a[p - nx], s = a[p + nx];
+                double u = a[p - plane], d = a[p + plane];
+                b[p] = (((w + e) + (n + s)) + (u + d)) / 6.0;
+            }
+        }
+    }
+}
+
+int orc_jacobi3d_run(double *a, int64_t nz, int64_t ny, int64_t nx, int reduce_op, int cond_kind,
+                     double thr, int check_every, int64_t max_iter, double *trace,
+                     int64_t trace_cap, orc_result *out) {
+    if (!a || !out || nz < 3 || ny < 3 || nx < 3 || check_every < 1 || max_iter < 1) return -1;
+    if (reduce_op != ORC_RED_MAX_ABS_DELTA && reduce_op != ORC_RED_L2_DELTA &&
+        reduce_op != ORC_RED_MEAN_ABS_DELTA) return -1;
+    if (cond_kind != ORC_COND_BELOW && cond_kind != ORC_COND_NEVER) return -1;
+    size_t bytes = sizeof(double) * (size_t)(nz * ny * nx);
+    double *cur = (double *)malloc(bytes), *nxt = (double *)malloc(bytes);
+    memcpy(cur, a, bytes);
+    memset(out, 0, sizeof *out);
+    out->r = NAN;
+    int64_t n = 0;
+    int stop = 0;
+    do {
+        jacobi3d_sweep(cur, nxt, nz, ny, nx);
+        n = n + 1;
+        if (is_check_sweep(n, check_every, max_iter)) {
+            /* the reduce runs over all cells; faces contribute a zero change */
+            double r = reduce_delta(reduce_op, nxt, cur, nz * ny, nx);
+            if (trace && out->checks < trace_cap) trace[out->checks] = r;
+            out->checks += 1;
+            out->r = r;
+            if (isnan(r) || isinf(r)) { out->numeric_error = 1; stop = 1; }
+            else if (cond_kind == ORC_COND_BELOW && r < thr) { out->converged = 1; stop = 1; }
+        }
+        double *t = cur; cur = nxt; nxt = t;
+    } while (!stop && n < max_iter);
+    memcpy(a, cur, bytes);
+    out->n = n;
+    free(cur);
+    free(nxt);
+    return 0;
+}

@@ -122,6 +122,25 @@ double orc_restore_argmin(const double *v, int count, double beta, int quadratic
 int orc_sobel_run(uint8_t *a, int64_t rows, int64_t cols, int check_every, int64_t max_iter,
                   uint64_t *trace, int64_t trace_cap, orc_result *out);
 
+/*
+ * Radius-k box stencil (sigma_k, k >= 1): cells at least k from the edge take the
+ * mean of their (2k+1)^2 neighbourhood (rows of the box summed left to right, the
+ * row sums top to bottom, one division by (2k+1)^2); the band of width k at the
+ * edge is fixed. reduce / cond as orc_jacobi_run.
+ */
+int orc_box_run(double *a, int64_t rows, int64_t cols, int k, int reduce_op, int cond_kind,
+                double thr, int check_every, int64_t max_iter, double *trace, int64_t trace_cap,
+                orc_result *out);
+
+/*
+ * 3D 7-point Jacobi on nz planes of ny x nx cells (plane after plane, row-major);
+ * the faces are fixed; b = (((W+E) + (N+S)) + (U+D)) / 6 inside. reduce / cond as
+ * orc_jacobi_run, over all cells.
+ */
+int orc_jacobi3d_run(double *a, int64_t nz, int64_t ny, int64_t nx, int reduce_op, int cond_kind,
+                     double thr, int check_every, int64_t max_iter, double *trace,
+                     int64_t trace_cap, orc_result *out);
+
 #ifdef __cplusplus
 }
 #endif
