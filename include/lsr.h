@@ -84,7 +84,7 @@ typedef enum {
                                Sobel derivative masks and samples outside the image 0 (the edge
                                detector of Sect. 4.2, a single-iteration pattern: max_iter = 1,
                                cond NEVER; the reduce SUM is the sum of the new image) */
-    LSR_ST_HELMHOLTZ5_SEP = 6 /* the -i form of HELMHOLTZ5 (Sect. 3.1: the elemental function also
+    LSR_ST_HELMHOLTZ5_SEP = 6, /* the -i form of HELMHOLTZ5 (Sect. 3.1: the elemental function also
                                receives the cell's index): g(i, j) = c2 * (c1 * (p[i] * q[j])),
                                evaluated in FP64 from the cell's indices, replaces the env array;
                                env0 = p (rows FP64 values), env1 = q (cols FP64 values), both
@@ -92,6 +92,13 @@ typedef enum {
                                param[3] = c2. With the factors of a separable right-hand side it
                                gives HELMHOLTZ5's result bit for bit while reading 16 instead of
                                24 bytes per cell update. Plain contexts and device buffers only */
+    LSR_ST_BOX = 7,         /* radius-k box mean (sigma_k of Sect. 3.1, k = param[0] in 1..4): cells at
+                               least k from the edge take the mean of their (2k+1)^2 neighbourhood
+                               (box rows summed left to right, the row sums top to bottom, one
+                               division by (2k+1)^2); the band of width k is fixed (bc RING) */
+    LSR_ST_LAPLACE7_3D = 8  /* 3D 7-point Jacobi on nz planes of ny rows stored plane after plane
+                               (rows = nz * ny, param[0] = ny, cols = nx, pitch per row): inside,
+                               b = (((W+E) + (N+S)) + (U+D)) / 6; the six faces are fixed (bc RING) */
 } lsr_stencil_id;
 
 typedef enum {
@@ -246,6 +253,9 @@ lsr_status lsr_tune_import(lsr_ctx *ctx, const char *json);
  *   RESTORE    F64|F32  BOTTOM          env0 mask (u8)   MAX_ABS|MEAN_ABS     BELOW|NEVER
  *   SOBEL      U8       BOTTOM          env0 NULL        SUM                  NEVER
  *   HELMHOLTZ5_SEP F64|F32 RING         env0 p, env1 q   as HELMHOLTZ5        as HELMHOLTZ5
+ *   BOX        F64|F32  RING            env0 NULL        MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
+ *   LAPLACE7_3D F64|F32 RING            env0 NULL        MAX_ABS|L2|MEAN_ABS  BELOW|NEVER
+ * (HELMHOLTZ5_SEP, BOX and LAPLACE7_3D run on plain contexts only.)
  * EINVAL: null pointers, rows/cols too small, pitch < cols, a combination outside the table,
  * check_every < 1, max_iter < 1, stable_window < 1 with STABLE_FOR. ENOMEM/EBUSY: scratch.
  */

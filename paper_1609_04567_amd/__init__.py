@@ -12,7 +12,7 @@ from ._native import (  # noqa: F401
     LSR_COND_STABLE_FOR, LSR_FLAG_BATCHED, LSR_EBUSY, LSR_ECANCELED, LSR_EDEVICE, LSR_EINVAL, LSR_ENOMEM,
     LSR_ENOTFOUND, LSR_ENUMERIC, LSR_F32, LSR_F64, LSR_OK, LSR_RED_L2_DELTA,
     LSR_RED_MAX_ABS_DELTA, LSR_RED_MEAN_ABS_DELTA, LSR_RED_SUM, LSR_ST_HELMHOLTZ5,
-    LSR_ST_HELMHOLTZ5_SEP,
+    LSR_ST_HELMHOLTZ5_SEP, LSR_ST_BOX, LSR_ST_LAPLACE7_3D,
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_ST_SOBEL, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
     lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_noalloc, lsr_run_restore_host,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBUSY", 4: "EDEVICE", 5: 
 LSR_U8, LSR_F32, LSR_F64 = 1, 4, 8
 LSR_BC_RING, LSR_BC_TORUS, LSR_BC_BOTTOM = 0, 1, 2
 LSR_ST_LAPLACE5, LSR_ST_HELMHOLTZ5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_ST_SOBEL = 1, 2, 3, 4, 5
-LSR_ST_HELMHOLTZ5_SEP = 6
+LSR_ST_HELMHOLTZ5_SEP, LSR_ST_BOX, LSR_ST_LAPLACE7_3D = 6, 7, 8
 LSR_RED_MAX_ABS_DELTA, LSR_RED_L2_DELTA, LSR_RED_SUM, LSR_RED_MEAN_ABS_DELTA = 1, 2, 3, 4
 LSR_COND_BELOW, LSR_COND_STABLE_FOR, LSR_COND_NEVER = 1, 2, 3
 LSR_FLAG_BATCHED = 1

@@ -11,8 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblsr.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["control.hip", "jacobi.hip", "jacobi_tb.hip", "life.hip", "life_tb.hip", "restore.hip",
-           "sobel.hip", "probe.hip", "batch.hip", "noalloc.hip", "runtime.cpp", "engine.cpp",
-           "autotune.cpp"]
+           "sobel.hip", "generic.hip", "probe.hip", "batch.hip", "noalloc.hip", "runtime.cpp",
+           "engine.cpp", "autotune.cpp"]
 ARCH = os.environ.get("LSR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -108,6 +108,17 @@ hipError_t launch_restore(const RestoreArgs& a, const SweepGeom& g, JobState* st
 hipError_t launch_amf_detect(const uint8_t* y, int64_t rows, int64_t cols, int64_t pitch,
                              int w_max, uint8_t* mask, void* u_init, int u_dtype, hipStream_t s);
 
+// Radius-k box stencil and 3D 7-point Jacobi (generic.hip) -------------------------
+SweepGeom box_geom(int64_t rows, int64_t cols);
+hipError_t launch_box(const void* a, void* b, int64_t rows, int64_t cols, int64_t pitch, int k,
+                      int f32, const SweepGeom& g, JobState* st, void* partials, const LoopCtl& c,
+                      int j, hipStream_t s);
+// the grid holds nz planes of ny rows (rows = nz * ny), each row `pitch` elements
+SweepGeom laplace3d_geom(int64_t nz, int64_t ny, int64_t nx);
+hipError_t launch_laplace3d(const void* a, void* b, int64_t nz, int64_t ny, int64_t nx,
+                            int64_t pitch, int f32, const SweepGeom& g, JobState* st,
+                            void* partials, const LoopCtl& c, int j, hipStream_t s);
+
 // Sobel edge detector (u8 in, u8 out; partials are u64 sums of the new image) ----
 SweepGeom sobel_geom(int64_t rows, int64_t cols);
 hipError_t launch_sobel(const uint8_t* a, uint8_t* b, int64_t rows, int64_t cols, int64_t pitch,

@@ -96,6 +96,30 @@ lsr_status lsr_rt::validate(const lsr_grid* g, int stencil, int reduce, const ls
             if (c->kind != LSR_COND_BELOW && c->kind != LSR_COND_NEVER)
                 return fail(LSR_EINVAL, "restoration conditions are BELOW or NEVER");
             break;
+        case LSR_ST_BOX:
+        case LSR_ST_LAPLACE7_3D: {
+            if (!fp) return fail(LSR_EINVAL, "box and 3D grids are F64 or F32");
+            if (g->bc != LSR_BC_RING) return fail(LSR_EINVAL, "box and 3D stencils use the RING boundary");
+            if (g->env0) return fail(LSR_EINVAL, "box and 3D stencils take no env0");
+            if (stencil == LSR_ST_BOX) {
+                const double k = g->param[0];
+                if (!(k == 1.0 || k == 2.0 || k == 3.0 || k == 4.0))
+                    return fail(LSR_EINVAL, "box radius param[0] must be 1, 2, 3 or 4");
+                if (g->rows < 2 * (int64_t)k + 1 || g->cols < 2 * (int64_t)k + 1)
+                    return fail(LSR_EINVAL, "the grid must be at least 2k+1 wide");
+            } else {
+                const double ny = g->param[0];
+                if (!(ny >= 3.0 && ny == std::floor(ny)) || ny > (double)g->rows ||
+                    g->rows % (int64_t)ny != 0 || g->rows / (int64_t)ny < 3 || g->cols < 3)
+                    return fail(LSR_EINVAL, "3D grids: param[0] = ny >= 3 dividing rows, nz = rows/ny "
+                                            ">= 3, cols = nx >= 3");
+            }
+            if (reduce != LSR_RED_MAX_ABS_DELTA && reduce != LSR_RED_L2_DELTA && reduce != LSR_RED_MEAN_ABS_DELTA)
+                return fail(LSR_EINVAL, "box and 3D reduces are MAX_ABS_DELTA, L2_DELTA, MEAN_ABS_DELTA");
+            if (c->kind != LSR_COND_BELOW && c->kind != LSR_COND_NEVER)
+                return fail(LSR_EINVAL, "box and 3D conditions are BELOW or NEVER");
+            break;
+        }
         case LSR_ST_SOBEL:
             if (g->rows < 1 || g->cols < 1) return fail(LSR_EINVAL, "empty grid");
             if (g->dtype != LSR_U8) return fail(LSR_EINVAL, "Sobel images are U8");
@@ -212,6 +236,16 @@ lsr_status lsr_rt::launch_sweep(Job* j, int off, hipStream_t s) {
         case LSR_ST_LIFE:
             e = lsr::launch_life(life_args(j, src, dst), j->geom, j->st, j->partials, j->ctl, off, s);
             break;
+        case LSR_ST_BOX:
+            e = lsr::launch_box(src, dst, g.rows, g.cols, g.pitch, (int)g.param[0],
+                                g.dtype == LSR_F32, j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        case LSR_ST_LAPLACE7_3D: {
+            const int64_t ny = (int64_t)g.param[0];
+            e = lsr::launch_laplace3d(src, dst, g.rows / ny, ny, g.cols, g.pitch, g.dtype == LSR_F32,
+                                      j->geom, j->st, j->partials, j->ctl, off, s);
+            break;
+        }
         case LSR_ST_SOBEL:
             e = lsr::launch_sobel(static_cast<const uint8_t*>(src), static_cast<uint8_t*>(dst), g.rows,
                                   g.cols, g.pitch, j->geom, j->st, j->partials, j->ctl, off, s);
@@ -593,6 +627,8 @@ lsr_status lsr_rt::submit(lsr_ctx* ctx, const lsr_grid* grid, int32_t stencil_id
     if (v != LSR_OK) return v;
     if (stencil_id == LSR_ST_HELMHOLTZ5_SEP && (host || ctx->batched))
         return fail(LSR_EINVAL, "the -i Helmholtz form runs on device buffers on a plain context");
+    if ((stencil_id == LSR_ST_BOX || stencil_id == LSR_ST_LAPLACE7_3D) && ctx->batched)
+        return fail(LSR_EINVAL, "box and 3D stencils run on a plain context");
     HIP_TRY(hipSetDevice(ctx->device));
     std::unique_ptr<Job> j(new Job());
     j->host = host;
@@ -651,6 +687,12 @@ lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int*
             }
             case LSR_ST_SOBEL:
                 j->geom = lsr::sobel_geom(g.rows, g.cols);
+                break;
+            case LSR_ST_BOX:
+                j->geom = lsr::box_geom(g.rows, g.cols);
+                break;
+            case LSR_ST_LAPLACE7_3D:
+                j->geom = lsr::laplace3d_geom(g.rows / (int64_t)g.param[0], (int64_t)g.param[0], g.cols);
                 break;
             default: {
                 lsr::RestoreArgs a{};

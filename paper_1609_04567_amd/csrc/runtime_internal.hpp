@@ -150,7 +150,8 @@ inline bool life_rows_direct(const lsr_grid& g) {
 
 // True when a job runs on staged copies (see Job::staged).
 inline bool needs_staging(const lsr_grid& g, int stencil) {
-    if (stencil == LSR_ST_LAPLACE5 || stencil == LSR_ST_HELMHOLTZ5) return !jacobi_rows_aligned(g, stencil);
+    if (stencil == LSR_ST_LAPLACE5 || stencil == LSR_ST_HELMHOLTZ5 || stencil == LSR_ST_HELMHOLTZ5_SEP)
+        return !jacobi_rows_aligned(g, stencil);
     if (stencil == LSR_ST_LIFE) return !life_rows_direct(g);
     return false;
 }

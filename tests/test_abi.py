@@ -84,6 +84,10 @@ VALID = [
     (_g(1, 1, dtype=L.LSR_U8, bc=L.LSR_BC_BOTTOM), L.LSR_ST_SOBEL, L.LSR_RED_SUM, _c(L.LSR_COND_NEVER)),
     (_sep(), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_L2_DELTA, _c(every=10)),
     (_sep(dtype=L.LSR_F32), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_MAX_ABS_DELTA, _c()),
+    (_g(9, 9, param=(4.0,)), L.LSR_ST_BOX, L.LSR_RED_MAX_ABS_DELTA, _c()),
+    (_g(dtype=L.LSR_F32, param=(1.0,)), L.LSR_ST_BOX, L.LSR_RED_L2_DELTA, _c(L.LSR_COND_NEVER)),
+    (_g(12, 5, param=(4.0,)), L.LSR_ST_LAPLACE7_3D, L.LSR_RED_MAX_ABS_DELTA, _c()),
+    (_g(9, 3, dtype=L.LSR_F32, param=(3.0,)), L.LSR_ST_LAPLACE7_3D, L.LSR_RED_MEAN_ABS_DELTA, _c()),
 ]
 
 
@@ -137,6 +141,15 @@ INVALID = [
      L.LSR_ST_HELMHOLTZ5_SEP, 2, _c(), 10),
     ("sep sum reduce", _sep(), L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_SUM, _c(), 10),
     ("env1 on helmholtz", _sep(), L.LSR_ST_HELMHOLTZ5, 2, _c(), 10),
+    ("box radius 5", _g(param=(5.0,)), L.LSR_ST_BOX, 1, _c(), 10),
+    ("box radius 1.5", _g(param=(1.5,)), L.LSR_ST_BOX, 1, _c(), 10),
+    ("box too small", _g(8, 8, param=(4.0,)), L.LSR_ST_BOX, 1, _c(), 10),
+    ("box u8", _g(dtype=L.LSR_U8, param=(1.0,)), L.LSR_ST_BOX, 1, _c(), 10),
+    ("box torus", _g(bc=L.LSR_BC_TORUS, param=(1.0,)), L.LSR_ST_BOX, 1, _c(), 10),
+    ("3d ny not dividing", _g(10, 5, param=(4.0,)), L.LSR_ST_LAPLACE7_3D, 1, _c(), 10),
+    ("3d nz < 3", _g(8, 5, param=(4.0,)), L.LSR_ST_LAPLACE7_3D, 1, _c(), 10),
+    ("3d ny < 3", _g(8, 5, param=(2.0,)), L.LSR_ST_LAPLACE7_3D, 1, _c(), 10),
+    ("3d sum reduce", _g(12, 5, param=(4.0,)), L.LSR_ST_LAPLACE7_3D, L.LSR_RED_SUM, _c(), 10),
     ("unknown stencil", _g(), 99, 1, _c(), 10),
     ("env1 set", None, L.LSR_ST_LAPLACE5, 1, _c(), 10),
 ]
