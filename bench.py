@@ -115,9 +115,19 @@ def run_helmholtz(args, L, I, torch):
                  "unroll": b.unroll, "tuning_s": round(time.perf_counter() - t0, 2)}
         print(f"autotune: {tuned}", file=sys.stderr, flush=True)
 
-    def step(t):
-        return ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, sweeps, L.LSR_BC_RING,
-                       env0=g, param=(h.alpha, h.h))
+    if args.form == "sep":
+        # the -i form: g from the cell's indices and the factor vectors (same result)
+        sv, hh = I.helmholtz_factor(n)
+        fac = torch.from_numpy(sv).to(dev)
+
+        def step(t):
+            return ctx.run(t, L.LSR_ST_HELMHOLTZ5_SEP, L.LSR_RED_L2_DELTA, cond, sweeps,
+                           L.LSR_BC_RING, env0=fac, env1=fac,
+                           param=(h.alpha, h.h, 2 * math.pi ** 2 + h.alpha, hh * hh))
+    else:
+        def step(t):
+            return ctx.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, cond, sweeps, L.LSR_BC_RING,
+                           env0=g, param=(h.alpha, h.h))
 
     for k in range(args.warmup):
         r = step(grids[k])
@@ -1035,6 +1045,9 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--tb", type=int, default=0, help="Jacobi sweeps fused per launch (0 = auto)")
+    ap.add_argument("--form", default="array", choices=["array", "sep"],
+                    help="helmholtz: right-hand side read from an array, or the -i form (from the "
+                         "indices and two factor vectors)")
     ap.add_argument("--autotune", action="store_true",
                     help="measure launch settings for the job before timing it (helmholtz)")
     args = ap.parse_args()
