@@ -160,10 +160,15 @@ def run_helmholtz(args, L, I, torch):
                      "parallelism": "single-gpu"})
     # a launch reads u and g and writes u once, whatever number of sweeps it fuses
     kname = f"jacobi5_helmholtz_f64_{n}" if spl == 1 else f"jacobi5_tb{spl}_helmholtz_f64_{n}"
-    out["roofline"] = roofline(24.0 * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
-    out["roofline"]["basis"] = (f"compulsory bytes of one launch of {spl} fused sweeps: 24 B per "
-                                "interior cell (u and g read once, u written once), over the "
-                                "launch's mean device time")
+    bpc = 24.0 if args.form == "array" else 16.0   # the -i form reads no g array
+    if args.form == "sep":
+        kname += "_sep"
+        out["config"]["workload"] += ", right-hand side from the indices (-i form)"
+    out["roofline"] = roofline(bpc * (n - 2) ** 2, per_launch_s, measured_traffic(kname))
+    out["roofline"]["basis"] = (f"compulsory bytes of one launch of {spl} fused sweeps: {bpc:.0f} B "
+                                "per interior cell (u read and written once"
+                                + (", g read once" if bpc == 24.0 else "") +
+                                "), over the launch's mean device time")
     out["copy_probe_gbs"] = copy_gbs
     if tuned:
         out["autotuned"] = tuned
