@@ -138,3 +138,16 @@ def test_restore_mask_extremes_match_oracle(ctx, pattern, shape):
     assert res.status == L.LSR_OK
     assert res.iterations == ro.n and bool(res.converged) == ro.converged
     assert rel_err(x, o) <= 1e-12
+
+
+def test_detection_matches_hand_derived_golden(ctx):
+    """The GPU detection on the hand-derived cases of tests/golden/amf_hand.txt."""
+    import torch
+    from test_oracle_restore import _amf_hand_cases
+    say("detection hand golden")
+    for name, c in _amf_hand_cases().items():
+        y = torch.from_numpy(c["y"]).to("cuda:0")
+        m, u = ctx.amf_detect(y, c["w"], torch.uint8)
+        torch.cuda.synchronize()
+        assert np.array_equal(m.cpu().numpy(), c["mask"]), name
+        assert np.array_equal(u.cpu().numpy(), c["init"]), name

@@ -10,6 +10,8 @@ Parity unpinned by the paper: phi(t) = sqrt(beta + t^2), beta = 100, w_max = 19
 and the detection edge rules are this project's readings; the paper only names
 the method.
 """
+import os
+
 import numpy as np
 import pytest
 from scipy.optimize import minimize_scalar
@@ -139,3 +141,27 @@ def test_mean_abs_reduce_matches_definition():
     u = u0.astype(np.float64)
     b, res = O.restore_run(u, m, reduce_op=O.RED_MEAN_ABS_DELTA, cond=O.COND_NEVER, max_iter=1)
     assert abs(res.r - np.abs(b - u).sum() / u.size) < 1e-14 * 255
+
+
+def _amf_hand_cases():
+    """Cases of tests/golden/amf_hand.txt: images with masks and initial values derived
+    by hand from the detection rule (the derivation is in the file)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "amf_hand.txt")
+    cases, cur = {}, None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        if t[0] == "case":
+            cur = dict(rows=int(t[2]), cols=int(t[3]), w=int(t[4]))
+            cases[t[1]] = cur
+        else:
+            cur[t[0]] = np.array([int(v) for v in t[1:]], np.uint8).reshape(cur["rows"], cur["cols"])
+    return cases
+
+
+def test_detection_matches_hand_derived_golden():
+    for name, c in _amf_hand_cases().items():
+        m, u = O.amf_detect(c["y"], c["w"])
+        assert np.array_equal(m, c["mask"]), name
+        assert np.array_equal(u, c["init"]), name
