@@ -551,7 +551,7 @@ class _StreamRun:
                     self.collected += 1
                     done = self.collected
                 self.pool.submit(self._finish, k, v, job, r, need)
-                if done % 1000 == 0:   # progress of long streams
+                if done % 250 == 0:   # progress of long streams
                     print(f"  {done} / {self.total} results", file=sys.stderr, flush=True)
         except BaseException as e:
             with self.cv:
@@ -571,9 +571,40 @@ class _StreamRun:
                 self.out_bytes -= need
                 self.cv.notify_all()
 
+    def _stall_guard(self, stall_s=120.0):
+        """Ends the process (exit status 3) with a description of the stream's and the
+        context's state when no result has arrived for stall_s seconds."""
+        last, t_last = -1, time.monotonic()
+        while True:
+            time.sleep(5.0)
+            with self.cv:
+                done = self.collected >= self.total or self.error is not None
+                c = self.collected
+            if done:
+                return
+            if c != last:
+                last, t_last = c, time.monotonic()
+                continue
+            if time.monotonic() - t_last < stall_s:
+                continue
+            with self.cv:
+                oldest = sorted(self.jobs.items())[:8]
+                state = {"submitted": self.submitted, "collected": self.collected,
+                         "total": self.total, "out_bytes": self.out_bytes,
+                         "next_gen": self.next_gen, "ready": sorted(self.ready)[:8],
+                         "in_flight": [(jid, k, v, self.specs[k].kind, self.specs[k].side)
+                                       for jid, (k, v, _, _) in oldest]}
+            print(f"STALL: no result for {stall_s:.0f} s: {state}", file=sys.stderr, flush=True)
+            try:
+                print(f"STALL: context {self.ctx.stats()}", file=sys.stderr, flush=True)
+            except Exception as e:   # the report must not hide the stall
+                print(f"STALL: stats failed: {e}", file=sys.stderr, flush=True)
+            os._exit(3)
+
     def run(self):
         """Runs the stream; returns the wall time from the first submission to the
         last result (checks of the last jobs excluded)."""
+        threading.Thread(target=self._stall_guard, daemon=True).start()
         gens = [threading.Thread(target=self._gen, daemon=True) for _ in range(self.gen_threads)]
         for g in gens:
             g.start()

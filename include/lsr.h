@@ -329,6 +329,23 @@ lsr_status lsr_result(lsr_ctx *ctx, lsr_job job, int32_t wait, lsr_job_result *o
  */
 lsr_status lsr_wait_any(lsr_ctx *ctx, int32_t wait, lsr_job *job_out);
 
+/* A snapshot of a context's queues and memory, for a serving loop's monitoring. */
+typedef struct {
+    int64_t pending;            /* submitted and not yet admitted (batched) or started (plain) */
+    int64_t ingesting;          /* batched: host jobs whose H2D copies are in flight */
+    int64_t active;             /* in the sweep rounds (batched); running (plain) */
+    int64_t retiring;           /* batched: stopped, result being copied out */
+    int64_t unfinished;         /* submitted and not finished */
+    int64_t finished_untaken;   /* finished, result not yet taken with lsr_result */
+    uint64_t pool_live_bytes;   /* device memory the jobs hold from the pool */
+    uint64_t pool_cached_bytes; /* freed blocks the pool keeps for reuse */
+    uint64_t pool_budget_bytes; /* hbm_budget_bytes in force */
+} lsr_stats;
+
+/* Fills *out (EINVAL for NULL). The counts are consistent with each other only
+ * approximately: the engine publishes its own after every pass of its loop. */
+lsr_status lsr_get_stats(lsr_ctx *ctx, lsr_stats *out);
+
 /* Requests cancellation; the job stops at its next chunk boundary with ECANCELED. */
 lsr_status lsr_cancel(lsr_ctx *ctx, lsr_job job);
 

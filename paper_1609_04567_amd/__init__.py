@@ -16,7 +16,8 @@ from ._native import (  # noqa: F401
     LSR_ST_LAPLACE5, LSR_ST_LIFE, LSR_ST_RESTORE, LSR_ST_SOBEL, LSR_U8, LsrError, lsr_amf_detect,
     lsr_autotune, lsr_cancel, lsr_check_args, lsr_create, lsr_destroy, lsr_last_error,
     lsr_probe_copy, lsr_result, lsr_run, lsr_run_host, lsr_run_noalloc, lsr_run_restore_host,
-    lsr_set_tuning, lsr_tune_export, lsr_tune_import, lsr_version, lsr_wait_any, make_cond, make_grid,
+    lsr_set_tuning, lsr_tune_export, lsr_tune_import, lsr_version, lsr_wait_any, lsr_get_stats,
+    make_cond, make_grid,
 )
 
 
@@ -153,6 +154,10 @@ class Context:
     def wait_any(self, wait=True):
         """Id of a finished job whose result is not taken yet (lsr_wait_any)."""
         return lsr_wait_any(self.handle, wait)
+
+    def stats(self):
+        """Queue and memory snapshot (lsr_get_stats)."""
+        return lsr_get_stats(self.handle)
 
     def cancel(self, job):
         lsr_cancel(self.handle, job)

@@ -58,6 +58,16 @@ class lsr_tuning(C.Structure):
                 ("use_graph", C.c_int32), ("waves", C.c_int32), ("unroll", C.c_int32)]
 
 
+class lsr_stats(C.Structure):
+    _fields_ = [("pending", C.c_int64), ("ingesting", C.c_int64), ("active", C.c_int64),
+                ("retiring", C.c_int64), ("unfinished", C.c_int64), ("finished_untaken", C.c_int64),
+                ("pool_live_bytes", C.c_uint64), ("pool_cached_bytes", C.c_uint64),
+                ("pool_budget_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class LsrError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -85,6 +95,7 @@ _SIGS = {
     "lsr_result": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(lsr_job_result)]),
     "lsr_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "lsr_wait_any": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    "lsr_get_stats": (C.c_int, [C.c_void_p, C.POINTER(lsr_stats)]),
     "lsr_amf_detect": (C.c_int, [C.c_void_p, C.POINTER(lsr_grid), C.c_void_p, C.c_void_p,
                                  C.c_int32, C.c_int32]),
     "lsr_check_args": (C.c_int, [C.POINTER(lsr_grid), C.c_int32, C.c_int32, C.POINTER(lsr_cond),
@@ -200,6 +211,12 @@ def lsr_wait_any(ctx: int, wait: bool = True) -> int | None:
         return None
     _check(st)
     return job.value
+
+
+def lsr_get_stats(ctx: int) -> dict:
+    out = lsr_stats()
+    _check(lib().lsr_get_stats(ctx, C.byref(out)))
+    return out.as_dict()
 
 
 def lsr_cancel(ctx: int, job: int) -> None:

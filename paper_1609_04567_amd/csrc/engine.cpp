@@ -580,6 +580,9 @@ void lsr_ctx::serve() {
             const bool nothing_else = active.empty() && inflight.empty();
             engine_poll_retiring(nothing_else && !retiring.empty());
         }
+        pub_ingesting.store((int64_t)ingesting.size());
+        pub_active.store((int64_t)active.size());
+        pub_retiring.store((int64_t)retiring.size());
         if (s != LSR_OK && s != LSR_EBUSY) {
             // a device failure ends every job of the context
             fatal = g_last_error;

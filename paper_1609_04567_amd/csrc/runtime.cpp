@@ -865,6 +865,28 @@ lsr_status lsr_wait_any(lsr_ctx* ctx, int32_t wait, lsr_job* job_out) {
     }
 }
 
+lsr_status lsr_get_stats(lsr_ctx* ctx, lsr_stats* out) {
+    if (!ctx || !out) return fail(LSR_EINVAL, "ctx and out must not be NULL");
+    lsr_stats s{};
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        s.pending = (int64_t)(ctx->batched ? ctx->pending.size() : ctx->queue.size());
+        s.unfinished = ctx->unfinished;
+        s.finished_untaken = (int64_t)ctx->jobs.size() - ctx->unfinished;
+    }
+    if (ctx->batched) {
+        s.ingesting = ctx->pub_ingesting.load();
+        s.active = ctx->pub_active.load();
+        s.retiring = ctx->pub_retiring.load();
+    } else {
+        s.active = s.unfinished - s.pending;
+    }
+    ctx->pool.usage(&s.pool_live_bytes, &s.pool_cached_bytes);
+    s.pool_budget_bytes = ctx->pool.budget();
+    *out = s;
+    return LSR_OK;
+}
+
 lsr_status lsr_cancel(lsr_ctx* ctx, lsr_job job) {
     if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->mu);

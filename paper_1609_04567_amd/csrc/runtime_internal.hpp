@@ -117,6 +117,11 @@ class Pool {
         live_bytes_ = 0;
     }
     uint64_t budget() const { return budget_; }
+    void usage(uint64_t* live, uint64_t* cached) {
+        std::lock_guard<std::mutex> lk(mu_);
+        *live = live_bytes_;
+        *cached = cached_;
+    }
 
   private:
     void trim_locked() {
@@ -329,6 +334,8 @@ struct lsr_ctx {
     int seg_len[lsr::kBatchKinds + 1] = {};
     int64_t work_items = 0;
     int n_table = 0;                    // jobs in the device table (small jobs are not)
+    // engine-thread counts published for lsr_get_stats (read from other threads)
+    std::atomic<int64_t> pub_ingesting{0}, pub_active{0}, pub_retiring{0};
     bool tables_dirty = false;
     void serve();
     lsr_status engine_submit(lsr_rt::Job* j);
