@@ -516,16 +516,23 @@ class _StreamRun:
         try:
             while True:
                 with self.cv:
+                    # host bytes are reserved in job order: a later job that fits
+                    # must not take the room an earlier one waits for, since jobs
+                    # are submitted in order (a job larger than the limit still
+                    # runs, alone)
+                    def fits():
+                        k = self.next_gen
+                        if self.error or k >= len(self.specs):
+                            return True
+                        need = sum(_job_bytes(self.I, self.specs[k], v) for v in self.variants)
+                        return self.out_bytes == 0 or self.out_bytes + need <= self.limit
+                    self.cv.wait_for(fits)
                     k = self.next_gen
                     if k >= len(self.specs) or self.error:
                         return
                     self.next_gen += 1
                     spec = self.specs[k]
-                    need = sum(_job_bytes(self.I, spec, v) for v in self.variants)
-                    # a job larger than the limit still runs, alone
-                    self.cv.wait_for(lambda: self.error or self.out_bytes == 0 or
-                                     self.out_bytes + need <= self.limit)
-                    self.out_bytes += need
+                    self.out_bytes += sum(_job_bytes(self.I, spec, v) for v in self.variants)
                 built = [(_make_host_job(self.L, self.I, self.torch, spec, v), v,
                           _job_bytes(self.I, spec, v)) for v in self.variants]
                 with self.cv:
