@@ -18,7 +18,8 @@ namespace {
 // FP64: at least three wavefronts per SIMD (168 VGPRs). At depth 10 the register
 // pipeline needs about 174, and the compiler fits it in 168 with a few values
 // spilled, which the third wavefront repays (8192^2 Helmholtz +10 %).
-template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP = false>
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP = false,
+          bool VERT = false>
 __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
@@ -40,7 +41,9 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_ke
     if (!MC) mask &= 1u << (K - 1);   // K divides the check period and the cap
     const int t = xcd_logical_tile(blockIdx.x, gridDim.x);
     if (t >= tiles) return;
-    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM && !SEP, false, MC, SEP>(
+    // FP64: g rows read two levels ahead (8192^2 Helmholtz, depth 10: +1.5 %)
+    jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM && !SEP, false, MC, SEP, VERT,
+                    sizeof(T) == 8 ? 2 : 0>(
         a, b, g, rows, cols, pitch, rd, rd_lo, (uint32_t)n1, mask, ctl.reduce, t, strips, tiles,
         tile_rows, partials, lds, gring, sep);
 }
@@ -55,15 +58,30 @@ bool waves_ok(int waves) { return waves == 1 || waves == 2 || waves == 4; }
 // until it has them; 1024^2 measured best at 4-row bands, 1280 tiles).
 constexpr int64_t kMinTiles = 1024;
 
-template <typename T, bool HELM, int VEC, int NW, int K, bool MC = false, bool SEP = false>
-hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+
+// Workgroups of several wavefronts take consecutive bands of one window, odd
+// bands streamed upwards (8192^2 FP64 Helmholtz: depth 10 +1-2 %, depth 5 +3 %).
+constexpr bool kVertical = true;
+
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP, bool VERT>
+hipError_t launch_v(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC, SEP>), dim3(g.blocks),
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC, SEP, VERT>), dim3(g.blocks),
                        dim3(NW * 64), 0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
                        T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,
                        g.tiles, g.tile_rows, SepSource{a.sp, a.sq, a.c1, a.c2});
     return hipGetLastError();
+}
+
+// several wavefronts per workgroup: vertical band groups (the geometry sets
+// g.vert the same way); one wavefront has no vertical layout
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC = false, bool SEP = false>
+hipError_t launch_t(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
+                    const LoopCtl& c, int j, hipStream_t s) {
+    constexpr bool kVert = NW > 1 && kVertical;
+    if (g.vert != (int)kVert) return hipErrorInvalidValue;
+    return launch_v<T, HELM, VEC, NW, K, MC, SEP, kVert>(a, g, st, partials, c, j, s);
 }
 
 // The -i form: compiled for two wavefronts per workgroup at depths 10 and 5.
@@ -150,6 +168,7 @@ void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int w
     g.mc = mc;
     g.waves = waves;
     g.unroll = 3;
+    g.vert = waves > 1 && kVertical;
     // deeper blocks want taller bands (the 2K halo rows are re-read per band),
     // small grids want more, shorter bands: a band is a serial stream of rows
     // through K levels, so a launch lasts as long as its tallest band (256^2
@@ -160,12 +179,14 @@ void jacobi_tb_geom(const JacobiArgs& a, int depth, int mc, int tile_rows, int w
     const int64_t ow = (64 * g.vec - 2 * depth) / g.vec * g.vec;
     const int64_t need = a.cols - 1 - depth;
     const int64_t nwin = need > 0 ? (need + ow - 1) / ow : 1;
-    g.strips = (int)((nwin + waves - 1) / waves);
+    // a workgroup: `waves` windows of one band, or (vert) `waves` bands of one window
+    g.strips = (int)(g.vert ? nwin : (nwin + waves - 1) / waves);
     auto bands_of = [&](int tr) { return (int)((a.rows - 2 + tr - 1) / tr); };
+    auto groups_of = [&](int tr) { return g.vert ? (bands_of(tr) + waves - 1) / waves : bands_of(tr); };
     if (tile_rows <= 0)
-        while (g.tile_rows > 2 && (int64_t)g.strips * bands_of(g.tile_rows) < kMinTiles)
+        while (g.tile_rows > 2 && (int64_t)g.strips * groups_of(g.tile_rows) < kMinTiles)
             g.tile_rows = g.tile_rows > 4 ? g.tile_rows / 2 : 2;
-    g.bands = bands_of(g.tile_rows);
+    g.bands = groups_of(g.tile_rows);
     g.tiles = g.strips * g.bands;
     g.blocks = pad_to_xcds(g.tiles);
 }

@@ -21,6 +21,7 @@ struct SweepGeom {
     int blocks = 0;      // tiles padded to a multiple of 8
     int tb = 1;          // sweeps advanced per launch (temporal blocking depth)
     int mc = 0;          // fused launches may hold several checks (partials per level)
+    int vert = 0;        // fused Jacobi: a workgroup's waves take consecutive bands of one window
 };
 
 // Jacobi 5-point (Laplace / Helmholtz) -------------------------------------

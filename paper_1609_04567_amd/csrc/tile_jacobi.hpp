@@ -301,8 +301,17 @@ constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 // partials[(j-1) * tiles + t], its delta taken against level j-1.
 // SEP: the -i form (HELM must be set): level j computes g of its row from `sep`
 // (no g rows are loaded and gring is unused).
+// VERT: the workgroup's NW wavefronts take NW consecutive bands of one window
+// (tile t = band group t / strips, window t % strips) instead of NW windows of
+// one band. Odd wavefronts stream their band upwards (from row r1 + K - 1 down to
+// r0 - K in index), so each pair of neighbouring bands reaches the 2K rows both
+// read at about the same time and the second read is served by the cache instead
+// of HBM. The N + S sum is commutative, so a band streamed upwards computes the
+// same values bit for bit; only the order of a lane's delta sum changes.
+// GA > 0: the g rows of the next GA levels are read from the ring ahead of their
+// use, so a level does not wait for its own LDS read.
 template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false,
-          bool MC = false, bool SEP = false>
+          bool MC = false, bool SEP = false, bool VERT = false, int GA = 0>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
@@ -314,28 +323,35 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
+    static_assert(!VERT || !WT, "vertical band groups are workgroup tiles");
     const bool check = (check_mask >> (K - 1)) & 1u;
-    const int band = t / strips, strip = t - band * strips;
+    const int tband = t / strips, strip = t - tband * strips;
     const int lane = threadIdx.x & 63;
     // the wavefront's slot in the workgroup (a wavefront tile of the batched kernel
     // is NW = 1 in a workgroup of several); readfirstlane keeps it scalar
     const int hw_wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wave = WT ? 0 : hw_wave;
-    const int64_t cw = ((int64_t)strip * NW + wave) * OW;       // window start (aligned)
+    const int band = VERT ? tband * NW + wave : tband;
+    const bool up = VERT && (wave & 1);
+    const int64_t cw = (VERT ? (int64_t)strip : (int64_t)strip * NW + wave) * OW;   // window start (aligned)
     const int64_t c = cw + (int64_t)lane * VEC;
     const int64_t olo = (cw == 0) ? 1 : cw + K;                  // output columns [olo, ohi)
     const int64_t ohi = min(cw + K + (int64_t)OW, cols - 1);
     const int64_t r0 = 1 + (int64_t)band * tile_rows;
-    const int64_t r1 = min(r0 + (int64_t)tile_rows, rows - 1);
-    // level-0 rows r0-K .. r1+K-1 stream through, three per iteration (the
-    // rows past r1+K-1 that round the count up are computed and never stored)
-    const int64_t i_beg = r0 - K;
-    const int64_t i_end = i_beg + (r1 + K - i_beg + 2) / 3 * 3;
+    const int64_t r1 = min(r0 + (int64_t)tile_rows, rows - 1);   // r0 >= r1: no rows (VERT)
+    // level-0 rows r0-K .. r1+K-1 stream through, three per iteration, from
+    // i_first (r0-K downwards, r1+K-1 upwards); the rows past the far end that
+    // round the count up are computed and never stored
+    const int64_t nstream = (r1 - r0 + 2 * K + 2) / 3 * 3;
+    const int64_t i_first = up ? r1 + K - 1 : r0 - K;
     // the window holds a ring column: per-lane selects needed
     const bool edge = (cw == 0) || (cw + 64 * VEC > cols - 1);
-    // every row a level computes (r0-2K .. i_end-2) is interior and every
-    // level-0 row loaded is in the grid: no row or column tests at all
-    const bool fast = !edge && r0 - 2 * K >= 1 && i_end <= rows;
+    // every row a level computes is interior and every row loaded (level-0 row
+    // i, g row i -+ 1) is in the grid: no row or column tests at all. Computed
+    // rows: r0-2K .. i_first+nstream-2 downwards, i_first-nstream+2 .. r1+2K-1
+    // upwards.
+    const bool fast = !edge && (up ? i_first - nstream + 1 >= 0 && r1 + 2 * K + 1 <= rows
+                                   : r0 - 2 * K >= 1 && i_first + nstream <= rows);
     const bool vec_ok = c + VEC <= cols;
     const bool store_vec = c >= olo && c + VEC <= ohi;
     V* ring = reinterpret_cast<V*>(gring) + (size_t)hw_wave * K * 64 + lane;  // slot s at ring[s * 64]
@@ -366,7 +382,7 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     double accs[MC ? K : 1];   // per-level deltas (MC)
 #pragma unroll
     for (int k = 0; k < (MC ? K : 1); ++k) accs[k] = 0.0;
-    int slot = 0;   // ring slot of g row (i - 1) at step i
+    int slot = 0;   // ring slot of g row (i -+ 1) at step i
 
     auto load = [&](auto fast_tag, const T* __restrict__ base, int64_t row, T (&v)[VEC], bool nt) {
         constexpr bool FAST = decltype(fast_tag)::value;
@@ -393,23 +409,34 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
         }
     };
 
-    // one stream step: level-0 row i arrives in slot P of every level's triple
-    auto step = [&](auto fast_tag, auto phase, int64_t i, const T (&inrow)[VEC],
+    // one stream step: level-0 row i arrives in slot P of every level's triple;
+    // level j computes row i - j (downwards) or i + j (upwards)
+    auto step = [&](auto fast_tag, auto dir_tag, auto phase, int64_t i, const T (&inrow)[VEC],
                     const T (&grow)[VEC]) {
         constexpr bool FAST = decltype(fast_tag)::value;
+        constexpr bool UP = decltype(dir_tag)::value;
         constexpr int P = decltype(phase)::value;
         constexpr int PN = (P + 1) % 3, PC = (P + 2) % 3;   // older rows: north, centre
 #pragma unroll
         for (int e = 0; e < VEC; ++e) W[0][P][e] = inrow[e];
+        // ring slot of the g row level jj reads at this step
+        auto gslot = [&](int jj) { int s2 = slot - (jj - 1); return s2 < 0 ? s2 + K : s2; };
+        V gb[GA > 0 ? GA : 1];   // g rows of the next GA levels, read ahead of their use
         if (GRING) {
             V x;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) x[e] = grow[e];
-            ring[slot * 64] = x;   // g row i-1
+            ring[slot * 64] = x;   // g row i -+ 1
+            if (GA > 0) {
+                gb[0] = x;
+#pragma unroll
+                for (int d = 1; d < GA; ++d)
+                    if (1 + d <= K) gb[d] = ring[gslot(1 + d) * 64];
+            }
         }
 #pragma unroll
         for (int j = 1; j <= K; ++j) {
-            const int64_t row = i - j;
+            const int64_t row = UP ? i + j : i - j;
             const T(&src)[3][VEC] = W[j - 1];
             const T wl = lane_shift<kDppWaveShr1>(src[PC][VEC - 1]);
             const T er = lane_shift<kDppWaveShl1>(src[PC][0]);
@@ -420,9 +447,13 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) gv[e] = sep_value<T>(sep, pr, qv[e]);
             } else if (HELM) {
-                int s2 = slot - (j - 1);
-                if (s2 < 0) s2 += K;
-                const V x = ring[s2 * 64];   // g row i - j
+                V x;   // g row i -+ j
+                if (GA > 0) {
+                    x = gb[(j - 1) % (GA > 0 ? GA : 1)];
+                    if (j + GA <= K) gb[(j - 1) % (GA > 0 ? GA : 1)] = ring[gslot(j + GA) * 64];
+                } else {
+                    x = ring[gslot(j) * 64];
+                }
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) gv[e] = x[e];
             } else {
@@ -493,21 +524,35 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     // computed. (Keeping the next group's loads in flight in a second register
     // buffer cost 24 VGPRs, and with them the third wavefront per SIMD at depth
     // 10: 8192^2 FP64 Helmholtz 1190 -> 1320 GLUP/s without it.)
-    auto stream = [&](auto fast_tag) {
-        for (int64_t i0 = i_beg; i0 < i_end; i0 += 3) {
+    auto stream = [&](auto fast_tag, auto dir_tag) {
+        constexpr int D = decltype(dir_tag)::value ? -1 : 1;   // row step of the stream
+        for (int64_t n = 0; n < nstream; n += 3) {
+            const int64_t i0 = i_first + D * n;
             T in[3][VEC], gin[3][VEC];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                load(fast_tag, a, i0 + q, in[q], false);
-                if (GRING) load(fast_tag, g, i0 + q - 1, gin[q], NTG);
+                load(fast_tag, a, i0 + D * q, in[q], false);
+                if (GRING) load(fast_tag, g, i0 + D * (q - 1), gin[q], NTG);
             }
-            step(fast_tag, std::integral_constant<int, 0>{}, i0, in[0], gin[0]);
-            step(fast_tag, std::integral_constant<int, 1>{}, i0 + 1, in[1], gin[1]);
-            step(fast_tag, std::integral_constant<int, 2>{}, i0 + 2, in[2], gin[2]);
+            step(fast_tag, dir_tag, std::integral_constant<int, 0>{}, i0, in[0], gin[0]);
+            step(fast_tag, dir_tag, std::integral_constant<int, 1>{}, i0 + D, in[1], gin[1]);
+            step(fast_tag, dir_tag, std::integral_constant<int, 2>{}, i0 + 2 * D, in[2], gin[2]);
         }
     };
-    if (fast) stream(std::true_type{});
-    else stream(std::false_type{});
+    if (r0 < r1) {
+        if constexpr (VERT) {
+            if (up) {
+                if (fast) stream(std::true_type{}, std::true_type{});
+                else stream(std::false_type{}, std::true_type{});
+            } else {
+                if (fast) stream(std::true_type{}, std::false_type{});
+                else stream(std::false_type{}, std::false_type{});
+            }
+        } else {
+            if (fast) stream(std::true_type{}, std::false_type{});
+            else stream(std::false_type{}, std::false_type{});
+        }
+    }
 
     auto reduce_out = [&](double v, int slot_index) {
         if (WT) {

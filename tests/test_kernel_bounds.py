@@ -259,43 +259,66 @@ def test_model_flags_the_unguarded_west_halo():
 # lets in-grid rows be read.
 # ---------------------------------------------------------------------------
 
-def _tb_geometry(rows, cols, vec, nw, k, tile_rows):
+def _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert=False):
     ow = (64 * vec - 2 * k) // vec * vec
     need = cols - 1 - k
     nwin = -(-need // ow) if need > 0 else 1
-    strips = -(-nwin // nw)
     bands = -(-(rows - 2) // tile_rows)
-    return ow, strips, bands
+    if vert:                              # a workgroup: nw consecutive bands of one window
+        return ow, nwin, -(-bands // nw)
+    return ow, -(-nwin // nw), bands
 
 
-def _tb_model(u, k, vec, nw, tile_rows):
+def _tb_waves(rows, cols, vec, nw, k, tile_rows, vert):
+    """(t, w, cw, r0, r1, up) of every wavefront of a launch, as the kernel derives them."""
+    ow, strips, groups = _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert)
+    for t in range(strips * groups):
+        tband, strip = divmod(t, strips)
+        for w in range(nw):
+            band = tband * nw + w if vert else tband
+            cw = (strip if vert else strip * nw + w) * ow
+            r0 = 1 + band * tile_rows
+            r1 = min(r0 + tile_rows, rows - 1)
+            yield t, w, cw, r0, r1, vert and w % 2 == 1
+
+
+def _tb_stream(rows, cols, vec, k, cw, r0, r1, up):
+    """Level-0 rows in stream order, the g row loaded with each, and the fast flag."""
+    width = 64 * vec
+    nstream = (r1 - r0 + 2 * k + 2) // 3 * 3
+    d = -1 if up else 1
+    first = r1 + k - 1 if up else r0 - k
+    edge = cw == 0 or cw + width > cols - 1
+    if up:
+        fast = not edge and first - nstream + 1 >= 0 and r1 + 2 * k + 1 <= rows
+    else:
+        fast = not edge and r0 - 2 * k >= 1 and first + nstream <= rows
+    return [(first + d * n, first + d * n - d) for n in range(nstream)], fast
+
+
+def _tb_model(u, k, vec, nw, tile_rows, vert=False):
     rows, cols = u.shape
-    ow, strips, bands = _tb_geometry(rows, cols, vec, nw, k, tile_rows)
+    ow = _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert)[0]
     out = u.copy()                       # the partner buffer starts as a copy
     written = np.zeros(u.shape, dtype=np.int64)
     width = 64 * vec
     loads_ok = True
-    for t in range(strips * bands):
-        band, strip = divmod(t, strips)
-        r0 = 1 + band * tile_rows
-        r1 = min(r0 + tile_rows, rows - 1)
-        for w in range(nw):
-            cw = (strip * nw + w) * ow
+    for t, w, cw, r0, r1, up in _tb_waves(rows, cols, vec, nw, k, tile_rows, vert):
+        if r0 >= r1:
+            continue                     # a wavefront past the last band (vert)
+        if True:   # (one wavefront)
             cidx = cw + np.arange(width)
             inside = cidx < cols
             olo = 1 if cw == 0 else cw + k
             ohi = min(cw + k + ow, cols - 1)
             if vec > 1 and cw % vec:
                 loads_ok = False         # windows must start 16-byte aligned
-            # rows stream in groups of three (level-0 row i and g row i - 1 at
+            # rows stream in groups of three (level-0 row i and g row i -+ 1 at
             # step i); the kernel's load guard, as written: the fast path reads
             # unguarded, the other path only rows in [0, rows)
-            i_beg = r0 - k
-            i_end = i_beg + (r1 + k - i_beg + 2) // 3 * 3
-            edge = cw == 0 or cw + width > cols - 1
-            fast = not edge and r0 - 2 * k >= 1 and i_end <= rows
-            for i in range(i_beg, i_end):
-                for row in (i, i - 1):
+            stream, fast = _tb_stream(rows, cols, vec, k, cw, r0, r1, up)
+            for pair in stream:
+                for row in pair:
                     read = fast or 0 <= row < rows
                     if read and not 0 <= row < rows:
                         loads_ok = False
@@ -312,7 +335,7 @@ def _tb_model(u, k, vec, nw, tile_rows):
                 prev = level
                 level = {}
                 for i in range(r0 - k, r1 + k):
-                    r = i - j
+                    r = i + j if up else i - j     # level j's row at step i
                     zero = np.zeros(width)
                     n, c, s = prev.get(r - 1, zero), prev.get(r, zero), prev.get(r + 1, zero)
                     wv = np.concatenate([[0.0], c[:-1]])
@@ -331,11 +354,12 @@ def _tb_model(u, k, vec, nw, tile_rows):
                                        (70, 250)])
 @pytest.mark.parametrize("vec", [2, 4])
 @pytest.mark.parametrize("k", [2, 4, 5, 8, 10])
-@pytest.mark.parametrize("nw,tile_rows", [(1, 5), (2, 16), (4, 64)])
-def test_tb_schedule_covers_interior_and_matches_k_sweeps(rows, cols, vec, k, nw, tile_rows):
+@pytest.mark.parametrize("nw,tile_rows,vert", [(1, 5, False), (2, 16, False), (4, 64, False),
+                                                (2, 5, True), (2, 16, True), (4, 7, True)])
+def test_tb_schedule_covers_interior_and_matches_k_sweeps(rows, cols, vec, k, nw, tile_rows, vert):
     rng = np.random.default_rng(rows * 1000 + cols)
     u = rng.standard_normal((rows, cols))
-    out, written, loads_ok = _tb_model(u, k, vec, nw, tile_rows)
+    out, written, loads_ok = _tb_model(u, k, vec, nw, tile_rows, vert)
     assert loads_ok
     want_written = np.zeros_like(written)
     want_written[1:-1, 1:-1] = 1
@@ -362,6 +386,37 @@ def test_tb_stores_stay_in_interior_at_full_size(rows, cols, vec, k):
     live = olo < ohi
     # consecutive output ranges abut: no column is skipped or written twice
     assert (olo[live][1:] == ohi[live][:-1]).all() and ohi[live][-1] == cols - 1
+
+
+@pytest.mark.parametrize("rows,cols", [(8192, 8192), (4096, 4096), (8191, 8190), (2049, 2049),
+                                       (131, 8192), (4097, 257)])
+@pytest.mark.parametrize("vec,k", [(2, 10), (2, 5), (4, 5), (4, 2), (2, 8)])
+@pytest.mark.parametrize("nw,tile_rows", [(2, 40), (4, 40), (2, 32), (2, 7)])
+def test_tb_vertical_groups_cover_rows_and_guard_loads_at_full_size(rows, cols, vec, k, nw,
+                                                                   tile_rows):
+    """Vertical band groups at the benchmark sizes: every interior row is stored by
+    exactly one wavefront of each window, and a fast (unguarded) stream loads only
+    rows in [0, rows) and computes only interior rows."""
+    ow, strips, groups = _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert=True)
+    cover = {}
+    for t, w, cw, r0, r1, up in _tb_waves(rows, cols, vec, nw, k, tile_rows, True):
+        if t % strips not in (0, 1, strips - 1):
+            continue                     # windows are alike apart from the edge ones
+        if r0 >= r1:
+            continue
+        cover.setdefault(cw, []).append((r0, r1))
+        stream, fast = _tb_stream(rows, cols, vec, k, cw, r0, r1, up)
+        lo = min(min(p) for p in stream)
+        hi = max(max(p) for p in stream)
+        if fast:
+            assert 0 <= lo and hi < rows
+            done_lo = lo + 1 if up else r0 - 2 * k      # rows the levels compute
+            done_hi = r1 + 2 * k - 1 if up else hi - 1
+            assert 1 <= done_lo and done_hi <= rows - 2
+    for cw, spans in cover.items():
+        spans.sort()
+        assert spans[0][0] == 1 and spans[-1][1] == rows - 1
+        assert all(a[1] == b[0] for a, b in zip(spans, spans[1:]))
 
 
 # ---------------------------------------------------------------------------
