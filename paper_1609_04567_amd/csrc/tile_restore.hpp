@@ -68,7 +68,13 @@ __device__ T restore_argmin(const T (&v)[8], unsigned valid, T beta, bool quadra
         }
         if (gs == T(0)) return t;
         if (gs < T(0)) lo = t; else hi = t;
-        T tn = t - gs / dg;
+        const T dt = gs / dg;
+        T tn = t - dt;
+        // a Newton step below the tolerance: t is the root to working accuracy
+        // (its step may round back onto t, a bracket end, which must not turn into
+        // a bisection that walks back to the same root)
+        if (fabs(dt) <= (sizeof(T) == 8 ? T(4e-16) : T(2e-7)) * (fabs(t) > T(1) ? fabs(t) : T(1)))
+            return (tn > lo && tn < hi) ? tn : t;
         if (!(tn > lo && tn < hi)) tn = lo + T(0.5) * (hi - lo);
         const T step = tn - t;
         t = tn;
