@@ -40,6 +40,7 @@ constexpr int kWindowsInFlight = 2;
 lsr_status lsr_ctx::engine_setup() {
     HIP_TRY(hipStreamCreateWithFlags(&small_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&copy_out_stream, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&d_jobs, sizeof(lsr::BatchJob) * kMaxBatch));
     HIP_TRY(hipMalloc(&d_work, sizeof(lsr::WorkItem) * (kMaxWork + kPad)));
     for (int i = 0; i < 2; ++i) {
@@ -59,10 +60,12 @@ void lsr_ctx::engine_teardown() {
         (void)hipStreamDestroy(small_stream);
         small_stream = nullptr;
     }
-    if (copy_stream) {
-        (void)hipStreamSynchronize(copy_stream);
-        (void)hipStreamDestroy(copy_stream);
-        copy_stream = nullptr;
+    for (hipStream_t* cs : {&copy_stream, &copy_out_stream}) {
+        if (*cs) {
+            (void)hipStreamSynchronize(*cs);
+            (void)hipStreamDestroy(*cs);
+            *cs = nullptr;
+        }
     }
     for (int i = 0; i < 2; ++i) {
         if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
@@ -443,7 +446,7 @@ void lsr_ctx::engine_scan() {
         const size_t esz = dtype_size(g.dtype);
         // a stop inside a fused round is replayed first; then the buffer holding
         // sweep n goes back to the caller's grid (a host job's by a D2H copy on
-        // the copy stream, after the execution stream's work so far)
+        // the copy-out stream, after the execution stream's work so far)
         int last = 0;
         hipError_t e = finish_fused(j, fin, j->desc.step, j->desc.ctl, &last, stream) == LSR_OK
                            ? hipSuccess : hipErrorLaunchFailure;
@@ -451,14 +454,14 @@ void lsr_ctx::engine_scan() {
             hipEvent_t done_ev = get_event();
             if (!done_ev) e = hipErrorOutOfMemory;
             if (e == hipSuccess) e = hipEventRecord(done_ev, stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(copy_stream, done_ev, 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(copy_out_stream, done_ev, 0);
             if (done_ev) put_event(done_ev);
             void* dst = j->two_phase ? j->out_host : ug.data;
             const size_t dpitch = (size_t)(j->two_phase ? j->host_pitch : ug.pitch) * esz;
             if (e == hipSuccess)
                 e = hipMemcpy2DAsync(dst, dpitch, j->buf[last], g.pitch * esz, g.cols * esz,
-                                     g.rows, hipMemcpyDeviceToHost, copy_stream);
-            if (e == hipSuccess) e = hipEventRecord(j->ev_end, copy_stream);
+                                     g.rows, hipMemcpyDeviceToHost, copy_out_stream);
+            if (e == hipSuccess) e = hipEventRecord(j->ev_end, copy_out_stream);
         } else {
             if (e == hipSuccess && j->staged)
                 e = hipMemcpy2DAsync(ug.data, ug.pitch * esz, j->buf[last], g.pitch * esz,
@@ -588,6 +591,7 @@ void lsr_ctx::serve() {
             fatal = g_last_error;
             (void)hipStreamSynchronize(stream);
             (void)hipStreamSynchronize(copy_stream);
+            (void)hipStreamSynchronize(copy_out_stream);
             std::vector<Job*> all(active.begin(), active.end());
             all.insert(all.end(), retiring.begin(), retiring.end());
             all.insert(all.end(), ingesting.begin(), ingesting.end());

@@ -290,7 +290,9 @@ struct lsr_ctx {
     hipStream_t user_stream = nullptr;
     hipStream_t stream = nullptr;    // internal execution stream
     hipStream_t small_stream = nullptr;  // batched engine: whole-grid-in-LDS jobs
-    hipStream_t copy_stream = nullptr;   // batched engine: H2D/D2H copies of host jobs
+    hipStream_t copy_stream = nullptr;       // batched engine: H2D copies of host jobs
+    hipStream_t copy_out_stream = nullptr;   // batched engine: D2H copies at retirement (the two
+                                             // directions of the link run at the same time)
     hipStream_t capture = nullptr;   // stream used only for graph capture
     lsr_rt::Pool pool;
     lsr_tuning tuning{};
