@@ -2,10 +2,12 @@
 //
 // Phase 1, adaptive-median detection (integer, one shot). A 16x16 workgroup
 // stages its pixels plus a halo of w_max/2 in LDS. Each thread grows its window
-// w = 3, 5, ..., w_max over the in-range pixels only; for each window it finds
-// min and max in one pass and the lower median (rank (count-1)/2) by a radix
-// select: the largest v with #{x < v} <= rank, decided two bits at a time from
-// the top (four passes over the window). The first window with min < med < max decides the flag
+// w = 3, 5, ..., w_max over the in-range pixels only. A full 3x3 or 5x5 window
+// goes through a comparator network (select_networks.hpp) that leaves its min,
+// lower median (rank (count-1)/2) and max in known registers; any other window
+// finds min and max in one pass and the lower median by a radix select: the
+// largest v with #{x < v} <= rank, decided two bits at a time from the top (four
+// passes over the window). The first window with min < med < max decides the flag
 // !(min < y < max); otherwise the w_max window decides (y == min || y == max).
 // Output: mask (0/1) and the initial iterate (med where flagged, y elsewhere).
 //
@@ -17,6 +19,7 @@
 // (a step that leaves the bracket is replaced by its midpoint). Unflagged pixels
 // are never written: both ping-pong buffers hold them from the start.
 #include "kernels.hpp"
+#include "select_networks.hpp"
 #include "tile_restore.hpp"
 
 namespace lsr {
@@ -45,7 +48,43 @@ __global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
     const int yv = tile[ci * TW + cj];
     int lo = 0, hi = 0, med = 0, flag = 0;
     bool decided = false;
-    for (int w = 3; w <= w_max && !decided; w += 2) {
+    // full 3x3 and 5x5 windows (most pixels decide in one of them): minimum,
+    // lower median and maximum by comparator networks on registers; windows
+    // clipped by the border and larger ones by the radix select below
+    int w0 = 3;
+    if (i >= 1 && i + 1 < rows && jx >= 1 && jx + 1 < cols) {
+        int v[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) v[a * 3 + b] = tile[(ci - 1 + a) * TW + cj - 1 + b];
+        select9(v);
+        lo = v[kSel9Min];
+        med = v[kSel9Med];
+        hi = v[kSel9Max];
+        if (lo < med && med < hi) {
+            flag = !(lo < yv && yv < hi);
+            decided = true;
+        }
+        w0 = 5;
+        if (!decided && w_max >= 5 && i >= 2 && i + 2 < rows && jx >= 2 && jx + 2 < cols) {
+            int u[25];
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = 0; b < 5; ++b) u[a * 5 + b] = tile[(ci - 2 + a) * TW + cj - 2 + b];
+            select25(u);
+            lo = u[kSel25Min];
+            med = u[kSel25Med];
+            hi = u[kSel25Max];
+            if (lo < med && med < hi) {
+                flag = !(lo < yv && yv < hi);
+                decided = true;
+            }
+            w0 = 7;
+        }
+    }
+    for (int w = w0; w <= w_max && !decided; w += 2) {
         const int k = w / 2;
         // in-range part of the w x w box, in tile coordinates
         const int ia = ci - (int)min<int64_t>(k, i), ib = ci + (int)min<int64_t>(k, rows - 1 - i);
