@@ -141,7 +141,7 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     j->nparts_alloc = nparts;
     // device time of a round per cell, in bytes at 5 TB/s (restoration: its
     // measured ALU time per pixel)
-    const double per_cell = life || sobel ? 2.0 : restore ? (f32 ? 150.0 : 480.0)
+    const double per_cell = life || sobel ? 2.0 : restore ? (f32 ? 28.0 : 58.0)
                                                           : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
     if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");

@@ -148,8 +148,14 @@ constexpr int64_t kMaxChunkBase = 65536;
 // of a captured one) starts from buffer 0, and every chunk has its check sweeps
 // at the same offsets. A check period of at least max_iter leaves only the check
 // at the cap, which falls at one fixed offset of the last chunk: the base is then
-// 2 * tb. Computed in 64 bits; 0 when the base exceeds kMaxChunkBase.
-int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int override_chunk, int tb) {
+// 2 * tb. Computed in 64 bits; 0 when the base exceeds kMaxChunkBase. The
+// restoration sweep is bound by its per-pixel solve rather than by HBM: its
+// estimate is the measured time per pixel (4096^2 at 40 % impulses: 196 us per
+// FP64 sweep, 94 us FP32), which keeps its chunks short; such jobs usually stop
+// after a few sweeps, and every launch enqueued past the stop still costs its
+// early exit.
+int pick_chunk(const lsr_grid* g, int stencil_id, int check_every, int64_t max_iter,
+               int override_chunk, int tb) {
     const int64_t base = (int64_t)check_every >= max_iter ? 2 * (int64_t)tb
                                                            : std::lcm((int64_t)check_every, 2 * (int64_t)tb);
     if (base > kMaxChunkBase) return 0;
@@ -157,8 +163,11 @@ int pick_chunk(const lsr_grid* g, int check_every, int64_t max_iter, int overrid
     if (override_chunk > 0) {
         chunk = ((int64_t)override_chunk + base - 1) / base * base;
     } else {
-        const double bytes = (double)g->rows * (double)g->cols * (double)dtype_size(g->dtype) * 3.0;
-        const double est_us = std::max(4.0, bytes / 5.0e6);
+        const double cells = (double)g->rows * (double)g->cols;
+        const double bytes = cells * (double)dtype_size(g->dtype) * 3.0;
+        double est_us = std::max(4.0, bytes / 5.0e6);
+        if (stencil_id == LSR_ST_RESTORE)
+            est_us = std::max(est_us, cells * (g->dtype == LSR_F32 ? 5.6e-6 : 1.17e-5));
         const int64_t m = (int64_t)std::max(1.0, std::floor(kChunkTargetUs / (est_us * (double)base)));
         chunk = base * m;
         if (chunk > kMaxChunk) chunk = std::max(base, kMaxChunk / base * base);
@@ -701,7 +710,7 @@ lsr_status lsr_rt::plan_plain(Job* j, int reduce_op, const lsr_tuning& tun, int*
                 j->geom = lsr::restore_geom(a, tun.tile_rows);
             }
         }
-        return pick_chunk(&g, check_every, j->max_iter, tun.chunk, j->geom.tb);
+        return pick_chunk(&g, stencil_id, check_every, j->max_iter, tun.chunk, j->geom.tb);
     };
     int chunk = plan(tun.tb_depth);
     // a check period whose lcm with two fused launches is too long to capture:
