@@ -696,13 +696,40 @@ def run_served(args, L, I, torch):
     out = None
     sat = args.rate or None
 
+    # --autotune: the batched engine's settings for every key of the stream (kind,
+    # size class = bit length of the side, check period), measured on a batched
+    # context before the legs and loaded into each batched context they use
+    tune_json, tune_info = None, None
+    if args.autotune:
+        t0 = time.perf_counter()
+        kinds = [(L.LSR_ST_LAPLACE5, L.LSR_F32, 1), (L.LSR_ST_HELMHOLTZ5, L.LSR_F32, 10),
+                 (L.LSR_ST_LIFE, L.LSR_U8, 1)]
+        classes = sorted({s.side.bit_length() for s in specs})
+        chosen = {}
+        with L.Context(0, batched=True) as tctx:
+            for b in classes:
+                side = min(max(s.side for s in specs), int(round(2 ** (b - 0.5))))
+                for st, dt, every in kinds:
+                    best = tctx.autotune(st, dt, side, side, every)
+                    chosen[f"{st}/{b}"] = (best.tb_depth, best.tile_rows)
+            tune_json = L.lsr_tune_export(tctx.handle)
+        tune_info = {"keys": len(chosen), "seconds": round(time.perf_counter() - t0, 1),
+                     "depth_tile_rows": chosen}
+        print(f"autotune: {tune_info}", file=sys.stderr, flush=True)
+
+    def batched_ctx():
+        c = L.Context(0, batched=True)
+        if tune_json:
+            L.lsr_tune_import(c.handle, tune_json)
+        return c
+
     def lup_of(k, n):
         s = specs[k]
         return (s.side - (0 if s.kind == I.KIND_LIFE else 2)) ** 2 * n
 
     # -- closed loop, batched FP32 --------------------------------------------
     if "closed" in legs:
-        bctx = L.Context(0, batched=True)
+        bctx = batched_ctx()
         done_lup = [0]
 
         def check(k, v, job, r):
@@ -749,7 +776,7 @@ def run_served(args, L, I, torch):
             rate = lam * sat
             arr = I.poisson_arrivals(specs, rate)
             lat = []
-            bctx = L.Context(0, batched=True)
+            bctx = batched_ctx()
 
             def check(k, v, job, r, lat=lat):
                 lat.append(r.latency_ms)
@@ -767,7 +794,7 @@ def run_served(args, L, I, torch):
     # -- verification: FP32 against FP64, every Laplace and Helmholtz job -----------
     if "verify" in legs:
         vspecs = [(k, s) for k, s in enumerate(specs) if s.kind != I.KIND_LIFE]
-        bctx = L.Context(0, batched=True)
+        bctx = batched_ctx()
         pend = {}
         lock = threading.Lock()
 
@@ -901,6 +928,8 @@ def run_served(args, L, I, torch):
             "life_plain_equal": sum(bool(e.get("plain_equal")) for e in res),
             "by_kind": {kd: sum(e["kind"] == kd for e in res) for kd in
                         (I.KIND_LAPLACE, I.KIND_HELMHOLTZ, I.KIND_LIFE)}}
+    if tune_info:
+        out["autotune"] = tune_info
     if args.records:
         with open(args.records, "w") as fh:
             json.dump({str(k): v for k, v in recs.items()}, fh)

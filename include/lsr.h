@@ -222,11 +222,14 @@ lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
  * the fastest in the context's table under the key (stencil_id, dtype, bit lengths of rows
  * and cols, check_every). Later lsr_run calls whose overrides leave the launch shape
  * automatic (tile_rows, tb_depth, waves and unroll all 0) take the table's entry for their
- * key, so a job's settings depend only on its key (a batched context takes the entry's fused
- * depth and band rows; give it a measured table with lsr_tune_import). The winner is copied
- * to best_out when it is not NULL. Blocks until done (a few hundred short jobs; about a
- * second at 8192^2). Runs on plain contexts only (EINVAL on a batched one, or for RESTORE);
- * ENOMEM/EDEVICE as lsr_run.
+ * key, so a job's settings depend only on its key. On a batched context the candidates are
+ * the engine's own settings (the fused depths its Jacobi families hold and the band rows of a
+ * wavefront tile; band rows for Life) and each candidate job runs alone in the engine's rounds;
+ * the table then serves that context's later jobs (and others through lsr_tune_export /
+ * lsr_tune_import). The winner is copied to best_out when it is not NULL. Blocks until done
+ * (a few hundred short jobs on a plain context, a few dozen on a batched one; about a second
+ * at 8192^2); no other job of the context may run meanwhile. EINVAL for stencils other than
+ * Laplace, Helmholtz and Life; ENOMEM/EDEVICE as lsr_run.
  * The caller owns nothing new; scratch returns to the context's pool.
  */
 lsr_status lsr_autotune(lsr_ctx *ctx, int32_t stencil_id, int32_t dtype, int64_t rows,

@@ -4,6 +4,8 @@
 // the launch shape automatic, so a job's settings are a pure function of its key
 // (and of the table), the same whatever else runs. The table round-trips as JSON
 // text tagged with the device's architecture name.
+#include <chrono>
+
 #include "runtime_internal.hpp"
 
 using namespace lsr_rt;
@@ -52,6 +54,31 @@ std::vector<lsr_tuning> candidates(int stencil) {
     return out;
 }
 
+// Candidates on a batched context: the engine's families take the fused depth
+// (Jacobi: FP32 5 or 2, FP64 10, 5 or 2, kept only where it divides the check
+// period; otherwise depth 5 with checks inside) and the band rows of a wavefront
+// tile (Life: band rows of the one-generation SWAR tile).
+std::vector<lsr_tuning> candidates_batched(int stencil, int dtype, int check_every) {
+    std::vector<lsr_tuning> out;
+    auto add = [&](int tile_rows, int depth) {
+        lsr_tuning t{};
+        t.tile_rows = tile_rows;
+        t.tb_depth = depth;
+        out.push_back(t);
+    };
+    if (stencil == LSR_ST_LIFE) {
+        for (int tr : {8, 16, 32, 64, 128}) add(tr, 0);
+        return out;
+    }
+    std::vector<int> depths;
+    for (int k : dtype == LSR_F32 ? std::initializer_list<int>{5, 2} : std::initializer_list<int>{10, 5, 2})
+        if (check_every % k == 0) depths.push_back(k);
+    if (depths.empty()) depths.push_back(5);
+    for (int k : depths)
+        for (int tr : {8, 16, 24, 32, 48, 64}) add(tr, k);
+    return out;
+}
+
 const char* arch_name(int device) {
     static thread_local char name[64];
     hipDeviceProp_t p;
@@ -89,8 +116,8 @@ extern "C" {
 lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t rows, int64_t cols,
                         int32_t check_every, int64_t max_iter, lsr_tuning* best_out) {
     if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
-    if (ctx->batched) return fail(LSR_EINVAL, "the autotuner measures the plain path (non-batched context)");
-    if (stencil_id == LSR_ST_RESTORE) return fail(LSR_EINVAL, "restoration has no launch shapes to tune");
+    if (stencil_id != LSR_ST_LAPLACE5 && stencil_id != LSR_ST_HELMHOLTZ5 && stencil_id != LSR_ST_LIFE)
+        return fail(LSR_EINVAL, "the autotuner covers the Laplace, Helmholtz and Life sweeps");
     if (rows < 1 || cols < 1 || rows > (1 << 20) || cols > (1 << 20))
         return fail(LSR_EINVAL, "rows and cols must be in [1, 2^20]");
     const size_t esz = dtype_size(dtype);
@@ -125,21 +152,41 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
     if (v != LSR_OK) return v;
 
     HIP_TRY(hipSetDevice(ctx->device));
-    void* grid_buf = nullptr;
+    // a batched context is measured under load: enough jobs of the key to hold
+    // about 2^25 cells run together (8 to 256 jobs, each on its own grid, sharing
+    // the read-only g), as the jobs of a stream fill the rounds, and a candidate is
+    // ranked by the wall time of the whole batch (a job alone, or a few, favour
+    // the most and smallest tiles, which a full round does not need: measured on
+    // the mixed stream, tuning with 1 or 8 jobs lost 15-27 % of its jobs/s)
+    const int copies = ctx->batched
+        ? (int)std::min(256.0, std::max(8.0, std::ceil(33554432.0 / std::max(cells, 1.0))))
+        : 1;
+    std::vector<void*> grid_bufs(copies, nullptr);
     void* env_buf = nullptr;
-    lsr_status st = ctx->pool.alloc(bytes, &grid_buf);
+    auto release_all = [&]() {
+        for (void*& b : grid_bufs) {
+            ctx->pool.release(b);
+            b = nullptr;
+        }
+        ctx->pool.release(env_buf);
+        env_buf = nullptr;
+    };
+    lsr_status st = LSR_OK;
+    for (int c = 0; c < copies && st == LSR_OK; ++c) st = ctx->pool.alloc(bytes, &grid_bufs[c]);
     if (st == LSR_OK && helm) st = ctx->pool.alloc(bytes, &env_buf);
     if (st != LSR_OK) {
-        ctx->pool.release(grid_buf);
+        release_all();
         return st;
     }
-    g.data = grid_buf;
+    g.data = grid_bufs[0];
     g.env0 = env_buf;
-    hipError_t e = hipMemsetAsync(grid_buf, 0, bytes, ctx->user_stream);
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < copies && e == hipSuccess; ++c)
+        e = hipMemsetAsync(grid_bufs[c], 0, bytes, ctx->user_stream);
     if (e == hipSuccess && env_buf) e = hipMemsetAsync(env_buf, 0, bytes, ctx->user_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->user_stream);
     if (e != hipSuccess) {
-        ctx->pool.release(grid_buf);
-        ctx->pool.release(env_buf);
+        release_all();
         return fail(LSR_EDEVICE, "autotune scratch: %s", hipGetErrorString(e));
     }
 
@@ -158,7 +205,9 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
         g.bc = bcs[b];
         lsr_tuning best{};
         double best_ms = 1e300;
-        for (const lsr_tuning& cand : candidates(stencil_id)) {
+        const std::vector<lsr_tuning> cands = ctx->batched ? candidates_batched(stencil_id, dtype, check_every)
+                                                           : candidates(stencil_id);
+        for (const lsr_tuning& cand : cands) {
             lsr_tuning t = base;
             t.tile_rows = cand.tile_rows;
             t.tb_depth = cand.tb_depth;
@@ -166,14 +215,44 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
             t.unroll = cand.unroll;
             double ms = 1e300;
             for (int rep = 0; rep < 2 && st == LSR_OK; ++rep) {   // the first run also warms up
-                std::unique_ptr<Job> j(new Job());
-                j->grid = g;
-                j->xgrid = g;
-                j->stencil = stencil_id;
-                j->cond = cond;
-                j->max_iter = sweeps;
                 lsr_job id = 0;
-                st = submit_plain(ctx, std::move(j), &g, stencil_id, reduce, &cond, sweeps, t, &id);
+                if (ctx->batched) {
+                    // the engine reads the context's overrides at submission: the
+                    // candidate's jobs run in its rounds with this setting
+                    const auto t0 = std::chrono::steady_clock::now();
+                    std::vector<lsr_job> ids;
+                    {
+                        std::lock_guard<std::mutex> lk(ctx->mu);
+                        ctx->tuning = t;
+                    }
+                    for (int c = 0; c < copies && st == LSR_OK; ++c) {
+                        lsr_grid gc = g;
+                        gc.data = grid_bufs[c];
+                        st = submit(ctx, &gc, stencil_id, reduce, &cond, sweeps, false, &id);
+                        if (st == LSR_OK) ids.push_back(id);
+                    }
+                    {
+                        std::lock_guard<std::mutex> lk(ctx->mu);
+                        ctx->tuning = base;
+                    }
+                    for (lsr_job jid : ids) {   // every submitted job is collected
+                        lsr_job_result r{};
+                        const lsr_status s2 = lsr_result(ctx, jid, 1, &r);
+                        if (st == LSR_OK) st = s2;
+                    }
+                    if (st != LSR_OK) break;
+                    ms = std::min(ms, std::chrono::duration<double, std::milli>(
+                                          std::chrono::steady_clock::now() - t0).count());
+                    continue;
+                } else {
+                    std::unique_ptr<Job> j(new Job());
+                    j->grid = g;
+                    j->xgrid = g;
+                    j->stencil = stencil_id;
+                    j->cond = cond;
+                    j->max_iter = sweeps;
+                    st = submit_plain(ctx, std::move(j), &g, stencil_id, reduce, &cond, sweeps, t, &id);
+                }
                 if (st != LSR_OK) break;
                 lsr_job_result r{};
                 st = lsr_result(ctx, id, 1, &r);
@@ -193,8 +272,7 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
         if (b == 0) best_first = best;
     }
     (void)hipStreamSynchronize(ctx->user_stream);
-    ctx->pool.release(grid_buf);
-    ctx->pool.release(env_buf);
+    release_all();
     if (st != LSR_OK) return st;
     if (best_out) *best_out = best_first;
     return LSR_OK;

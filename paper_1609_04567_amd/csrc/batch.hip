@@ -328,9 +328,9 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_
     if (is_life) {
         // rows are 16-byte aligned with zeroed padding to a multiple of 16 cells
         j.kind = BK_LIFE_SWAR;
-        j.tile_rows = kLifeTileRows;
+        j.tile_rows = want_tile_rows > 0 ? want_tile_rows : kLifeTileRows;
         j.strips = (int)((j.cols + 1023) / 1024);
-        j.tiles = j.strips * (int)((j.rows + kLifeTileRows - 1) / kLifeTileRows);
+        j.tiles = j.strips * (int)((j.rows + j.tile_rows - 1) / j.tile_rows);
         return;
     }
     // rows are 16-byte aligned (the engine stages any other grid)

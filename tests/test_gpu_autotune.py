@@ -92,13 +92,51 @@ def test_table_round_trips_and_rejects_other_arch(tctx):
         other.close()
 
 
-def test_batched_context_is_rejected():
+def test_batched_context_tunes_its_own_families():
+    """On a batched context the autotuner measures the engine's settings (fused
+    depth where it divides the check period, band rows; Life band rows), later
+    jobs of the key run with the winner, and their fields equal the default
+    geometry's bit for bit (Life: and the oracle's)."""
+    import torch
+    say("batched autotune")
+    h = I.helmholtz_input(300)
+    life = I.life_input(200, seed=6)
     c = L.Context(0, batched=True)
     try:
-        with pytest.raises(L.LsrError):
-            c.autotune(L.LSR_ST_LAPLACE5, L.LSR_F64, 64, 64, 1)
+        with pytest.raises(L.LsrError) as ei:
+            c.autotune(L.LSR_ST_RESTORE, L.LSR_F32, 64, 64, 1)
+        assert ei.value.status == L.LSR_EINVAL
+        best = c.autotune(L.LSR_ST_HELMHOLTZ5, L.LSR_F32, 300, 300, 10, 160)
+        assert best.tb_depth in (5, 2) and best.tile_rows in (8, 16, 24, 32, 48, 64)
+        assert best.waves == 0 and best.unroll == 0
+        lb = c.autotune(L.LSR_ST_LIFE, L.LSR_U8, 200, 200, 1, 240)
+        assert lb.tb_depth == 0 and lb.tile_rows in (8, 16, 32, 64, 128)
+        entries = json.loads(L.lsr_tune_export(c.handle))["entries"]
+        assert len(entries) == 3   # Helmholtz, Life torus, Life dead border
+        t = torch.from_numpy(h.u0.astype(np.float32)).to("cuda:0")
+        g = torch.from_numpy(h.g.astype(np.float32)).to("cuda:0")
+        r = c.run(t, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                  L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 160, L.LSR_BC_RING, env0=g,
+                  param=(h.alpha, h.h))
+        assert r.sweeps_per_launch == best.tb_depth
+        s = torch.from_numpy(life).to("cuda:0")
+        rl = c.run(s, L.LSR_ST_LIFE, L.LSR_RED_SUM, L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, 10),
+                   300, L.LSR_BC_TORUS)
+        torch.cuda.synchronize()
+        xt, xs = t.cpu().numpy(), s.cpu().numpy()
     finally:
         c.close()
+    with L.Context(0, batched=True) as d:
+        t2 = torch.from_numpy(h.u0.astype(np.float32)).to("cuda:0")
+        g2 = torch.from_numpy(h.g.astype(np.float32)).to("cuda:0")
+        r2 = d.run(t2, L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA,
+                   L.make_cond(L.LSR_COND_BELOW, 1e-9, 10), 160, L.LSR_BC_RING, env0=g2,
+                   param=(h.alpha, h.h))
+        torch.cuda.synchronize()
+        assert r2.iterations == r.iterations == 160
+        assert np.array_equal(t2.cpu().numpy(), xt)
+    o, ro = O.life_run(life, bc=O.BC_TORUS, cond=O.COND_STABLE_FOR, stable_window=10, max_iter=300)
+    assert rl.iterations == ro.n and np.array_equal(xs, o)
 
 
 def test_batched_jobs_take_the_table_entry():

@@ -105,3 +105,24 @@ def test_invalid_run_is_rejected_synchronously(ctx):
         ctx.submit(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
                    L.make_cond(L.LSR_COND_BELOW, 1e-6, 1), 10, L.LSR_BC_RING)
     assert ei.value.status == L.LSR_EINVAL
+
+
+def test_extreme_check_periods(ctx):
+    # a check period of at least max_iter checks only at the cap (a period of
+    # 2^31 - 1 with a cap of 64 sweeps runs); a period whose chunk base
+    # lcm(period, 2K) would pass the driver's bound is rejected at submission
+    # instead of overflowing the chunk arithmetic
+    import torch
+    say("extreme check periods")
+    a = I.laplace_input(96, seed=4)
+    t = torch.from_numpy(a).to("cuda:0")
+    r = ctx.run(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                L.make_cond(L.LSR_COND_BELOW, 0.0, (1 << 31) - 1), 64, L.LSR_BC_RING)
+    o, ro = O.jacobi_run(a, reduce_op=O.RED_MAX_ABS_DELTA, thr=0.0, check_every=64, max_iter=64)
+    assert r.status == L.LSR_OK and r.iterations == 64 and ro.n == 64
+    assert np.array_equal(t.cpu().numpy(), o)
+    for every in ((1 << 31) - 1, 65537 * 2):
+        with pytest.raises(L.LsrError) as ei:
+            ctx.submit(t, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                       L.make_cond(L.LSR_COND_BELOW, 0.0, every), 1 << 40, L.LSR_BC_RING)
+        assert ei.value.status == L.LSR_EINVAL
