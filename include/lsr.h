@@ -224,12 +224,13 @@ lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
  * automatic (tile_rows, tb_depth, waves and unroll all 0) take the table's entry for their
  * key, so a job's settings depend only on its key. On a batched context the candidates are
  * the engine's own settings (the fused depths its Jacobi families hold and the band rows of a
- * wavefront tile; band rows for Life) and each candidate job runs alone in the engine's rounds;
- * the table then serves that context's later jobs (and others through lsr_tune_export /
- * lsr_tune_import). The winner is copied to best_out when it is not NULL. Blocks until done
- * (a few hundred short jobs on a plain context, a few dozen on a batched one; about a second
- * at 8192^2); no other job of the context may run meanwhile. EINVAL for stencils other than
- * Laplace, Helmholtz and Life; ENOMEM/EDEVICE as lsr_run.
+ * wavefront tile; band rows for Life), each measured on 8-256 jobs of the key run together
+ * (about 2^25 cells, so the rounds are full); the table then serves that context's later jobs
+ * (and others through lsr_tune_export / lsr_tune_import). The winner is copied to best_out
+ * when it is not NULL. Blocks until done (a plain context: a few hundred short jobs, about a
+ * second at 8192^2; a batched one: up to a few seconds per key); no other job of the context
+ * may run meanwhile. EINVAL for stencils other than Laplace, Helmholtz and Life; ENOMEM/EDEVICE
+ * as lsr_run.
  * The caller owns nothing new; scratch returns to the context's pool.
  */
 lsr_status lsr_autotune(lsr_ctx *ctx, int32_t stencil_id, int32_t dtype, int64_t rows,
