@@ -273,9 +273,14 @@ lsr_status lsr_ctx::engine_admit() {
             HIP_TRY(hipMemsetAsync(partner, 0, (size_t)g.rows * g.pitch * esz, copy_stream));
         }
         if (j->two_phase) {
-            // the frame only: detection writes the mask and the initial iterate
+            // the frame only; detection (the mask and the initial iterate) follows
+            // on the copy stream, so it overlaps the sweep rounds of the frames
+            // already in the tables instead of queueing behind them
             HIP_TRY(hipMemcpy2DAsync(sy, g.pitch, j->in_host, j->host_pitch, g.cols, g.rows,
                                      hipMemcpyHostToDevice, copy_stream));
+            HIP_TRY(lsr::launch_amf_detect(static_cast<const uint8_t*>(sy), g.rows, g.cols, g.pitch,
+                                           j->w_max, static_cast<uint8_t*>(senv), s0, g.dtype,
+                                           copy_stream));
         } else {
             const size_t ee = env_esz(j);
             HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
@@ -347,10 +352,7 @@ lsr_status lsr_ctx::engine_activate(Job* j) {
                                      g.cols * ee, g.rows, hipMemcpyDeviceToDevice, stream));
         }
     }
-    if (j->two_phase)   // phase 1 on the device: mask and initial iterate
-        HIP_TRY(lsr::launch_amf_detect(static_cast<const uint8_t*>(j->stage_y), g.rows, g.cols,
-                                       g.pitch, j->w_max, static_cast<uint8_t*>(j->stage_env),
-                                       j->buf[0], g.dtype, stream));
+    // (a two-phase frame's detection ran on the copy stream after its H2D copy)
     if (j->stencil == LSR_ST_LIFE) {
         int np = 0;
         HIP_TRY(lsr::launch_count_u8(static_cast<uint8_t*>(g.data), g.rows, g.cols, g.pitch,
