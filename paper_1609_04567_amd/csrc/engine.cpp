@@ -41,6 +41,7 @@ lsr_status lsr_ctx::engine_setup() {
     HIP_TRY(hipStreamCreateWithFlags(&small_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&copy_out_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&detect_stream, hipStreamNonBlocking));
     HIP_TRY(hipMalloc(&d_jobs, sizeof(lsr::BatchJob) * kMaxBatch));
     HIP_TRY(hipMalloc(&d_work, sizeof(lsr::WorkItem) * (kMaxWork + kPad)));
     for (int i = 0; i < 2; ++i) {
@@ -60,7 +61,7 @@ void lsr_ctx::engine_teardown() {
         (void)hipStreamDestroy(small_stream);
         small_stream = nullptr;
     }
-    for (hipStream_t* cs : {&copy_stream, &copy_out_stream}) {
+    for (hipStream_t* cs : {&copy_stream, &copy_out_stream, &detect_stream}) {
         if (*cs) {
             (void)hipStreamSynchronize(*cs);
             (void)hipStreamDestroy(*cs);
@@ -274,13 +275,18 @@ lsr_status lsr_ctx::engine_admit() {
         }
         if (j->two_phase) {
             // the frame only; detection (the mask and the initial iterate) follows
-            // on the copy stream, so it overlaps the sweep rounds of the frames
-            // already in the tables instead of queueing behind them
+            // on a stream of its own after the copy, so it overlaps the sweep rounds
+            // of the frames already in the tables and the next frames' copies
             HIP_TRY(hipMemcpy2DAsync(sy, g.pitch, j->in_host, j->host_pitch, g.cols, g.rows,
                                      hipMemcpyHostToDevice, copy_stream));
+            hipEvent_t copied = get_event();
+            if (!copied) return fail(LSR_EDEVICE, "event pool");
+            HIP_TRY(hipEventRecord(copied, copy_stream));
+            HIP_TRY(hipStreamWaitEvent(detect_stream, copied, 0));
+            put_event(copied);
             HIP_TRY(lsr::launch_amf_detect(static_cast<const uint8_t*>(sy), g.rows, g.cols, g.pitch,
                                            j->w_max, static_cast<uint8_t*>(senv), s0, g.dtype,
-                                           copy_stream));
+                                           detect_stream));
         } else {
             const size_t ee = env_esz(j);
             HIP_TRY(hipMemcpy2DAsync(s0, g.pitch * esz, ug.data, ug.pitch * esz, g.cols * esz,
@@ -291,7 +297,7 @@ lsr_status lsr_ctx::engine_admit() {
         }
         j->ev_in = get_event();
         if (!j->ev_in) return fail(LSR_EDEVICE, "event pool");
-        HIP_TRY(hipEventRecord(j->ev_in, copy_stream));
+        HIP_TRY(hipEventRecord(j->ev_in, j->two_phase ? detect_stream : copy_stream));
         j->t_admit = Clock::now();
     }
 }
@@ -594,6 +600,7 @@ void lsr_ctx::serve() {
             (void)hipStreamSynchronize(stream);
             (void)hipStreamSynchronize(copy_stream);
             (void)hipStreamSynchronize(copy_out_stream);
+            (void)hipStreamSynchronize(detect_stream);
             std::vector<Job*> all(active.begin(), active.end());
             all.insert(all.end(), retiring.begin(), retiring.end());
             all.insert(all.end(), ingesting.begin(), ingesting.end());

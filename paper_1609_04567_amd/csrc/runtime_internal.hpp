@@ -293,6 +293,7 @@ struct lsr_ctx {
     hipStream_t copy_stream = nullptr;       // batched engine: H2D copies of host jobs
     hipStream_t copy_out_stream = nullptr;   // batched engine: D2H copies at retirement (the two
                                              // directions of the link run at the same time)
+    hipStream_t detect_stream = nullptr;     // batched engine: detection of two-phase frames
     hipStream_t capture = nullptr;   // stream used only for graph capture
     lsr_rt::Pool pool;
     lsr_tuning tuning{};
