@@ -337,6 +337,15 @@ def run_life(args, L, I, torch):
         out["cpu_baseline"] = {"value": round(n * n * k / dt / 1e9, 4), "unit": "GLUP/s",
                                "cores": O.threads(), "kind": "oracle",
                                "sample": f"first {k} generations ({dt:.1f} s)"}
+        cores = O.threads()
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        O.life_run(s, cond=O.COND_NEVER, max_iter=1)
+        dt1 = time.perf_counter() - t0
+        O.set_threads(cores)
+        out["cpu_baseline_1core"] = {"value": round(n * n / dt1 / 1e9, 4), "unit": "GLUP/s",
+                                     "cores": 1, "kind": "oracle", "all_cores": cores,
+                                     "sample": f"first generation ({dt1:.1f} s)"}
     ctx.close()
     return out
 
@@ -396,6 +405,18 @@ def run_restore(args, L, I, torch):
                "cores": O.threads(), "kind": "oracle",
                "sample": f"the whole job: detection {t1 - t0:.2f} s, {ro.n} restoration "
                          f"sweeps {t2 - t1:.2f} s"}
+        # the same oracle on one core: detection and the first sweep of the job
+        cores = O.threads()
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        O.amf_detect(rin.y, 19)
+        t1 = time.perf_counter()
+        O.restore_run(u_o.astype(np.float64), m_o, thr=0.1, max_iter=1)
+        t2 = time.perf_counter()
+        O.set_threads(cores)
+        cpu1 = {"value": round(n * n / (t2 - t0) / 1e9, 4), "unit": "GLUP/s", "cores": 1,
+                "kind": "oracle", "all_cores": cores,
+                "sample": f"detection {t1 - t0:.2f} s and one restoration sweep {t2 - t1:.2f} s"}
     for v in out_runs.values():
         v.pop("field")
         v.pop("mask")
@@ -409,6 +430,7 @@ def run_restore(args, L, I, torch):
     if oracle_cmp:
         out["accuracy"] = oracle_cmp
         out["cpu_baseline"] = cpu
+        out["cpu_baseline_1core"] = cpu1
     ctx.close()
     return out
 
