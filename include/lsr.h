@@ -229,8 +229,8 @@ lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
  * (and others through lsr_tune_export / lsr_tune_import). The winner is copied to best_out
  * when it is not NULL. Blocks until done (a plain context: a few hundred short jobs, about a
  * second at 8192^2; a batched one: up to a few seconds per key); no other job of the context
- * may run meanwhile. EINVAL for stencils other than Laplace, Helmholtz and Life; ENOMEM/EDEVICE
- * as lsr_run.
+ * may run meanwhile (a batched context with unfinished jobs: EBUSY). EINVAL for stencils other
+ * than Laplace, Helmholtz and Life; ENOMEM/EDEVICE as lsr_run.
  * The caller owns nothing new; scratch returns to the context's pool.
  */
 lsr_status lsr_autotune(lsr_ctx *ctx, int32_t stencil_id, int32_t dtype, int64_t rows,

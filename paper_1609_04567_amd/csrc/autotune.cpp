@@ -118,6 +118,10 @@ lsr_status lsr_autotune(lsr_ctx* ctx, int32_t stencil_id, int32_t dtype, int64_t
     if (!ctx) return fail(LSR_EINVAL, "ctx is NULL");
     if (stencil_id != LSR_ST_LAPLACE5 && stencil_id != LSR_ST_HELMHOLTZ5 && stencil_id != LSR_ST_LIFE)
         return fail(LSR_EINVAL, "the autotuner covers the Laplace, Helmholtz and Life sweeps");
+    if (ctx->batched) {   // its candidates go through the context's overrides
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->unfinished > 0) return fail(LSR_EBUSY, "the batched context has jobs running");
+    }
     if (rows < 1 || cols < 1 || rows > (1 << 20) || cols > (1 << 20))
         return fail(LSR_EINVAL, "rows and cols must be in [1, 2^20]");
     const size_t esz = dtype_size(dtype);

@@ -106,6 +106,14 @@ def test_batched_context_tunes_its_own_families():
         with pytest.raises(L.LsrError) as ei:
             c.autotune(L.LSR_ST_RESTORE, L.LSR_F32, 64, 64, 1)
         assert ei.value.status == L.LSR_EINVAL
+        # a job still running on the context: the tuner would change its settings
+        big = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda:0")
+        busy = c.submit(big, L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA,
+                        L.make_cond(L.LSR_COND_NEVER, 0.0, 1), 4000, L.LSR_BC_RING)
+        with pytest.raises(L.LsrError) as ei:
+            c.autotune(L.LSR_ST_LAPLACE5, L.LSR_F32, 300, 300, 1, 40)
+        assert ei.value.status == L.LSR_EBUSY
+        assert c.result(busy).status == L.LSR_OK
         best = c.autotune(L.LSR_ST_HELMHOLTZ5, L.LSR_F32, 300, 300, 10, 160)
         assert best.tb_depth in (5, 2) and best.tile_rows in (8, 16, 24, 32, 48, 64)
         assert best.waves == 0 and best.unroll == 0
