@@ -32,6 +32,22 @@ def test_amf_detect_bit_exact(ctx, shape, noise, wmax):
         assert np.array_equal(u.cpu().numpy().astype(np.float64), u_o.astype(np.float64))
 
 
+@pytest.mark.parametrize("shape,noise,wmax,frame", [((480, 640), 0.7, 19, 3), ((480, 640), 0.3, 19, 50),
+                                                    ((130, 97), 0.7, 5, 7), ((61, 200), 0.9, 9, 1)])
+def test_amf_detect_bit_exact_on_video_frames(ctx, shape, noise, wmax, frame):
+    """Video frames (smooth integer plateaus, where windows often grow past 5x5):
+    the comparator-network windows, the radix windows and their hand-over."""
+    import torch
+    say(f"amf video frame {shape} noise={noise} wmax={wmax}")
+    r = I.video_frame(*shape, frame, noise=noise)
+    m_o, u_o = O.amf_detect(r.y, wmax)
+    y = torch.from_numpy(r.y).to("cuda:0")
+    m, u = ctx.amf_detect(y, wmax, torch.uint8)
+    torch.cuda.synchronize()
+    assert np.array_equal(m.cpu().numpy(), m_o)
+    assert np.array_equal(u.cpu().numpy(), u_o)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (64, 64), (128, 200), (257, 255)])
 @pytest.mark.parametrize("red", [L.LSR_RED_MAX_ABS_DELTA, L.LSR_RED_MEAN_ABS_DELTA])
 def test_restore_f64_matches_oracle(ctx, shape, red):
