@@ -2,8 +2,8 @@
 //
 // Phase 1, adaptive-median detection (integer, one shot). A 16x16 workgroup
 // stages its pixels plus a halo of w_max/2 in LDS. Each thread grows its window
-// w = 3, 5, ..., w_max over the in-range pixels only. A full 3x3 or 5x5 window
-// goes through a comparator network (select_networks.hpp) that leaves its min,
+// w = 3, 5, ..., w_max over the in-range pixels only. A full 3x3, 5x5 or 7x7
+// window goes through a comparator network (select_networks.hpp) that leaves its min,
 // lower median (rank (count-1)/2) and max in known registers; any other window
 // finds min and max in one pass and the lower median by a radix select: the
 // largest v with #{x < v} <= rank, decided two bits at a time from the top (four
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
     const int yv = tile[ci * TW + cj];
     int lo = 0, hi = 0, med = 0, flag = 0;
     bool decided = false;
-    // full 3x3 and 5x5 windows (most pixels decide in one of them): minimum,
+    // full 3x3, 5x5 and 7x7 windows (most pixels decide in one of them): minimum,
     // lower median and maximum by comparator networks on registers; windows
     // clipped by the border and larger ones by the radix select below
     int w0 = 3;
@@ -82,6 +82,22 @@ __global__ __launch_bounds__(kAmfTile * kAmfTile) void amf_detect_kernel(
                 decided = true;
             }
             w0 = 7;
+            if (!decided && w_max >= 7 && i >= 3 && i + 3 < rows && jx >= 3 && jx + 3 < cols) {
+                int x[49];
+#pragma unroll
+                for (int a = 0; a < 7; ++a)
+#pragma unroll
+                    for (int b = 0; b < 7; ++b) x[a * 7 + b] = tile[(ci - 3 + a) * TW + cj - 3 + b];
+                select49(x);
+                lo = x[kSel49Min];
+                med = x[kSel49Med];
+                hi = x[kSel49Max];
+                if (lo < med && med < hi) {
+                    flag = !(lo < yv && yv < hi);
+                    decided = true;
+                }
+                w0 = 9;
+            }
         }
     }
     for (int w = w0; w <= w_max && !decided; w += 2) {

@@ -1,6 +1,6 @@
 """The comparator networks of csrc/select_networks.hpp (the detection's minimum,
-lower median and maximum of full 3x3 and 5x5 windows), checked exhaustively by the
-0-1 principle: a comparator network puts the rank-r element into a register for
+lower median and maximum of full 3x3, 5x5 and 7x7 windows); the first two checked
+exhaustively by the 0-1 principle: a comparator network puts the rank-r element into a register for
 every input iff it does so for every input of zeros and ones. All 2^9 and 2^25
 0-1 inputs are run bit-parallel (one bit per input, 64 inputs per word); the 3x3
 network is also checked against a fresh run of its generator."""
@@ -81,7 +81,7 @@ def test_network_selects_min_median_max_for_every_01_input(count):
     assert np.array_equal(v[rmax], _at_least(_wires(count), 1))
 
 
-@pytest.mark.parametrize("count", [9, 25])
+@pytest.mark.parametrize("count", [9, 25, 49])
 def test_network_on_random_bytes(count):
     ops, (rmin, rmed, rmax) = _parse(count)
     rng = np.random.default_rng(count)
@@ -112,3 +112,48 @@ def test_generator_sorts_and_reproduces_the_3x3_network():
     assert (np.diff(x.astype(np.int8), axis=1) >= 0).all()
     ops, outs = gen.selection_network(9, 16, [0, 4, 8])
     assert (ops, outs) == _parse(9)
+    # the 7x7 network is the backward-pruned Batcher network (no greedy step): an
+    # exact pruning, since a dropped comparator writes nothing that reaches an output
+    ops, outs = gen.selection_network(49, 64, [0, 24, 48], greedy=False)
+    assert (ops, outs) == _parse(49)
+
+
+def test_49_network_on_random_01_inputs():
+    """2^20 random 0-1 inputs (bit-parallel, 64 per word), each wire's bit drawn
+    with a per-word probability so every count of ones is well covered."""
+    ops, (rmin, rmed, rmax) = _parse(49)
+    rng = np.random.default_rng(11)
+    nwords = 1 << 14
+    p = rng.uniform(0.2, 0.8, size=nwords)   # density of ones of each word's 64 inputs
+    bits = rng.random((49, nwords, 64)) < p[None, :, None]
+    weights = (1 << np.arange(64, dtype=np.uint64)).astype(np.uint64)
+    w = [(bits[k].astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64) for k in range(49)]
+    v = list(w)
+    for a, b in ops:
+        v[a], v[b] = v[a] & v[b], v[a] | v[b]
+    assert np.array_equal(v[rmin], _at_least(w, 49))
+    assert np.array_equal(v[rmed], _at_least(w, 25))
+    assert np.array_equal(v[rmax], _at_least(w, 1))
+
+
+def test_49_network_on_structured_inputs():
+    """All-equal runs, two-valued inputs with every count of ones at every
+    position shift, and sorted / reversed byte ramps (the cases a selection
+    network gets wrong first)."""
+    ops, (rmin, rmed, rmax) = _parse(49)
+    rng = np.random.default_rng(7)
+    cases = []
+    for ones in range(50):
+        for _ in range(40):
+            x = np.zeros(49, dtype=np.int64)
+            x[rng.permutation(49)[:ones]] = 1
+            cases.append(x)
+    cases += [np.arange(49), np.arange(49)[::-1], np.full(49, 7)]
+    x = np.array(cases).T
+    v = [x[k].copy() for k in range(49)]
+    for a, b in ops:
+        v[a], v[b] = np.minimum(v[a], v[b]), np.maximum(v[a], v[b])
+    s = np.sort(x, axis=0)
+    assert np.array_equal(v[rmin], s[0])
+    assert np.array_equal(v[rmed], s[24])
+    assert np.array_equal(v[rmax], s[-1])
