@@ -310,6 +310,11 @@ constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 // same values bit for bit; only the order of a lane's delta sum changes.
 // GA > 0: the g rows of the next GA levels are read from the ring ahead of their
 // use, so a level does not wait for its own LDS read.
+// Band groups per dispatch chunk of a vertical-tile launch (8192^2 FP64 Helmholtz,
+// depth 10: 1, 4, 8, 16, 32 -> 1387, 1381, 1401, 1393, 1365 GLUP/s; fetched bytes
+// -2 % at 8, +10 % at 32, where a chunk's windows no longer run together).
+constexpr int kTbChunk = 8;
+
 template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false,
           bool MC = false, bool SEP = false, bool VERT = false, int GA = 0>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
@@ -325,7 +330,20 @@ __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __re
     constexpr int OW = tb_out_width<VEC, K>();
     static_assert(!VERT || !WT, "vertical band groups are workgroup tiles");
     const bool check = (check_mask >> (K - 1)) & 1u;
-    const int tband = t / strips, strip = t - tband * strips;
+    int tband, strip;
+    if (VERT) {
+        // band groups in chunks of kTbChunk: a chunk's tiles go window by window,
+        // its band groups innermost, so the groups above and below a seam start
+        // together and read the seam's 2K rows from L2 the second time
+        const int bands = tiles / strips, span = strips * kTbChunk;
+        const int ch = t / span, r = t - ch * span;
+        const int hb = min(kTbChunk, bands - ch * kTbChunk);
+        strip = r / hb;
+        tband = ch * kTbChunk + (r - strip * hb);
+    } else {
+        tband = t / strips;
+        strip = t - tband * strips;
+    }
     const int lane = threadIdx.x & 63;
     // the wavefront's slot in the workgroup (a wavefront tile of the batched kernel
     // is NW = 1 in a workgroup of several); readfirstlane keeps it scalar

@@ -259,6 +259,9 @@ def test_model_flags_the_unguarded_west_halo():
 # lets in-grid rows be read.
 # ---------------------------------------------------------------------------
 
+TB_CHUNK = 8                              # band groups per dispatch chunk (vertical tiles)
+
+
 def _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert=False):
     ow = (64 * vec - 2 * k) // vec * vec
     need = cols - 1 - k
@@ -273,7 +276,13 @@ def _tb_waves(rows, cols, vec, nw, k, tile_rows, vert):
     """(t, w, cw, r0, r1, up) of every wavefront of a launch, as the kernel derives them."""
     ow, strips, groups = _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert)
     for t in range(strips * groups):
-        tband, strip = divmod(t, strips)
+        if vert:                          # chunks of TB_CHUNK band groups, groups innermost
+            ch, r = divmod(t, strips * TB_CHUNK)
+            hb = min(TB_CHUNK, groups - ch * TB_CHUNK)
+            strip, h = divmod(r, hb)
+            tband = ch * TB_CHUNK + h
+        else:
+            tband, strip = divmod(t, strips)
         for w in range(nw):
             band = tband * nw + w if vert else tband
             cw = (strip if vert else strip * nw + w) * ow
@@ -400,7 +409,7 @@ def test_tb_vertical_groups_cover_rows_and_guard_loads_at_full_size(rows, cols, 
     ow, strips, groups = _tb_geometry(rows, cols, vec, nw, k, tile_rows, vert=True)
     cover = {}
     for t, w, cw, r0, r1, up in _tb_waves(rows, cols, vec, nw, k, tile_rows, True):
-        if t % strips not in (0, 1, strips - 1):
+        if cw // ow not in (0, 1, strips - 1):
             continue                     # windows are alike apart from the edge ones
         if r0 >= r1:
             continue
