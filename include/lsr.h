@@ -185,8 +185,9 @@ typedef struct {
                                unfused. Fields and counts are bit for bit those of unfused
                                sweeps; a float reduce value differs at most in the order of
                                its partial sums. Restoration is never fused. A batched context
-                               takes the depth (FP64 10, 5 or 2; FP32 5 or 2) and tile_rows
-                               from the same overrides or tuning table. */
+                               takes the depth (FP64 10, 5 or 2; FP32 5 or 2; Life 8 where
+                               rows hold a multiple of 16 cells, 1 = one generation per
+                               round) and tile_rows from the same overrides or tuning table. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */
     int32_t waves;          /* Jacobi: wavefronts per workgroup (1, 2 or 4) */
@@ -224,7 +225,8 @@ lsr_status lsr_set_tuning(lsr_ctx *ctx, const lsr_tuning *tuning);
  * automatic (tile_rows, tb_depth, waves and unroll all 0) take the table's entry for their
  * key, so a job's settings depend only on its key. On a batched context the candidates are
  * the engine's own settings (the fused depths its Jacobi families hold and the band rows of a
- * wavefront tile; band rows for Life), each measured on 8-256 jobs of the key run together
+ * wavefront tile; for Life one or 8 generations per round, each with its band rows), each
+ * measured on 8-256 jobs of the key run together
  * (about 2^25 cells, so the rounds are full); the table then serves that context's later jobs
  * (and others through lsr_tune_export / lsr_tune_import). The winner is copied to best_out
  * when it is not NULL. Blocks until done (a plain context: a few hundred short jobs, about a

@@ -57,7 +57,8 @@ std::vector<lsr_tuning> candidates(int stencil) {
 // Candidates on a batched context: the engine's families take the fused depth
 // (Jacobi: FP32 5 or 2, FP64 10, 5 or 2, kept only where it divides the check
 // period; otherwise depth 5 with checks inside) and the band rows of a wavefront
-// tile (Life: band rows of the one-generation SWAR tile).
+// tile (Life: one generation per round, the SWAR tile, or 8, the fused tile of
+// grids whose rows hold a multiple of 16 cells, each with its band rows).
 std::vector<lsr_tuning> candidates_batched(int stencil, int dtype, int check_every) {
     std::vector<lsr_tuning> out;
     auto add = [&](int tile_rows, int depth) {
@@ -67,7 +68,8 @@ std::vector<lsr_tuning> candidates_batched(int stencil, int dtype, int check_eve
         out.push_back(t);
     };
     if (stencil == LSR_ST_LIFE) {
-        for (int tr : {8, 16, 32, 64, 128}) add(tr, 0);
+        for (int tr : {8, 16, 32, 64, 128}) add(tr, 1);
+        for (int tr : {16, 32, 64, 128}) add(tr, 8);
         return out;
     }
     std::vector<int> depths;

@@ -18,6 +18,7 @@
 #include "kernels.hpp"
 #include "tile_jacobi.hpp"
 #include "tile_life.hpp"
+#include "tile_life_tb.hpp"
 #include "tile_restore.hpp"
 #include "tile_sobel.hpp"
 
@@ -27,6 +28,7 @@ namespace {
 constexpr int kBatchThreads = 256;
 constexpr int kWavesPerGroup = kBatchThreads / 64;
 constexpr int kLifeTileRows = 32;
+constexpr int kLifeTbRows = 64;   // band of a fused Life tile (8 generations: 16 halo rows)
 constexpr int kRestoreTileRows = 16;
 
 template <typename T, int VEC, int K, bool MC>
@@ -56,6 +58,7 @@ template <> struct KindInfo<BK_JAC_F32_TB5> { static constexpr int step = 5, vec
 template <> struct KindInfo<BK_JAC_F32_TB2> { static constexpr int step = 2, vec = 4; static constexpr bool mc = false; };
 template <> struct KindInfo<BK_JAC_F64_TB5_MC> { static constexpr int step = 5, vec = 2; static constexpr bool mc = true; };
 template <> struct KindInfo<BK_JAC_F32_TB5_MC> { static constexpr int step = 5, vec = 4; static constexpr bool mc = true; };
+template <> struct KindInfo<BK_LIFE_TB8> { static constexpr int step = 8, vec = 0; static constexpr bool mc = true; };
 
 // Work items of one kernel family; the work list segment of this launch holds only
 // jobs of that family (one launch per family keeps each its own register budget).
@@ -92,6 +95,28 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
                                          J.rows, J.cols, J.pitch, J.torus, check, w.tile, J.strips,
                                          J.tile_rows, static_cast<unsigned long long*>(J.partials),
                                          nullptr);
+    if constexpr (KIND == BK_LIFE_TB8) {
+        // generations n+1 .. n+8 of one band of one window; generation n+l's count
+        // goes to partials[(l - 1) * tiles + tile]
+        const int band = w.tile / J.strips, strip = w.tile - band * J.strips;
+        uint32_t cnt[STEP];
+#pragma unroll
+        for (int l = 0; l < STEP; ++l) cnt[l] = 0;
+        const uint8_t* a = static_cast<const uint8_t*>(src);
+        uint8_t* b = static_cast<uint8_t*>(dst);
+        if (J.torus)
+            life_tb_band<STEP, 3, true>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
+        else
+            life_tb_band<STEP, 3, false>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
+        auto* parts = static_cast<unsigned long long*>(J.partials);
+#pragma unroll
+        for (int l = 0; l < STEP; ++l) {
+            if ((mask >> l) & 1u) {
+                const unsigned long long v = wave_sum_u64(cnt[l]);
+                if ((threadIdx.x & 63) == 0) parts[(size_t)l * (size_t)J.tiles + w.tile] = v;
+            }
+        }
+    }
     if constexpr (KIND == BK_RESTORE_F64 || KIND == BK_RESTORE_F32) {
         typedef typename std::conditional<KIND == BK_RESTORE_F64, double, float>::type T;
         __shared__ uint16_t rlist[kWavesPerGroup][kRestoreTileRows * 64];
@@ -325,6 +350,16 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_
         j.tiles = 1;   // one work item = the whole job; no partials
         return;
     }
+    if (is_life && j.cols % 16 == 0 && want_depth != 1) {
+        // rows are 16-byte aligned and hold no padding cells
+        j.kind = BK_LIFE_TB8;
+        j.step = KindInfo<BK_LIFE_TB8>::step;
+        j.mc = 1;
+        j.tile_rows = want_tile_rows > 0 ? want_tile_rows : kLifeTbRows;
+        j.strips = (int)((j.cols + kLifeTbWinCols - 1) / kLifeTbWinCols);
+        j.tiles = j.strips * (int)((j.rows + j.tile_rows - 1) / j.tile_rows);
+        return;
+    }
     if (is_life) {
         // rows are 16-byte aligned with zeroed padding to a multiple of 16 cells
         j.kind = BK_LIFE_SWAR;
@@ -393,6 +428,7 @@ hipError_t launch_batch_sweep(const BatchJob* jobs, const WorkItem* work, int ki
         case BK_RESTORE_F64: launch_kind<BK_RESTORE_F64>(jobs, work, groups, s); break;
         case BK_RESTORE_F32: launch_kind<BK_RESTORE_F32>(jobs, work, groups, s); break;
         case BK_SOBEL: launch_kind<BK_SOBEL>(jobs, work, groups, s); break;
+        case BK_LIFE_TB8: launch_kind<BK_LIFE_TB8>(jobs, work, groups, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -131,6 +131,11 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     int nparts = d.mc ? d.tiles * d.step : d.tiles;
     if (life) {
         nparts = std::max(nparts, lsr::count_u8_parts(g.rows, g.cols));
+        if (d.step > 1) {
+            // single generations that replay a stop inside a fused round
+            j->replay_geom = lsr::life_geom(life_args(j, nullptr, nullptr), 0);
+            nparts = std::max(nparts, j->replay_geom.tiles);
+        }
     } else if (!restore && !sobel) {
         // unfused geometry that replays a stop inside a round (rows are aligned:
         // null pointers stand for the buffers, which are not allocated yet)
@@ -141,9 +146,11 @@ lsr_status lsr_ctx::engine_submit(Job* j) {
     }
     j->nparts_alloc = nparts;
     // device time of a round per cell, in bytes at 5 TB/s (restoration: its
-    // measured ALU time per pixel)
-    const double per_cell = life || sobel ? 2.0 : restore ? (f32 ? 28.0 : 58.0)
-                                                          : (double)esz * (d.helm ? 3.0 : 2.0);
+    // measured ALU time per pixel; a fused Life round of 8 generations: 2.1
+    // single ones)
+    const double per_cell = life ? (d.step > 1 ? 4.3 : 2.0)
+                            : sobel ? 2.0 : restore ? (f32 ? 28.0 : 58.0)
+                                      : (double)esz * (d.helm ? 3.0 : 2.0);
     j->est_us = (double)g.rows * (double)g.cols * per_cell / 5.0e6;
     if (d.tiles > kMaxWork) return fail(LSR_EINVAL, "grid too large for the batched engine");
     return LSR_OK;

@@ -143,9 +143,10 @@ enum BatchKind : int32_t {
     BK_SMALL_LIFE = 11,    //   Life
     BK_RESTORE_F64 = 12,   // restoration sweep (phase 2 of Sect. 4.3), FP64, 16 x 64 pixels per tile
     BK_RESTORE_F32 = 13,   //   FP32 storage
-    BK_SOBEL = 14          // Sobel edge detector, 8 rows x 256 columns per tile
+    BK_SOBEL = 14,         // Sobel edge detector, 8 rows x 256 columns per tile
+    BK_LIFE_TB8 = 15       // Life, 8 fused generations per round, any checks inside
 };
-constexpr int kBatchKinds = 14;
+constexpr int kBatchKinds = 15;
 // A grid runs whole-grid-in-LDS when both of its buffers fit in this many bytes
 // (rows * cols * element size * 2; one 1024-thread workgroup per job).
 constexpr int64_t kSmallLdsBytes = 160 * 1024 - 1024;
@@ -188,7 +189,10 @@ struct WorkItem {
 // cap, else the deepest such depth, else depth 5 with checks inside (also
 // chosen by want_depth = 5); want_tile_rows > 0 sets the band height. The
 // wanted values come from the context's tuning table, so the geometry is still
-// a function of the job's own key.
+// a function of the job's own key. A Life job whose rows hold a multiple of 16
+// cells runs 8 generations per round (one band of one 992-column window per
+// wavefront, tile_life_tb.hpp) unless want_depth is 1; other Life jobs one
+// generation per round.
 void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth = 0, int want_tile_rows = 0);
 // The same for a restoration job: one tile = 16 rows x 64 columns (one wavefront),
 // one sweep per round; never whole-grid-in-LDS.

@@ -118,7 +118,7 @@ def test_batched_context_tunes_its_own_families():
         assert best.tb_depth in (5, 2) and best.tile_rows in (8, 16, 24, 32, 48, 64)
         assert best.waves == 0 and best.unroll == 0
         lb = c.autotune(L.LSR_ST_LIFE, L.LSR_U8, 200, 200, 1, 240)
-        assert lb.tb_depth == 0 and lb.tile_rows in (8, 16, 32, 64, 128)
+        assert lb.tb_depth in (1, 8) and lb.tile_rows in (8, 16, 32, 64, 128)
         entries = json.loads(L.lsr_tune_export(c.handle))["entries"]
         assert len(entries) == 3   # Helmholtz, Life torus, Life dead border
         t = torch.from_numpy(h.u0.astype(np.float32)).to("cuda:0")

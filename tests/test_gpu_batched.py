@@ -235,3 +235,61 @@ def test_stops_inside_rounds_are_replayed(bctx):
         assert bool(r.converged) == ro.converged
         assert np.array_equal(t.cpu().numpy(), o)
         assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
+
+
+# (rows, cols, torus, cond, check_every, max_iter): rows of a multiple of 16 cells
+# take the fused family (8 generations per round), others one generation per round
+FUSED_LIFE = [(320, 512, True, L.LSR_COND_STABLE_FOR, 1, 700),
+              (300, 1008, False, L.LSR_COND_STABLE_FOR, 1, 900),   # a 16-column second window
+              (257, 2000, True, L.LSR_COND_STABLE_FOR, 3, 400),
+              (200, 1984, False, L.LSR_COND_NEVER, 1, 123),        # cap inside a round
+              (333, 496, True, L.LSR_COND_NEVER, 5, 61),
+              (300, 500, True, L.LSR_COND_STABLE_FOR, 1, 300)]     # not a multiple of 16
+
+
+def test_fused_life_rounds_match_oracle(bctx):
+    """Life jobs on the fused batched family (8 generations per round, counts of
+    every checked generation inside a round, a stop inside a round replayed one
+    generation at a time) equal the oracle bit for bit: field, stop generation and
+    live count; a width that is not a multiple of 16 cells runs one generation per
+    round and agrees too."""
+    import torch
+    say("batched fused life")
+    cases = []
+    for k, (rows, cols, torus, cond, every, mi) in enumerate(FUSED_LIFE):
+        a = I.life_input(rows, cols, seed=40 + k)
+        t = torch.from_numpy(a).to("cuda:0")
+        c = L.make_cond(cond, 0.0, every, 10)
+        jid = bctx.submit(t, L.LSR_ST_LIFE, L.LSR_RED_SUM, c, mi,
+                          L.LSR_BC_TORUS if torus else L.LSR_BC_BOTTOM)
+        cases.append((rows, cols, torus, cond, every, mi, a, t, jid))
+    for rows, cols, torus, cond, every, mi, a, t, jid in cases:
+        r = bctx.result(jid)
+        torch.cuda.synchronize()
+        o, ro = O.life_run(a, bc=O.BC_TORUS if torus else O.BC_BOTTOM,
+                           cond=O.COND_STABLE_FOR if cond == L.LSR_COND_STABLE_FOR else O.COND_NEVER,
+                           stable_window=10, check_every=every, max_iter=mi)
+        name = (rows, cols, torus, every, mi)
+        assert r.status == L.LSR_OK, name
+        assert r.sweeps_per_launch == (8 if cols % 16 == 0 else 1), name
+        assert r.iterations == ro.n and r.last_count == ro.count, (name, r.iterations, ro.n)
+        assert np.array_equal(t.cpu().numpy(), o), name
+
+
+def test_fused_life_stop_inside_a_round(bctx):
+    """A still life plus a blinker on a wide dead-border grid: the live count is
+    constant from generation 0, so a stable window of 10 stops at generation 10,
+    inside the second fused round; the engine replays generations 9 and 10."""
+    import torch
+    say("batched fused life, stop inside a round")
+    cells = [(5, 5), (5, 6), (6, 5), (6, 6),           # block
+             (40, 991), (40, 992), (40, 993)]         # blinker across the first window seam
+    for window, stop in ((10, 10), (5, 5), (17, 17)):
+        a = I.life_pattern(96, 1024, cells)
+        t = torch.from_numpy(a).to("cuda:0")
+        r = bctx.run(t, L.LSR_ST_LIFE, L.LSR_RED_SUM, L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1, window),
+                     500, L.LSR_BC_BOTTOM)
+        torch.cuda.synchronize()
+        o, ro = O.life_run(a, bc=O.BC_BOTTOM, stable_window=window, max_iter=500)
+        assert ro.n == stop and r.iterations == stop and r.sweeps_per_launch == 8
+        assert r.last_count == 7 and np.array_equal(t.cpu().numpy(), o)
