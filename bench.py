@@ -300,7 +300,7 @@ def run_life(args, L, I, torch):
     else:
         # fused generations are bound by the vector ALU: LIFE_OPS_PER_CELL 32-bit
         # lane operations per cell and generation against the chip's lane rate
-        kname, files = f"life_tb{spl}_{n}", ("life_tb.hip", "common.hpp")
+        kname, files = f"life_tb{spl}_{n}", ("life_tb.hip", "tile_life_tb.hpp", "tile_life.hpp", "common.hpp")
         achieved = n * n * spl * LIFE_OPS_PER_CELL / per_launch_s / 1e12
         out["roofline"] = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_VALU_TOPS,
                            "unit": "Tops/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
