@@ -212,47 +212,82 @@ __device__ void small_jacobi(const BatchJob& J, T* A, T* B, double* red_lds, int
 
 __device__ void small_life(const BatchJob& J, uint8_t* A, uint8_t* B, unsigned long long* red_lds,
                            int* flag) {
+    // LDS rows of small_life_words(cols) 32-bit words, one byte per cell: byte 3 of
+    // word 0 is a ghost copy of the row's last cell, bytes 4 .. cols + 3 are the
+    // cells, byte cols + 4 is a ghost copy of the first cell (torus; both ghosts 0
+    // on a dead border), every other byte 0. A thread takes one word (4 cells) of
+    // one row: column sums of the three rows, the two outer neighbours from the
+    // next words' edge bytes, and B3/S23 as (T - c | c) == 3 per byte, T the 3x3
+    // total. Bytes past the last cell are masked to 0 and the ghosts refreshed
+    // after every generation.
     const int tid = threadIdx.x;
-    const int64_t rows = J.rows, cols = J.cols, cells = rows * cols;
+    const int rows = (int)J.rows, cols = (int)J.cols;
+    const int wt = small_life_words(cols);   // words per LDS row
+    const int nw = (cols + 3) / 4;           // words holding cells: 1 .. nw
+    const int lastb = cols + 3;              // byte index of the last cell in a row
+    const bool torus = J.torus != 0;
+    uint32_t* A32 = reinterpret_cast<uint32_t*>(A);
+    uint32_t* B32 = reinterpret_cast<uint32_t*>(B);
     JobState s = *J.st;
     const uint8_t* src = static_cast<const uint8_t*>(J.buf[s.n & 1]);
-    for (int64_t k = tid; k < cells; k += kSmallThreads) {
-        const int64_t i = k / cols, jj = k - i * cols;
-        A[k] = src[i * J.pitch + jj];   // 0/1 after the job's initial count pass
+    for (int k = tid; k < 2 * rows * wt; k += kSmallThreads) A32[k] = 0;   // both buffers
+    __syncthreads();
+    for (int64_t k = tid; k < (int64_t)rows * cols; k += kSmallThreads) {
+        const int i = (int)(k / cols), jj = (int)(k - (int64_t)i * cols);
+        A[i * wt * 4 + 4 + jj] = src[i * J.pitch + jj];   // 0/1 after the job's initial count pass
     }
+    __syncthreads();
+    auto ghosts = [&](uint8_t* G) {
+        if (!torus) return;
+        for (int i = tid; i < rows; i += kSmallThreads) {
+            uint8_t* r = G + i * wt * 4;
+            const uint8_t first = r[4], last = r[lastb];
+            r[3] = last;
+            r[cols + 4] = first;
+        }
+    };
+    ghosts(A);
     __syncthreads();
     int64_t n = s.n;
     while (n < J.ctl.max_iter) {
         const int64_t n1 = n + 1;
         const bool check = is_check_sweep(n1, J.ctl);
-        unsigned long long cnt = 0;
-        // 32-bit cell indices: the grid fits in LDS
-        const int rows32 = (int)rows, cols32 = (int)cols, cells32 = (int)cells;
-        for (int k = tid; k < cells32; k += kSmallThreads) {
-            const int i = k / cols32, jj = k - i * cols32;
-            int nb = 0;
-#pragma unroll
-            for (int di = -1; di <= 1; ++di)
-#pragma unroll
-                for (int dj = -1; dj <= 1; ++dj) {
-                    if (di == 0 && dj == 0) continue;
-                    int r = i + di, c = jj + dj;
-                    if (J.torus) {
-                        r = r < 0 ? r + rows32 : r >= rows32 ? r - rows32 : r;
-                        c = c < 0 ? c + cols32 : c >= cols32 ? c - cols32 : c;
-                    } else if (r < 0 || r >= rows32 || c < 0 || c >= cols32) {
-                        continue;
-                    }
-                    nb += A[r * cols32 + c];
-                }
-            const uint8_t v = (nb == 3 || (A[k] && nb == 2)) ? 1 : 0;
-            B[k] = v;
-            cnt += v;
+        uint32_t cnt = 0;
+        for (int k = tid; k < rows * nw; k += kSmallThreads) {
+            const int i = k / nw, w = k - i * nw + 1;
+            const int iu = i > 0 ? i - 1 : (torus ? rows - 1 : -1);
+            const int id = i + 1 < rows ? i + 1 : (torus ? 0 : -1);
+            const uint32_t* c = A32 + i * wt + w;
+            uint32_t V0 = c[-1], V1 = c[0], V2 = c[1];
+            const uint32_t mid = V1;
+            if (iu >= 0) {
+                const uint32_t* u = A32 + iu * wt + w;
+                V0 += u[-1];
+                V1 += u[0];
+                V2 += u[1];
+            }
+            if (id >= 0) {
+                const uint32_t* d = A32 + id * wt + w;
+                V0 += d[-1];
+                V1 += d[0];
+                V2 += d[1];
+            }
+            // bytes hold column sums <= 3; the 3x3 totals <= 9 stay inside their bytes
+            const uint32_t T = ((V1 << 8) | (V0 >> 24)) + V1 + ((V1 >> 8) | (V2 << 24));
+            uint32_t out = zero_bytes_hi(((T - mid) | mid) ^ 0x03030303u) >> 7;
+            const int spare = 4 * w + 3 - lastb;   // bytes of this word past the last cell
+            if (spare > 0) out &= 0xFFFFFFFFu >> (8 * spare);
+            B32[i * wt + w] = out;
+            cnt += (uint32_t)__popc(out);
         }
+        __syncthreads();
+        ghosts(B);
         __syncthreads();
         uint8_t* t = A;
         A = B;
         B = t;
+        A32 = reinterpret_cast<uint32_t*>(A);
+        B32 = reinterpret_cast<uint32_t*>(B);
         n = n1;
         if (check) {
             const unsigned long long total = block_reduce_u64<kSmallWaves>(cnt, red_lds);
@@ -265,9 +300,9 @@ __device__ void small_life(const BatchJob& J, uint8_t* A, uint8_t* B, unsigned l
         }
     }
     uint8_t* dst = static_cast<uint8_t*>(const_cast<void*>(J.buf[n & 1]));
-    for (int64_t k = tid; k < cells; k += kSmallThreads) {
-        const int64_t i = k / cols, jj = k - i * cols;
-        dst[i * J.pitch + jj] = A[k];
+    for (int64_t k = tid; k < (int64_t)rows * cols; k += kSmallThreads) {
+        const int i = (int)(k / cols), jj = (int)(k - (int64_t)i * cols);
+        dst[i * J.pitch + jj] = A[i * wt * 4 + 4 + jj];
     }
     if (tid == 0) publish_state(J.st, J.mirror, s);
 }
@@ -291,7 +326,7 @@ __global__ __launch_bounds__(kSmallThreads) void batch_small_kernel(const BatchJ
         if (J.helm) small_jacobi<float, true>(J, A, A + cells, red_d, &flag);
         else small_jacobi<float, false>(J, A, A + cells, red_d, &flag);
     } else {
-        small_life(J, grid_lds, grid_lds + cells, red_u, &flag);
+        small_life(J, grid_lds, grid_lds + J.rows * small_life_words(J.cols) * 4, red_u, &flag);
     }
 }
 

@@ -150,7 +150,12 @@ constexpr int kBatchKinds = 15;
 // A grid runs whole-grid-in-LDS when both of its buffers fit in this many bytes
 // (rows * cols * element size * 2; one 1024-thread workgroup per job).
 constexpr int64_t kSmallLdsBytes = 160 * 1024 - 1024;
+// 32-bit words of one LDS row of a small Life grid: the cells from byte 4 on, a
+// ghost byte on either side, whole words up to one past the last cell's word.
+__host__ __device__ inline int64_t small_life_words(int64_t cols) { return (cols + 3) / 4 + 2; }
+// esz 1 is a Life grid (rows of small_life_words words).
 inline bool batch_small_fits(int64_t rows, int64_t cols, int esz) {
+    if (esz == 1) return rows * small_life_words(cols) * 4 * 2 <= kSmallLdsBytes;
     return rows * cols * (int64_t)esz * 2 <= kSmallLdsBytes;
 }
 

@@ -293,3 +293,34 @@ def test_fused_life_stop_inside_a_round(bctx):
         o, ro = O.life_run(a, bc=O.BC_BOTTOM, stable_window=window, max_iter=500)
         assert ro.n == stop and r.iterations == stop and r.sweeps_per_launch == 8
         assert r.last_count == 7 and np.array_equal(t.cpu().numpy(), o)
+
+
+SMALL_LIFE = [(1, 1), (1, 7), (2, 2), (3, 3), (5, 1), (7, 131), (64, 99), (33, 250), (250, 33),
+              (200, 203), (280, 280)]
+
+
+def test_small_life_grids_in_lds_match_oracle(bctx):
+    """Life grids whose two buffers fit in LDS run their whole loop in one workgroup
+    (one 32-bit word of 4 cells per thread, ghost bytes for the torus wrap): every
+    width modulo 4, single rows and columns, both borders, equal to the oracle in
+    field, stop generation and count."""
+    import torch
+    say("batched small life shapes")
+    cases = []
+    for k, (rows, cols) in enumerate(SMALL_LIFE):
+        for torus in (True, False):
+            a = I.life_input(rows, cols, seed=rows * 1000 + cols, density=0.4)
+            t = torch.from_numpy(a).to("cuda:0")
+            jid = bctx.submit(t, L.LSR_ST_LIFE, L.LSR_RED_SUM,
+                              L.make_cond(L.LSR_COND_STABLE_FOR, 0.0, 1 + k % 3, 10), 300,
+                              L.LSR_BC_TORUS if torus else L.LSR_BC_BOTTOM)
+            cases.append((rows, cols, torus, 1 + k % 3, a, t, jid))
+    for rows, cols, torus, every, a, t, jid in cases:
+        r = bctx.result(jid)
+        torch.cuda.synchronize()
+        o, ro = O.life_run(a, bc=O.BC_TORUS if torus else O.BC_BOTTOM, stable_window=10,
+                           check_every=every, max_iter=300)
+        name = (rows, cols, torus, every)
+        assert r.status == L.LSR_OK, name
+        assert r.iterations == ro.n and r.last_count == ro.count, (name, r.iterations, ro.n)
+        assert np.array_equal(t.cpu().numpy(), o), name

@@ -580,3 +580,80 @@ def test_life_tb_stores_tile_the_grid_at_full_size(rows, cols, tile_rows):
     for band in range(bands):
         row_cover[band * tile_rows:min(rows, band * tile_rows + tile_rows)] += 1
     assert (row_cover == 1).all()
+
+
+# ---------------------------------------------------------------------------
+# Small Life grids in LDS (batch_small_kernel, Life): rows of (cols + 3) // 4 + 2
+# 32-bit words, byte 3 of word 0 and byte cols + 4 ghost copies of the row's last
+# and first cells (torus; 0 on a dead border), cells at bytes 4 .. cols + 3. One
+# thread per word 1 .. (cols + 3) // 4 of a row: column sums of three rows over
+# words w-1 .. w+1, B3/S23 per byte, bytes past the last cell masked off. The
+# model replays the word arithmetic with Python integers, checks every LDS index
+# against the two buffers and compares generations with the oracle.
+# ---------------------------------------------------------------------------
+
+def _zero_bytes_hi(x):
+    return ~(x + 0x7F7F7F7F) & 0x80808080 & 0xFFFFFFFF
+
+
+def _small_life_model(a, torus, gens):
+    rows, cols = a.shape
+    wt = (cols + 3) // 4 + 2
+    nw = (cols + 3) // 4
+    lastb = cols + 3
+    size = rows * wt * 4
+    A = bytearray(size)
+    for i in range(rows):
+        A[i * wt * 4 + 4:i * wt * 4 + 4 + cols] = bytes(a[i])
+
+    def ghosts(G):
+        if torus:
+            for i in range(rows):
+                r = i * wt * 4
+                assert r + cols + 4 < size
+                first, last = G[r + 4], G[r + lastb]
+                G[r + 3] = last
+                G[r + cols + 4] = first
+
+    def word(G, idx):
+        assert 0 <= idx < rows * wt
+        return int.from_bytes(G[4 * idx:4 * idx + 4], "little")
+
+    ghosts(A)
+    for _ in range(gens):
+        B = bytearray(size)
+        for i in range(rows):
+            iu = i - 1 if i > 0 else (rows - 1 if torus else -1)
+            idn = i + 1 if i + 1 < rows else (0 if torus else -1)
+            for w in range(1, nw + 1):
+                V = [word(A, i * wt + w + d) for d in (-1, 0, 1)]
+                mid = V[1]
+                for rr in (iu, idn):
+                    if rr >= 0:
+                        V = [v + word(A, rr * wt + w + d) for v, d in zip(V, (-1, 0, 1))]
+                V0, V1, V2 = V
+                T = ((((V1 << 8) & 0xFFFFFFFF) | (V0 >> 24)) + V1
+                     + ((V1 >> 8) | ((V2 << 24) & 0xFFFFFFFF))) & 0xFFFFFFFF
+                out = _zero_bytes_hi((((T - mid) & 0xFFFFFFFF) | mid) ^ 0x03030303) >> 7
+                spare = 4 * w + 3 - lastb
+                if spare > 0:
+                    out &= 0xFFFFFFFF >> (8 * spare)
+                B[4 * (i * wt + w):4 * (i * wt + w) + 4] = out.to_bytes(4, "little")
+        ghosts(B)
+        A = B
+    return np.array([[A[i * wt * 4 + 4 + j] for j in range(cols)] for i in range(rows)],
+                    dtype=np.uint8)
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 1), (1, 6), (2, 2), (3, 5), (6, 1), (7, 13), (9, 16),
+                                       (11, 22), (5, 31)])
+@pytest.mark.parametrize("torus", [True, False])
+def test_small_life_lds_model_matches_oracle(rows, cols, torus):
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    a = I.life_input(rows, cols, seed=rows * 100 + cols, density=0.45)
+    gens = 6
+    got = _small_life_model(a, torus, gens)
+    o, _ = O.life_run(a, bc=O.BC_TORUS if torus else O.BC_BOTTOM, cond=O.COND_NEVER,
+                      max_iter=gens)
+    assert np.array_equal(got, o)
