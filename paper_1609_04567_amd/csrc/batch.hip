@@ -169,23 +169,26 @@ __device__ void small_jacobi(const BatchJob& J, T* A, T* B, double* red_lds, int
     __syncthreads();
     const T* g = static_cast<const T*>(J.env);
     const T rd = (T)J.rd, rd_lo = (T)(0.25 - J.rd);
-    // the grid fits in LDS, so cell indices fit in 32 bits (a 64-bit division per
-    // cell cost more than the update)
-    const int cols32 = (int)cols, icols = cols32 - 2, inner = ((int)rows - 2) * icols;
+    // the grid fits in LDS, so cell indices fit in 32 bits. Wavefront w takes
+    // interior rows 1 + w, 1 + w + 16, ..., its lanes consecutive columns (no
+    // division per cell; a narrow grid's rows still spread over the wavefronts).
+    const int cols32 = (int)cols, rows32 = (int)rows;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     int64_t n = s.n;
     while (n < J.ctl.max_iter) {
         const int64_t n1 = n + 1;
         const bool check = is_check_sweep(n1, J.ctl);
         double acc = 0.0;
-        for (int k = tid; k < inner; k += kSmallThreads) {
-            const int q = k / icols;
-            const int i = 1 + q, jj = 1 + (k - q * icols);
-            const int c = i * cols32 + jj;
-            const T v = jacobi_update<T, HELM>(A[c - cols32], A[c + cols32], A[c - 1], A[c + 1],
-                                               HELM ? g[(int64_t)i * J.pitch + jj] : T(0), rd, rd_lo,
-                                               (int64_t)i, (int64_t)jj, (uint32_t)n1);
-            if (check) acc = jacobi_accum(J.ctl.reduce, acc, (double)v - (double)A[c]);
-            B[c] = v;
+        for (int i = 1 + wave; i < rows32 - 1; i += kSmallWaves) {
+            const T* grow = HELM ? g + (int64_t)i * J.pitch : nullptr;
+            for (int jj = 1 + lane; jj < cols32 - 1; jj += 64) {
+                const int c = i * cols32 + jj;
+                const T v = jacobi_update<T, HELM>(A[c - cols32], A[c + cols32], A[c - 1], A[c + 1],
+                                                   HELM ? grow[jj] : T(0), rd, rd_lo, (int64_t)i,
+                                                   (int64_t)jj, (uint32_t)n1);
+                if (check) acc = jacobi_accum(J.ctl.reduce, acc, (double)v - (double)A[c]);
+                B[c] = v;
+            }
         }
         __syncthreads();
         T* t = A;
