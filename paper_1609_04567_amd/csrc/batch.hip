@@ -106,8 +106,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
         uint8_t* b = static_cast<uint8_t*>(dst);
         if (J.torus)
             life_tb_band<STEP, 3, true>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
-        else
+        else if (J.cols % 16 == 0)
             life_tb_band<STEP, 3, false>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
+        else
+            life_tb_band<STEP, 3, false, true>(a, b, J.rows, J.cols, J.pitch, mask, band, strip,
+                                               J.tile_rows, cnt);
         auto* parts = static_cast<unsigned long long*>(J.partials);
 #pragma unroll
         for (int l = 0; l < STEP; ++l) {
@@ -388,8 +391,8 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_
         j.tiles = 1;   // one work item = the whole job; no partials
         return;
     }
-    if (is_life && j.cols % 16 == 0 && want_depth != 1) {
-        // rows are 16-byte aligned and hold no padding cells
+    if (is_life && (j.cols % 16 == 0 || !j.torus) && want_depth != 1) {
+        // rows are 16-byte aligned; a dead border's rows may end in zeroed padding
         j.kind = BK_LIFE_TB8;
         j.step = KindInfo<BK_LIFE_TB8>::step;
         j.mc = 1;

@@ -64,11 +64,15 @@ __device__ __forceinline__ void life_rule16(const uint32_t (&V)[4], const uint32
 // and band `band` (tile_rows rows, the last one shorter). Loads generation n,
 // stores generation n + K, and adds the live cells it owns of every checked
 // generation n + l (check_mask bit l - 1) to the lane's cnt[l - 1].
-template <int K, int U, bool TORUS>
+// RAGGED (dead border only): rows hold round_up(cols, 16) bytes, the bytes past
+// cols zero; the lane holding the last cell masks the bytes past it at every
+// level, so they stay dead, are never counted and are stored as zero.
+template <int K, int U, bool TORUS, bool RAGGED = false>
 __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
                                              int64_t rows, int64_t cols, int64_t pitch, uint32_t mask,
                                              int band, int strip, int tile_rows, uint32_t (&cnt)[K]) {
     static_assert(K >= 2 && K <= 16, "halo lanes cover at most 16 generations");
+    static_assert(!(TORUS && RAGGED), "a torus wraps at a 16-cell boundary");
     using namespace life_tb_detail;
     const int lane = threadIdx.x & 63;
     const int64_t col_raw = (int64_t)strip * kLifeTbWinCols - 16 + (int64_t)lane * 16;
@@ -81,6 +85,12 @@ __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
     const bool loads = TORUS || in_cols;
     const uint32_t own = (lane >= 1 && lane <= kLifeTbWinLanes && col_raw < cols) ? 0xFFFFFFFFu : 0u;
     const uint32_t live = loads ? 0xFFFFFFFFu : 0u;   // dead columns of a dead border
+    uint32_t cmask[4];   // RAGGED: bytes of the lane's word m that hold cells
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int64_t in = cols - col_raw - 4 * m;   // cells of word m inside the grid
+        cmask[m] = !RAGGED || in >= 4 ? live : in <= 0 ? 0u : live >> (8 * (4 - (int)in));
+    }
     const int64_t r0 = (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows);
     const int64_t i_beg = r0 - K, i_end = r1 + K;
@@ -133,7 +143,11 @@ __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
 #pragma unroll
             for (int m = 0; m < 4; ++m) V[m] = src[PU][m] + src[PM][m] + src[P][m];
             life_rule16(V, src[PM], out);
-            if (!TORUS) {
+            if (RAGGED) {
+                const bool in_rows = row >= 0 && row < rows;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) out[m] &= in_rows ? cmask[m] : 0u;
+            } else if (!TORUS) {
                 const uint32_t lv = (row >= 0 && row < rows) ? live : 0u;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) out[m] &= lv;

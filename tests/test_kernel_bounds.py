@@ -448,11 +448,15 @@ def _c_rem(x, m):
     return np.where(r < 0, r + m, r)
 
 
-def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=None):
+def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=None, ragged=False):
+    """ragged: a dead border whose rows (buf's width, a multiple of 16) end in zero
+    padding past cols."""
     lead = k if lead is None else lead   # rows streamed before and after the band
     words = buf.view(np.uint32)
+    width = buf.shape[1]                  # bytes a row holds
+    assert ragged or width == cols
     out = np.zeros_like(buf)
-    writes = np.zeros((rows, cols), np.int32)
+    writes = np.zeros((rows, width), np.int32)
     bad = []
     strips = -(-cols // LIFE_TB_WIN)
     bands = -(-rows // tile_rows)
@@ -473,6 +477,10 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
             loads = in_cols | bool(torus)
             own = (lanes >= 1) & (lanes <= 62) & (col_raw < cols)
             live = np.where(loads, np.uint32(0xFFFFFFFF), np.uint32(0))[:, None]
+            inside = cols - col_raw[:, None] - 4 * np.arange(4)[None, :]   # cells of word m
+            cmask = np.where(inside >= 4, live, np.where(
+                inside <= 0, np.uint32(0),
+                live >> (np.uint32(8) * (4 - np.clip(inside, 1, 3)).astype(np.uint32)))).astype(np.uint32)
             r0, r1 = band * tile_rows, min(band * tile_rows + tile_rows, rows)
 
             def load(r):
@@ -483,7 +491,7 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
                 W = np.zeros((64, 4), np.uint32)
                 for ln in np.nonzero(loads)[0]:
                     c = int(col[ln])
-                    if not (0 <= r < rows and 0 <= c and c + 16 <= cols and c % 16 == 0):
+                    if not (0 <= r < rows and 0 <= c and c + 16 <= width and c % 16 == 0):
                         bad.append(("load", t, w, ln, r, c))
                         continue
                     W[ln] = words[r, c // 4:c // 4 + 4]
@@ -507,7 +515,10 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
                         c = mid[lv - 1][:, m]
                         o[:, m] = _zero_bytes_hi(((T - c) | c) ^ np.uint32(0x03030303)) >> np.uint32(7)
                     in_rows = 0 <= row < rows
-                    o &= live if (torus or in_rows) else np.uint32(0)
+                    if ragged:
+                        o &= cmask if in_rows else np.uint32(0)
+                    else:
+                        o &= live if (torus or in_rows) else np.uint32(0)
                     if (check_mask >> (lv - 1)) & 1 and r0 <= row < r1:
                         counts[lv - 1] += int(np.unpackbits(o[own].view(np.uint8)).sum())
                     up[lv - 1] = mid[lv - 1]
@@ -517,7 +528,7 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
                 if r0 <= row < r1:
                     for ln in np.nonzero(own)[0]:
                         c = int(col_raw[ln])
-                        if not (0 <= c and c + 16 <= cols):
+                        if not (0 <= c and c + 16 <= width):
                             bad.append(("store", t, w, ln, row, c))
                             continue
                         out[row, c:c + 16] = cur[ln].view(np.uint8)
@@ -542,6 +553,31 @@ def test_life_tb_model_matches_oracle(rows, cols, k, tile_rows, torus):
     assert np.array_equal(out, o)
     for lv in range(1, k + 1):
         _, ro = O.life_run(a, bc=bc, cond=O.COND_NEVER, max_iter=lv)
+        assert counts[lv - 1] == ro.count, lv
+
+
+@pytest.mark.parametrize("rows,cols,k,tile_rows", [
+    (1, 5, 2, 64), (3, 17, 3, 2), (7, 31, 8, 4), (20, 1000, 4, 16), (13, 999, 8, 5),
+    (9, 1009, 5, 3), (6, 2001, 6, 8)])
+def test_life_tb_ragged_dead_border_model_matches_oracle(rows, cols, k, tile_rows):
+    """Dead border, rows not a multiple of 16 cells (the batched fused family): the
+    cells past cols stay dead at every level, are stored as zero and never counted;
+    every access stays inside the padded rows."""
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    a = I.life_input(rows, cols, seed=rows * 11 + cols + k)
+    width = -(-cols // 16) * 16
+    buf = np.zeros((rows, width), np.uint8)
+    buf[:, :cols] = a
+    out, counts, writes, bad = _life_tb_launch(buf, rows, cols, False, k, tile_rows, 4,
+                                               (1 << k) - 1, ragged=True)
+    assert bad == []
+    assert (writes == 1).all()            # padding bytes are stored too, as zero
+    assert not out[:, cols:].any()
+    o, _ = O.life_run(a, bc=O.BC_BOTTOM, cond=O.COND_NEVER, max_iter=k)
+    assert np.array_equal(out[:, :cols], o)
+    for lv in range(1, k + 1):
+        _, ro = O.life_run(a, bc=O.BC_BOTTOM, cond=O.COND_NEVER, max_iter=lv)
         assert counts[lv - 1] == ro.count, lv
 
 
