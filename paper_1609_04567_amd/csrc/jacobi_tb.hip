@@ -19,7 +19,7 @@ namespace {
 // pipeline needs about 174, and the compiler fits it in 168 with a few values
 // spilled, which the third wavefront repays (8192^2 Helmholtz +10 %).
 template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP = false,
-          bool VERT = false>
+          bool VERT = false, int RED = -1>
 __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_kernel(
     const T* __restrict__ a, T* __restrict__ b, const T* __restrict__ g, int64_t rows,
     int64_t cols, int64_t pitch, T rd, T rd_lo, JobState* __restrict__ st,
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 8 ? 3 : 1) void jacobi5_tb_ke
     if (t >= tiles) return;
     // FP64: g rows read two levels ahead (8192^2 Helmholtz, depth 10: +1.5 %)
     jacobi5_tb_tile<T, HELM, VEC, NW, K, true, HELM && !SEP, false, MC, SEP, VERT,
-                    sizeof(T) == 8 ? 2 : 0>(
+                    sizeof(T) == 8 ? 2 : 0, RED>(
         a, b, g, rows, cols, pitch, rd, rd_lo, (uint32_t)n1, mask, ctl.reduce, t, strips, tiles,
         tile_rows, partials, lds, gring, sep);
 }
@@ -63,10 +63,18 @@ constexpr int64_t kMinTiles = 1024;
 // bands streamed upwards (8192^2 FP64 Helmholtz: depth 10 +1-2 %, depth 5 +3 %).
 constexpr bool kVertical = true;
 
-template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP, bool VERT>
+template <typename T, bool HELM, int VEC, int NW, int K, bool MC, bool SEP, bool VERT, int RED = -1>
 hipError_t launch_v(const JacobiArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
-    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC, SEP, VERT>), dim3(g.blocks),
+    // the L2 reduce (the Helmholtz checks) of two-wavefront vertical launches at
+    // depths 5 and 10 has its own kernels: 60 of the ~620 vector instructions of a
+    // depth-10 loop iteration were selects between the reduce kinds
+    constexpr bool kL2Own = RED < 0 && NW == 2 && VERT && !MC && !SEP && (K == 5 || K == 10);
+    if constexpr (kL2Own) {
+        if (c.reduce == RED_L2)
+            return launch_v<T, HELM, VEC, NW, K, MC, SEP, VERT, RED_L2>(a, g, st, partials, c, j, s);
+    }
+    hipLaunchKernelGGL((jacobi5_tb_kernel<T, HELM, VEC, NW, K, MC, SEP, VERT, RED>), dim3(g.blocks),
                        dim3(NW * 64), 0, s, static_cast<const T*>(a.a), static_cast<T*>(a.b),
                        static_cast<const T*>(a.g), a.rows, a.cols, a.pitch, T(a.rd),
                        T(0.25 - a.rd), st, static_cast<double*>(partials), c, j, g.strips,

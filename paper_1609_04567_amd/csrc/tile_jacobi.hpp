@@ -315,16 +315,19 @@ constexpr int tb_gring_elems() { return NW * K * 64 * VEC; }
 // -2 % at 8, +10 % at 32, where a chunk's windows no longer run together).
 constexpr int kTbChunk = 8;
 
+// RED >= 0: the reduce op is that constant (red is ignored), so the delta sums
+// carry no selects between the reduce kinds.
 template <typename T, bool HELM, int VEC, int NW, int K, bool NT, bool NTG, bool WT = false,
-          bool MC = false, bool SEP = false, bool VERT = false, int GA = 0>
+          bool MC = false, bool SEP = false, bool VERT = false, int GA = 0, int RED = -1>
 __device__ __forceinline__ void jacobi5_tb_tile(const T* __restrict__ a, T* __restrict__ b,
                                                 const T* __restrict__ g, int64_t rows,
                                                 int64_t cols, int64_t pitch, T rd, T rd_lo,
-                                                uint32_t sweep0, uint32_t check_mask, int red,
+                                                uint32_t sweep0, uint32_t check_mask, int red_arg,
                                                 int t, int strips, int tiles, int tile_rows,
                                                 double* __restrict__ partials, double* lds,
                                                 T* gring, SepSource sep = SepSource{}) {
     constexpr bool GRING = HELM && !SEP;   // g rows stream through the LDS ring
+    const int red = RED >= 0 ? RED : red_arg;
     static_assert(!WT || NW == 1, "a wavefront tile has one wavefront");
     typedef T V __attribute__((ext_vector_type(VEC)));
     constexpr int OW = tb_out_width<VEC, K>();
