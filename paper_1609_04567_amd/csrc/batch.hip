@@ -38,14 +38,27 @@ __device__ __forceinline__ void jac_tb_tile(const BatchJob& J, const void* src, 
     T* b = static_cast<T*>(dst);
     const T* g = static_cast<const T*>(J.env);
     double* parts = static_cast<double*>(J.partials);
-    if (J.helm)
-        jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true, MC>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, mask,
-            J.ctl.reduce, t, J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
-    else
-        jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true, MC>(
-            a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, mask, J.ctl.reduce, t,
-            J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
+    // each stencil's usual reduce (Helmholtz L2, Laplace max |delta|) compiled in,
+    // so the per-level delta sums carry no selects between the reduce kinds
+    if (J.helm) {
+        if (J.ctl.reduce == RED_L2)
+            jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true, MC, false, false, 0, RED_L2>(
+                a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, mask,
+                J.ctl.reduce, t, J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
+        else
+            jacobi5_tb_tile<T, true, VEC, 1, K, true, true, true, MC>(
+                a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)(0.25 - J.rd), sweep0, mask,
+                J.ctl.reduce, t, J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
+    } else {
+        if (J.ctl.reduce == RED_MAX_ABS)
+            jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true, MC, false, false, 0, RED_MAX_ABS>(
+                a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, mask, J.ctl.reduce, t,
+                J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
+        else
+            jacobi5_tb_tile<T, false, VEC, 1, K, true, false, true, MC>(
+                a, b, g, J.rows, J.cols, J.pitch, (T)J.rd, (T)0, sweep0, mask, J.ctl.reduce, t,
+                J.strips, J.tiles, J.tile_rows, parts, nullptr, gring);
+    }
 }
 
 // Per family: sweeps per round, element type width (0 = Life), and whether a
