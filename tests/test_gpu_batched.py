@@ -328,3 +328,36 @@ def test_small_life_grids_in_lds_match_oracle(bctx):
         assert r.status == L.LSR_OK, name
         assert r.iterations == ro.n and r.last_count == ro.count, (name, r.iterations, ro.n)
         assert np.array_equal(t.cpu().numpy(), o), name
+
+
+@pytest.mark.parametrize("f32", [True, False])
+def test_reduce_kind_leaves_the_field_unchanged(f32):
+    """The tiles with a job's usual reduce compiled in (Helmholtz L2, Laplace max
+    |delta|) and the general tile (any other reduce) compute the same field bit for
+    bit, on a batched context (depth 5, checks inside the rounds for Laplace) and on
+    a plain one (two-wavefront launches at depths 5 and 10)."""
+    import torch
+    say(f"reduce kinds, same field f32={f32}")
+    dt = torch.float32 if f32 else torch.float64
+    h = I.helmholtz_input(300)
+    lap = I.laplace_input(300, seed=4)
+    cases = [(L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, 10), (L.LSR_ST_HELMHOLTZ5, L.LSR_RED_MAX_ABS_DELTA, 10),
+             (L.LSR_ST_LAPLACE5, L.LSR_RED_MAX_ABS_DELTA, 1), (L.LSR_ST_LAPLACE5, L.LSR_RED_L2_DELTA, 1),
+             (L.LSR_ST_HELMHOLTZ5, L.LSR_RED_L2_DELTA, 1), (L.LSR_ST_HELMHOLTZ5, L.LSR_RED_MAX_ABS_DELTA, 1)]
+    fields = {}
+    for batched in (True, False):
+        with L.Context(0, batched=batched) as c:
+            for st, red, every in cases:
+                helm = st == L.LSR_ST_HELMHOLTZ5
+                t = torch.from_numpy(h.u0 if helm else lap).to("cuda:0").to(dt)
+                g = torch.from_numpy(h.g).to("cuda:0").to(dt) if helm else None
+                r = c.run(t, st, red, L.make_cond(L.LSR_COND_NEVER, 0.0, every), 200, L.LSR_BC_RING,
+                          env0=g, param=(h.alpha, h.h) if helm else ())
+                torch.cuda.synchronize()
+                assert r.status == L.LSR_OK and r.iterations == 200
+                fields[(batched, st, red, every)] = t.cpu().numpy()
+    for batched in (True, False):
+        for st, every in ((L.LSR_ST_HELMHOLTZ5, 10), (L.LSR_ST_LAPLACE5, 1), (L.LSR_ST_HELMHOLTZ5, 1)):
+            a = fields[(batched, st, L.LSR_RED_L2_DELTA, every)]
+            b = fields[(batched, st, L.LSR_RED_MAX_ABS_DELTA, every)]
+            assert np.array_equal(a, b), (batched, st, every)
