@@ -185,9 +185,8 @@ typedef struct {
                                unfused. Fields and counts are bit for bit those of unfused
                                sweeps; a float reduce value differs at most in the order of
                                its partial sums. Restoration is never fused. A batched context
-                               takes the depth (FP64 10, 5 or 2; FP32 5 or 2; Life 8 on a
-                               dead border, or on a torus whose rows hold a multiple of 16
-                               cells, 1 = one generation per round) and tile_rows from the
+                               takes the depth (FP64 10, 5 or 2; FP32 5 or 2; Life 8 at any
+                               width, 1 = one generation per round) and tile_rows from the
                                same overrides or tuning table. */
     int32_t chunk;          /* sweeps per enqueued chunk (a multiple of check_every) */
     int32_t use_graph;      /* 1 = replay chunks as HIP graphs, -1 = plain launches */

@@ -57,9 +57,8 @@ std::vector<lsr_tuning> candidates(int stencil) {
 // Candidates on a batched context: the engine's families take the fused depth
 // (Jacobi: FP32 5 or 2, FP64 10, 5 or 2, kept only where it divides the check
 // period; otherwise depth 5 with checks inside) and the band rows of a wavefront
-// tile (Life: one generation per round, the SWAR tile, or 8, the fused tile of
-// dead borders and of tori whose rows hold a multiple of 16 cells, each with its
-// band rows).
+// tile (Life: one generation per round, the SWAR tile, or 8, the fused tile,
+// each with its band rows).
 std::vector<lsr_tuning> candidates_batched(int stencil, int dtype, int check_every) {
     std::vector<lsr_tuning> out;
     auto add = [&](int tile_rows, int depth) {

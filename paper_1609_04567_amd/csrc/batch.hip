@@ -117,8 +117,11 @@ __global__ __launch_bounds__(kBatchThreads) void batch_sweep_kernel(const BatchJ
         for (int l = 0; l < STEP; ++l) cnt[l] = 0;
         const uint8_t* a = static_cast<const uint8_t*>(src);
         uint8_t* b = static_cast<uint8_t*>(dst);
-        if (J.torus)
+        if (J.torus && J.cols % 16 == 0)
             life_tb_band<STEP, 3, true>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
+        else if (J.torus)
+            life_tb_band<STEP, 3, true, true>(a, b, J.rows, J.cols, J.pitch, mask, band, strip,
+                                              J.tile_rows, cnt);
         else if (J.cols % 16 == 0)
             life_tb_band<STEP, 3, false>(a, b, J.rows, J.cols, J.pitch, mask, band, strip, J.tile_rows, cnt);
         else
@@ -404,8 +407,8 @@ void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth, int want_
         j.tiles = 1;   // one work item = the whole job; no partials
         return;
     }
-    if (is_life && (j.cols % 16 == 0 || !j.torus) && want_depth != 1) {
-        // rows are 16-byte aligned; a dead border's rows may end in zeroed padding
+    if (is_life && want_depth != 1) {
+        // rows are 16-byte aligned and may end in padding (zeroed at the start)
         j.kind = BK_LIFE_TB8;
         j.step = KindInfo<BK_LIFE_TB8>::step;
         j.mc = 1;

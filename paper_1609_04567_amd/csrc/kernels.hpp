@@ -194,10 +194,9 @@ struct WorkItem {
 // cap, else the deepest such depth, else depth 5 with checks inside (also
 // chosen by want_depth = 5); want_tile_rows > 0 sets the band height. The
 // wanted values come from the context's tuning table, so the geometry is still
-// a function of the job's own key. A Life job on a dead border, or on a torus
-// whose rows hold a multiple of 16 cells, runs 8 generations per round (one band
-// of one 992-column window per wavefront, tile_life_tb.hpp) unless want_depth
-// is 1; other Life jobs one generation per round. j.torus must be set.
+// a function of the job's own key. A Life job runs 8 generations per round (one
+// band of one 992-column window per wavefront, tile_life_tb.hpp) unless
+// want_depth is 1 (one generation per round). j.torus must be set.
 void batch_geometry(BatchJob& j, int is_life, int f32, int want_depth = 0, int want_tile_rows = 0);
 // The same for a restoration job: one tile = 16 rows x 64 columns (one wavefront),
 // one sweep per round; never whole-grid-in-LDS.

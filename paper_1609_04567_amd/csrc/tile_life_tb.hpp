@@ -64,32 +64,41 @@ __device__ __forceinline__ void life_rule16(const uint32_t (&V)[4], const uint32
 // and band `band` (tile_rows rows, the last one shorter). Loads generation n,
 // stores generation n + K, and adds the live cells it owns of every checked
 // generation n + l (check_mask bit l - 1) to the lane's cnt[l - 1].
-// RAGGED (dead border only): rows hold round_up(cols, 16) bytes, the bytes past
-// cols zero; the lane holding the last cell masks the bytes past it at every
-// level, so they stay dead, are never counted and are stored as zero.
+// RAGGED: rows hold round_up(cols, 16) bytes and cols need not be a multiple of
+// 16. On a dead border the bytes past cols start at zero and the lane holding the
+// last cell masks them at every level, so they stay dead, are never counted and
+// are stored as zero. On a torus, lanes whose 16 cells lie inside the row load
+// them as a word; the lane holding the row's end, the lane after it and the left
+// halo lane of the first window gather their cells byte by byte from the wrapped
+// columns (a row read as its periodic extension); lanes further out load nothing,
+// as no cell they feed lies within K of a stored one. The bytes past cols of the
+// last lane are counted out, and stored into the padding (0 or 1, never read).
 template <int K, int U, bool TORUS, bool RAGGED = false>
 __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
                                              int64_t rows, int64_t cols, int64_t pitch, uint32_t mask,
                                              int band, int strip, int tile_rows, uint32_t (&cnt)[K]) {
     static_assert(K >= 2 && K <= 16, "halo lanes cover at most 16 generations");
-    static_assert(!(TORUS && RAGGED), "a torus wraps at a 16-cell boundary");
     using namespace life_tb_detail;
     const int lane = threadIdx.x & 63;
     const int64_t col_raw = (int64_t)strip * kLifeTbWinCols - 16 + (int64_t)lane * 16;
     const bool in_cols = col_raw >= 0 && col_raw < cols;
     int64_t col = col_raw;
-    if (TORUS && !in_cols) {
+    if (TORUS && !RAGGED && !in_cols) {
         col %= cols;
         if (col < 0) col += cols;
     }
-    const bool loads = TORUS || in_cols;
+    constexpr bool RT = TORUS && RAGGED;
+    const bool inside = col_raw >= 0 && col_raw + 16 <= cols;
+    const bool gather = RT && !inside && col_raw >= -16 && col_raw < cols + 16;
+    const bool loads = RT ? inside : TORUS || in_cols;
     const uint32_t own = (lane >= 1 && lane <= kLifeTbWinLanes && col_raw < cols) ? 0xFFFFFFFFu : 0u;
     const uint32_t live = loads ? 0xFFFFFFFFu : 0u;   // dead columns of a dead border
     uint32_t cmask[4];   // RAGGED: bytes of the lane's word m that hold cells
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int64_t in = cols - col_raw - 4 * m;   // cells of word m inside the grid
-        cmask[m] = !RAGGED || in >= 4 ? live : in <= 0 ? 0u : live >> (8 * (4 - (int)in));
+        const uint32_t full = RT ? 0xFFFFFFFFu : live;
+        cmask[m] = !RAGGED || in >= 4 ? full : in <= 0 ? 0u : full >> (8 * (4 - (int)in));
     }
     const int64_t r0 = (int64_t)band * tile_rows;
     const int64_t r1 = min(r0 + (int64_t)tile_rows, rows);
@@ -106,6 +115,17 @@ __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
                 if (!TORUS) continue;
                 r %= rows;
                 if (r < 0) r += rows;
+            }
+            if (RT && gather) {
+                const uint8_t* row = a + r * pitch;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    int64_t cc = col_raw + q;   // in [-16, cols + 31)
+                    while (cc < 0) cc += cols;
+                    while (cc >= cols) cc -= cols;
+                    w[k][q >> 2] |= (uint32_t)row[cc] << (8 * (q & 3));
+                }
+                continue;
             }
             if (!loads) continue;
             const uint4 x = *reinterpret_cast<const uint4*>(a + r * pitch + col);
@@ -143,7 +163,7 @@ __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
 #pragma unroll
             for (int m = 0; m < 4; ++m) V[m] = src[PU][m] + src[PM][m] + src[P][m];
             life_rule16(V, src[PM], out);
-            if (RAGGED) {
+            if (RAGGED && !TORUS) {
                 const bool in_rows = row >= 0 && row < rows;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) out[m] &= in_rows ? cmask[m] : 0u;
@@ -153,8 +173,10 @@ __device__ __forceinline__ void life_tb_band(const uint8_t* a, uint8_t* b,
                 for (int m = 0; m < 4; ++m) out[m] &= lv;
             }
             if (((mask >> (l - 1)) & 1u) && row >= r0 && row < r1)
-                cnt[l - 1] += (uint32_t)(__popc(out[0]) + __popc(out[1]) + __popc(out[2]) +
-                                         __popc(out[3])) & own;
+                cnt[l - 1] += (uint32_t)(__popc(RT ? out[0] & cmask[0] : out[0]) +
+                                         __popc(RT ? out[1] & cmask[1] : out[1]) +
+                                         __popc(RT ? out[2] & cmask[2] : out[2]) +
+                                         __popc(RT ? out[3] & cmask[3] : out[3])) & own;
             if (l < K) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) R[l][P][m] = out[m];

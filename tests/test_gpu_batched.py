@@ -237,9 +237,10 @@ def test_stops_inside_rounds_are_replayed(bctx):
         assert abs(r.last_reduce - ro.r) <= 1e-12 * ro.r
 
 
-# (rows, cols, torus, cond, check_every, max_iter): dead borders and tori whose rows
-# hold a multiple of 16 cells take the fused family (8 generations per round),
-# other tori one generation per round
+# (rows, cols, torus, cond, check_every, max_iter): every large Life job takes the
+# fused family (8 generations per round), also rows that do not hold a multiple of
+# 16 cells (dead border: masked padding; torus: edge lanes gathered from the
+# wrapped columns)
 FUSED_LIFE = [(320, 512, True, L.LSR_COND_STABLE_FOR, 1, 700),
               (300, 1000, False, L.LSR_COND_STABLE_FOR, 1, 700),   # rows end in padding
               (130, 3003, False, L.LSR_COND_NEVER, 1, 61),
@@ -248,15 +249,18 @@ FUSED_LIFE = [(320, 512, True, L.LSR_COND_STABLE_FOR, 1, 700),
               (257, 2000, True, L.LSR_COND_STABLE_FOR, 3, 400),
               (200, 1984, False, L.LSR_COND_NEVER, 1, 123),        # cap inside a round
               (333, 496, True, L.LSR_COND_NEVER, 5, 61),
-              (300, 500, True, L.LSR_COND_STABLE_FOR, 1, 300)]     # torus, not a multiple of 16
+              (300, 500, True, L.LSR_COND_STABLE_FOR, 1, 300),     # torus, not a multiple of 16
+              (257, 1000, True, L.LSR_COND_STABLE_FOR, 3, 400),
+              (600, 301, True, L.LSR_COND_NEVER, 1, 77),
+              (130, 2001, True, L.LSR_COND_STABLE_FOR, 1, 500),
+              (2000, 131, True, L.LSR_COND_NEVER, 2, 100)]
 
 
 def test_fused_life_rounds_match_oracle(bctx):
     """Life jobs on the fused batched family (8 generations per round, counts of
     every checked generation inside a round, a stop inside a round replayed one
     generation at a time) equal the oracle bit for bit: field, stop generation and
-    live count, also dead borders whose rows end in padding; a torus whose width is
-    not a multiple of 16 cells runs one generation per round and agrees too."""
+    live count, also on dead borders and tori whose rows end in padding."""
     import torch
     say("batched fused life")
     cases = []
@@ -275,7 +279,7 @@ def test_fused_life_rounds_match_oracle(bctx):
                            stable_window=10, check_every=every, max_iter=mi)
         name = (rows, cols, torus, every, mi)
         assert r.status == L.LSR_OK, name
-        assert r.sweeps_per_launch == (8 if cols % 16 == 0 or not torus else 1), name
+        assert r.sweeps_per_launch == 8, name
         assert r.iterations == ro.n and r.last_count == ro.count, (name, r.iterations, ro.n)
         assert np.array_equal(t.cpu().numpy(), o), name
 

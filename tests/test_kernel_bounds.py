@@ -449,8 +449,10 @@ def _c_rem(x, m):
 
 
 def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=None, ragged=False):
-    """ragged: a dead border whose rows (buf's width, a multiple of 16) end in zero
-    padding past cols."""
+    """ragged: rows (buf's width, a multiple of 16) end in padding past cols (zero at
+    the start). On a torus, lanes inside the row load their word, the lane holding the
+    row's end, the lane after it and the first window's left halo lane gather their
+    cells from the wrapped columns, lanes further out load nothing."""
     lead = k if lead is None else lead   # rows streamed before and after the band
     words = buf.view(np.uint32)
     width = buf.shape[1]                  # bytes a row holds
@@ -475,12 +477,19 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
             in_cols = (col_raw >= 0) & (col_raw < cols)
             col = np.where(torus & ~in_cols, _c_rem(col_raw, cols), col_raw)
             loads = in_cols | bool(torus)
+            rt = bool(torus) and ragged
+            inside = (col_raw >= 0) & (col_raw + 16 <= cols)
+            gather = rt & ~inside & (col_raw >= -16) & (col_raw < cols + 16)
+            if rt:
+                loads = inside
+                col = col_raw
             own = (lanes >= 1) & (lanes <= 62) & (col_raw < cols)
             live = np.where(loads, np.uint32(0xFFFFFFFF), np.uint32(0))[:, None]
             inside = cols - col_raw[:, None] - 4 * np.arange(4)[None, :]   # cells of word m
-            cmask = np.where(inside >= 4, live, np.where(
+            full = np.uint32(0xFFFFFFFF) if rt else live
+            cmask = np.where(inside >= 4, full, np.where(
                 inside <= 0, np.uint32(0),
-                live >> (np.uint32(8) * (4 - np.clip(inside, 1, 3)).astype(np.uint32)))).astype(np.uint32)
+                full >> (np.uint32(8) * (4 - np.clip(inside, 1, 3)).astype(np.uint32)))).astype(np.uint32)
             r0, r1 = band * tile_rows, min(band * tile_rows + tile_rows, rows)
 
             def load(r):
@@ -489,6 +498,18 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
                         return zero.copy()
                     r = int(_c_rem(r, rows))
                 W = np.zeros((64, 4), np.uint32)
+                if rt:
+                    for ln in np.nonzero(gather)[0]:
+                        cells = bytearray(16)
+                        for q in range(16):
+                            cc = int(col_raw[ln]) + q
+                            assert -16 <= cc < cols + 32
+                            cc %= cols
+                            if not (0 <= r < rows and 0 <= cc < cols):
+                                bad.append(("gather", t, w, ln, r, cc))
+                                continue
+                            cells[q] = buf[r, cc]
+                        W[ln] = np.frombuffer(bytes(cells), np.uint32)
                 for ln in np.nonzero(loads)[0]:
                     c = int(col[ln])
                     if not (0 <= r < rows and 0 <= c and c + 16 <= width and c % 16 == 0):
@@ -515,12 +536,13 @@ def _life_tb_launch(buf, rows, cols, torus, k, tile_rows, nw, check_mask, lead=N
                         c = mid[lv - 1][:, m]
                         o[:, m] = _zero_bytes_hi(((T - c) | c) ^ np.uint32(0x03030303)) >> np.uint32(7)
                     in_rows = 0 <= row < rows
-                    if ragged:
+                    if ragged and not torus:
                         o &= cmask if in_rows else np.uint32(0)
-                    else:
-                        o &= live if (torus or in_rows) else np.uint32(0)
+                    elif not torus:
+                        o &= live if in_rows else np.uint32(0)
                     if (check_mask >> (lv - 1)) & 1 and r0 <= row < r1:
-                        counts[lv - 1] += int(np.unpackbits(o[own].view(np.uint8)).sum())
+                        oc = (o & cmask) if rt else o
+                        counts[lv - 1] += int(np.unpackbits(oc[own].view(np.uint8)).sum())
                     up[lv - 1] = mid[lv - 1]
                     mid[lv - 1] = cur
                     cur = o
@@ -578,6 +600,30 @@ def test_life_tb_ragged_dead_border_model_matches_oracle(rows, cols, k, tile_row
     assert np.array_equal(out[:, :cols], o)
     for lv in range(1, k + 1):
         _, ro = O.life_run(a, bc=O.BC_BOTTOM, cond=O.COND_NEVER, max_iter=lv)
+        assert counts[lv - 1] == ro.count, lv
+
+
+@pytest.mark.parametrize("rows,cols,k,tile_rows", [
+    (1, 5, 2, 64), (3, 17, 3, 2), (7, 31, 8, 4), (5, 1, 4, 2), (4, 2, 8, 3), (20, 1000, 4, 16),
+    (13, 999, 8, 5), (9, 1009, 5, 3), (6, 2001, 6, 8), (11, 993, 8, 4), (8, 1983, 8, 8)])
+def test_life_tb_ragged_torus_model_matches_oracle(rows, cols, k, tile_rows):
+    """Torus, rows not a multiple of 16 cells (the batched fused family): the edge
+    lanes' gathers read only cells of the grid, every cell is stored once, and the
+    field and the counts of every level equal the oracle's."""
+    import oracle as O
+    from paper_1609_04567_amd import inputs as I
+    a = I.life_input(rows, cols, seed=rows * 13 + cols + k)
+    width = -(-cols // 16) * 16
+    buf = np.zeros((rows, width), np.uint8)
+    buf[:, :cols] = a
+    out, counts, writes, bad = _life_tb_launch(buf, rows, cols, True, k, tile_rows, 4,
+                                               (1 << k) - 1, ragged=True)
+    assert bad == []
+    assert (writes[:, :cols] == 1).all() and (writes[:, cols:] <= 1).all()
+    o, _ = O.life_run(a, bc=O.BC_TORUS, cond=O.COND_NEVER, max_iter=k)
+    assert np.array_equal(out[:, :cols], o)
+    for lv in range(1, k + 1):
+        _, ro = O.life_run(a, bc=O.BC_TORUS, cond=O.COND_NEVER, max_iter=lv)
         assert counts[lv - 1] == ro.count, lv
 
 
