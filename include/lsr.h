@@ -178,11 +178,12 @@ typedef struct {
     int32_t tb_depth;       /* sweeps (generations) fused per launch (temporal blocking); 1 = off.
                                Jacobi: 2, 4, 5, 8 or 10; 0 = the measured best depth that
                                divides both check_every and max_iter, else 5 with checks
-                               inside launches. Life: 2, 3, 4, 6 or 8; 0 = 4. A stop or cap
-                               inside a launch is replayed exactly from the launch's source.
-                               Fusion needs 16-byte aligned grids (pitch and buffers; Life
-                               also rows of a multiple of 16 cells), else the job runs
-                               unfused. Fields and counts are bit for bit those of unfused
+                               inside launches. Life: 2, 3, 4, 5, 6 or 8; 0 = 8. A stop or
+                               cap inside a launch is replayed exactly from the launch's
+                               source. Grids whose rows are not 16-byte aligned (Life: or not
+                               a multiple of 16 cells) run on staged aligned copies (Life rows
+                               padded to 16 cells), fused as well. Fields and counts are bit
+                               for bit those of unfused
                                sweeps; a float reduce value differs at most in the order of
                                its partial sums. Restoration is never fused. A batched context
                                takes the depth (FP64 10, 5 or 2; FP32 5 or 2; Life 8 at any

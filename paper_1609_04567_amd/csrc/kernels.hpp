@@ -77,7 +77,7 @@ hipError_t launch_life(const LifeArgs& a, const SweepGeom& g, JobState* st, void
                        const LoopCtl& c, int j, hipStream_t s);
 // Temporally blocked Life (life_tb.hip): g.tb generations per launch, the count of
 // each checked generation in its own slice of partials (g.mc). Rows must be
-// 16-byte aligned multiples of 16 cells, unpadded (life_tb_ok).
+// 16-byte aligned and hold a multiple of 16 cells, or be padded (life_tb_ok).
 bool life_tb_ok(const LifeArgs& a);
 // True for a compiled fused Life depth (2, 3, 4, 5, 6, 8).
 bool life_tb_depth_ok(int depth);

@@ -6,8 +6,9 @@
 // generation.
 //
 // Requirements (life_tb_ok): 16-byte aligned rows holding a multiple of 16
-// cells, no padding. The cells hold 0 or 1 (the job's initial count pass
-// normalises them).
+// cells, or (staged copies) round_up(cols, 16) bytes with the padding zero at the
+// start, taken by the RAGGED band. The cells hold 0 or 1 (the job's initial
+// count pass normalises them).
 #include <algorithm>
 #include <atomic>
 #include <type_traits>
@@ -24,7 +25,7 @@ namespace {
 // in flight while the current one is computed).
 // check_mask bit l-1: generation n1 + l - 1 is checked; its count over the
 // workgroup's windows goes to partials[(l - 1) * tiles + t].
-template <int NW, int K, int U, bool TORUS>
+template <int NW, int K, int U, bool TORUS, bool RAGGED = false>
 __global__ __launch_bounds__(NW * 64) void life_tb_kernel(
     const uint8_t* __restrict__ a, uint8_t* __restrict__ b, int64_t rows, int64_t cols, int64_t pitch,
     JobState* __restrict__ st, unsigned long long* __restrict__ partials, LoopCtl ctl, int j,
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(NW * 64) void life_tb_kernel(
 
     if (wt < wave_tiles) {
         const int band = wt / strips, strip = wt - band * strips;
-        life_tb_band<K, U, TORUS>(a, b, rows, cols, pitch, mask, band, strip, tile_rows, cnt);
+        life_tb_band<K, U, TORUS, RAGGED>(a, b, rows, cols, pitch, mask, band, strip, tile_rows, cnt);
     }
     if (mask == 0) return;
 #pragma unroll
@@ -116,14 +117,25 @@ template <int K>
 hipError_t launch_k(const LifeArgs& a, const SweepGeom& g, JobState* st, void* partials,
                     const LoopCtl& c, int j, hipStream_t s) {
     auto* p = static_cast<unsigned long long*>(partials);
-    if (a.torus)
-        hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, true>), dim3(g.blocks), dim3(kWaves * 64),
-                           0, s, a.a, a.b, a.rows, a.cols, a.pitch, st, p, c, j, g.strips,
-                           g.strips * g.bands, g.tiles, g.tile_rows);
-    else
-        hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, false>), dim3(g.blocks), dim3(kWaves * 64),
-                           0, s, a.a, a.b, a.rows, a.cols, a.pitch, st, p, c, j, g.strips,
-                           g.strips * g.bands, g.tiles, g.tile_rows);
+    const dim3 grid(g.blocks), block(kWaves * 64);
+    const int wt = g.strips * g.bands;
+    if (a.cols % 16 == 0) {
+        if (a.torus)
+            hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, true>), grid, block, 0, s, a.a, a.b,
+                               a.rows, a.cols, a.pitch, st, p, c, j, g.strips, wt, g.tiles, g.tile_rows);
+        else
+            hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, false>), grid, block, 0, s, a.a, a.b,
+                               a.rows, a.cols, a.pitch, st, p, c, j, g.strips, wt, g.tiles, g.tile_rows);
+    } else {   // padded rows
+        if (a.torus)
+            hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, true, true>), grid, block, 0, s, a.a,
+                               a.b, a.rows, a.cols, a.pitch, st, p, c, j, g.strips, wt, g.tiles,
+                               g.tile_rows);
+        else
+            hipLaunchKernelGGL((life_tb_kernel<kWaves, K, kUnroll, false, true>), grid, block, 0, s, a.a,
+                               a.b, a.rows, a.cols, a.pitch, st, p, c, j, g.strips, wt, g.tiles,
+                               g.tile_rows);
+    }
     return hipGetLastError();
 }
 
@@ -131,7 +143,9 @@ hipError_t launch_k(const LifeArgs& a, const SweepGeom& g, JobState* st, void* p
 
 bool life_tb_ok(const LifeArgs& a) {
     const bool al = ((reinterpret_cast<uintptr_t>(a.a) | reinterpret_cast<uintptr_t>(a.b)) & 15) == 0;
-    return al && a.pitch % 16 == 0 && a.cols % 16 == 0 && !a.padded;
+    // rows of a multiple of 16 cells, or padded rows (staged: round_up(cols, 16)
+    // bytes, the padding zero at the start) for the RAGGED band
+    return al && a.pitch % 16 == 0 && (a.cols % 16 == 0 || a.padded);
 }
 
 bool life_tb_depth_ok(int depth) {

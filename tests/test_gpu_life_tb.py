@@ -93,13 +93,21 @@ def test_bands_chunks_and_graphs(ctx, tile_rows, chunk, graph):
     assert r.iterations == 50 and r.last_count == ro.count and np.array_equal(x, o)
 
 
-def test_unqualified_rows_fall_back_to_single_generations(ctx):
-    """Rows that are not a multiple of 16 cells run one generation per launch."""
-    say("life tb fallback")
-    a = I.life_input(40, 50, seed=9)
-    o, ro = O.life_run(a, cond=O.COND_NEVER, max_iter=12)
-    x, r = _tuned(ctx, lambda: run_life(ctx, a, cond=L.LSR_COND_NEVER, max_iter=12), tb_depth=4)
-    assert r.sweeps_per_launch == 1 and np.array_equal(x, o) and r.last_count == ro.count
+@pytest.mark.parametrize("rows,cols", [(40, 50), (33, 1), (21, 17), (64, 1000), (30, 2001)])
+@pytest.mark.parametrize("torus", [True, False])
+def test_ragged_rows_fuse_on_padded_copies(ctx, rows, cols, torus):
+    """Rows that are not a multiple of 16 cells run fused on the staged copy whose
+    rows are padded to 16 cells (dead border: padding masked at every level; torus:
+    edge lanes gathered from the wrapped columns), equal to the oracle; a stop
+    inside a launch (cap 13 at depth 4) is replayed."""
+    say(f"life tb ragged {rows}x{cols} torus={torus}")
+    a = I.life_input(rows, cols, seed=9 + cols)
+    bc = O.BC_TORUS if torus else O.BC_BOTTOM
+    o, ro = O.life_run(a, bc=bc, cond=O.COND_NEVER, max_iter=13)
+    x, r = _tuned(ctx, lambda: run_life(ctx, a, torus=torus, cond=L.LSR_COND_NEVER, max_iter=13),
+                  tb_depth=4)
+    assert r.sweeps_per_launch == 4 and r.iterations == 13
+    assert np.array_equal(x, o) and r.last_count == ro.count
 
 
 @pytest.mark.parametrize("depth", [2, 8])
